@@ -1,0 +1,229 @@
+/*
+ * emx.h - C ABI of the MI355X (gfx950) elevation-map fusion library (libemx.so).
+ *
+ * This is the data-parallel per-frame path of GPU elevation mapping (Miki et al.,
+ * "Elevation Mapping for Locomotion and Navigation using GPU", arXiv 2204.12876):
+ *   - rigid transform of a point cloud into the robot-centric map frame (Sec. II-A);
+ *   - range-quadratic height noise (Sec. II-C);
+ *   - binning into grid cells;
+ *   - a Mahalanobis outlier gate against each cell's prior (Sec. II-C);
+ *   - inverse-variance (Kalman) fusion of height and variance (Sec. II-C, Eq. 1, 2);
+ *   - visibility ray clearing (Sec. II-E, Eq. 3, 4);
+ *   - 3x3 surface normals (Sec. II-A);
+ *   - a small convolutional traversability filter (Sec. II-G).
+ *
+ * Conventions shared by every call:
+ *   - Pointers named d_* are device (HBM) pointers.  All other pointers are host
+ *     pointers, read synchronously during the call.
+ *   - The caller owns every device buffer: points, map state, scratch and outputs.
+ *     The library never allocates device memory.  Host-side map handles are the
+ *     only thing it allocates.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Device work is enqueued on it and the call returns without synchronising.
+ *     Results are visible after the stream passes the call.  Buffers handed to a
+ *     call must stay alive until then.
+ *   - Arguments are checked on the host before anything is enqueued.  On an
+ *     invalid argument a call returns a negative emx_status, enqueues nothing and
+ *     sets a thread-local message readable with emx_last_error().
+ *   - Kernel faults surface at the caller's next stream synchronisation.
+ *   - A map must not be used from two streams at once.  Distinct maps are
+ *     independent.
+ *   - Floating point: every result is computed in IEEE float32.  Decisions use a
+ *     fixed operation order, round-to-nearest and no fused multiply-add.  Those
+ *     decisions are the range check, cell index, gate, ray samples and clearing
+ *     predicate; the order is stated below.
+ *
+ * Map geometry (the paper is silent on it; these are this library's conventions):
+ *   - Cells are half-open squares of side r.  Global cell (gx, gy) covers
+ *     [gx*r, (gx+1)*r) x [gy*r, (gy+1)*r) of world x, y.
+ *   - The map is centred on cell (cgx, cgy) = (floor(cx/r), floor(cy/r)),
+ *     computed in double precision.
+ *   - Local cell (ix, iy) is global (cgx - nx/2 + ix, cgy - ny/2 + iy), with
+ *     integer division.  Layers are row-major [iy][ix], cell = iy*nx + ix.
+ *   - The local origin O = ((cgx - nx/2)*r, (cgy - ny/2)*r), in double.
+ *   - A pose is a row-major 3x4 sensor->world matrix [R | t] in double.  The
+ *     library rounds R to float32 and forms t32 = float32(t - (O.x, O.y, 0)):
+ *     the translation in map-local metres, subtracted in double.
+ */
+#ifndef EMX_H
+#define EMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t emx_status;
+#define EMX_OK 0
+#define EMX_EINVAL (-1)  /* invalid argument: nothing enqueued                     */
+#define EMX_ENOMEM (-2)  /* a caller buffer is smaller than the size query demands */
+#define EMX_EHIP (-3)    /* the HIP runtime refused a launch or copy               */
+#define EMX_ESTATE (-5)  /* the map handle is not usable (e.g. freed state)        */
+
+typedef struct emx_map emx_map; /* opaque host handle */
+
+/* Map parameters.  Units are metres, milliseconds, square metres. */
+typedef struct {
+  int32_t nx, ny;            /* cells; 3..16384 each                                 */
+  double resolution;         /* r, metres per cell, 1e-6..1e6                        */
+  float init_height;         /* prior height h_init of a fresh or removed cell       */
+  float init_variance;       /* prior variance, "a large number" (Sec. II-C), > 0    */
+  float noise_alpha;         /* alpha_d in sigma_p^2 = alpha_d * d^2 (Sec. II-C), > 0 */
+  float gate_k;              /* Mahalanobis gate k, in sigmas (Sec. II-C), >= 0       */
+  float min_range;           /* points with d < min_range are dropped, > 0           */
+  float ray_step;            /* clearing ray step (Sec. II-E), > 0                   */
+  float clear_normal_alpha;  /* alpha_n of Eq. 4, >= 0                               */
+  int32_t clear_min_age_ms;  /* clearing needs age > this (Sec. II-E), >= 0          */
+} emx_params;
+
+/* One point cloud in the sensor frame, structure of arrays. */
+typedef struct {
+  const float* x;   /* d_x[n], d_y[n], d_z[n]: float32 sensor-frame coordinates  */
+  const float* y;
+  const float* z;
+  int64_t n;        /* points; 0 makes every per-point call a no-op; < 2^31     */
+  double pose[12];  /* row-major 3x4 sensor->world [R | t]; R, t finite         */
+  int64_t t_ms;     /* frame time; t_ms - t0_ms must lie in [0, 2^31)           */
+} emx_frame;
+
+/* Layer identifiers for emx_layer().  Element types in brackets. */
+#define EMX_LAYER_HEIGHT 0     /* [float]   h                                      */
+#define EMX_LAYER_VARIANCE 1   /* [float]   sigma_m^2                              */
+#define EMX_LAYER_TIME 2       /* [int32]   ms since t0 of the last fusion         */
+#define EMX_LAYER_NORMAL_X 3   /* [float]   NaN where undefined                    */
+#define EMX_LAYER_NORMAL_Y 4   /* [float]                                          */
+#define EMX_LAYER_NORMAL_Z 5   /* [float]                                          */
+#define EMX_LAYER_TRAV 6       /* [float]   traversability, NaN where undefined    */
+#define EMX_LAYER_VALID 7      /* [uint8]   1 once a point has been fused          */
+#define EMX_NUM_LAYERS 8
+
+/* Library version string (static storage). */
+const char* emx_version(void);
+
+/* Text of the last non-OK status returned on the calling thread. */
+const char* emx_last_error(void);
+
+/* Host-only check of a parameter block.  Returns EMX_OK or EMX_EINVAL. */
+emx_status emx_params_check(const emx_params* params);
+
+/* Device bytes of one map's state, including the second buffer set that
+ * move_map writes into.  Returns 0 for invalid parameters. */
+size_t emx_state_bytes(const emx_params* params);
+
+/* Device scratch bytes emx_fuse_points needs for frames of up to max_points
+ * points.  Returns 0 for invalid parameters or max_points < 0. */
+size_t emx_scratch_bytes(const emx_params* params, int64_t max_points);
+
+/* Bytes of the packed export format: the layers in identifier order, each
+ * nx*ny elements: h, v, t_upd, normal x, y, z, trav (4 bytes each), valid
+ * (1 byte).  29*nx*ny. */
+size_t emx_export_bytes(const emx_params* params);
+
+/* Create a map centred on world (cx, cy).  Every cell starts at the prior:
+ * h_init, init_variance, t_upd 0, invalid, NaN normals and traversability
+ * (Sec. II-C: the variance is "initialized to a large number").
+ *   d_state:      caller-owned device buffer of state_bytes >= emx_state_bytes(),
+ *                 256-byte aligned; retained by the handle until emx_free_map.
+ *   t0_ms:        the time origin of the int32 time layer.
+ * The prior fill is enqueued on `stream`.  *out receives a new handle. */
+emx_status emx_init_map(const emx_params* params, double cx, double cy, int64_t t0_ms,
+                        void* d_state, size_t state_bytes, void* stream, emx_map** out);
+
+/* Release the host handle.  The caller frees d_state once the stream is idle. */
+emx_status emx_free_map(emx_map* map);
+
+/* Robot-centric re-centring (Sec. I; the map follows the robot).  The map
+ * shifts by whole cells to centre cell (floor(cx/r), floor(cy/r)).
+ *   - Cells that stay in the map keep every layer.
+ *   - Cells that enter take the prior, as in emx_init_map.
+ * A zero shift enqueues nothing.  Layer pointers from emx_layer() change after
+ * a non-zero shift. */
+emx_status emx_move_map(emx_map* map, double cx, double cy, void* stream);
+
+/* Fuse one point cloud into the map (Sec. II-C, Eq. 1 and Eq. 2).
+ *
+ * Per point, in float32 and in this operation order:
+ *   xm = ((R00*xs + R01*ys) + R02*zs) + t32.x   (likewise ym, zm)
+ *   d2 = (xs*xs + ys*ys) + zs*zs;  sp2 = alpha * d2
+ *   The point is valid iff xs, ys, zs, d2 and sp2 are finite and
+ *   d2 >= float32(min_range^2).
+ *   fx = xm*inv_r, fy = ym*inv_r, with inv_r = float32(1/r).  The point is in
+ *   the map iff 0 <= fx < nx and 0 <= fy < ny; then cell = floor(fy)*nx +
+ *   floor(fx).
+ *   Gate: e = zm - h0[cell]; accept iff e*e <= k2*(v0[cell] + sp2), with
+ *   k2 = float32(gate_k^2).  h0 and v0 are the map's values when the call
+ *   starts.
+ * Per cell c with a non-empty accepted set A:
+ *   W = 1/v0 + sum_A 1/sp2;  v = 1/W;  h = (h0/v0 + sum_A zm/sp2) * v
+ *   valid = 1, t_upd = t_ms - t0.
+ *   This equals Eq. 1 and 2 applied point by point, in exact arithmetic.
+ *   The float32 sums are formed in a fixed order of the points.  That order
+ *   depends only on the frame (chunks of 2048 points in index order), so
+ *   results are identical from run to run.
+ * Cells with no accepted point are left bitwise unchanged.
+ *   d_scratch:    >= emx_scratch_bytes(params, frame->n) bytes, 256-aligned.
+ *   d_out_cell:   optional int32[n]: cell, or -1 (dropped or outside).
+ *   d_out_accept: optional uint8[n]: 1 iff the point passed the gate. */
+emx_status emx_fuse_points(emx_map* map, const emx_frame* frame, void* d_scratch,
+                           size_t scratch_bytes, int32_t* d_out_cell,
+                           uint8_t* d_out_accept, void* stream);
+
+/* Visibility clean-up by ray casting (Sec. II-E, Eq. 3 and Eq. 4).
+ *
+ * Every valid point casts a ray from the sensor origin o = t32.  This includes
+ * gated-out points and points whose end lies outside the map.  In float32:
+ *   (dx, dy, dz) = (xm, ym, zm) - o;  m = max(|dx|, |dy|)
+ *   K = ceil(m * inv_step), with inv_step = float32(1/ray_step).
+ *   The ray is skipped unless m*inv_step < 2^24.
+ *   Samples k = 1..K-1: t = float(k)/float(K);
+ *   q = (o.x + t*dx, o.y + t*dy, o.z + t*dz).
+ * A sample in cell c (in the map, not the end point's own cell) marks c iff:
+ *   - valid[c];
+ *   - (t_ms - t0) - t_upd[c] > clear_min_age_ms;
+ *   - hd = h[c] - q.z satisfies hd > 0 and hd*hd > v[c]  (Eq. 3, sigma = sqrt(v));
+ *   - nz[c] is not NaN;
+ *   - ((dx*nx + dy*ny) + dz*nz)^2 > an2 * ((dx*dx + dy*dy) + dz*dz), with
+ *     an2 = float32(alpha_n^2)  (Eq. 4: |r.n| > alpha_n for unit r, n).
+ * Rays test the state as it was when the call started.  Afterwards each
+ * marked cell returns to (init_height, init_variance) and becomes invalid.
+ * Normals and traversability are left for the next per-cell pass.
+ *   d_out_cleared: optional uint8[nx*ny], set to 1 for removed cells, 0 else. */
+emx_status emx_clear_visibility(emx_map* map, const emx_frame* frame,
+                                uint8_t* d_out_cleared, void* stream);
+
+/* Surface normal per cell (Sec. II-A, "normal calculation").
+ *   The normal is the least-squares plane fit on the 3x3 window (Prewitt
+ *   differences):
+ *     gx = ((d(-1) + d(0)) + d(+1)) * float32(1/(6r)),
+ *     with d(dy) = h[iy+dy][ix+1] - h[iy+dy][ix-1]; gy likewise over columns.
+ *   n = (-gx, -gy, 1) / sqrt((gx*gx + gy*gy) + 1).
+ *   It is NaN unless 1 <= ix <= nx-2, 1 <= iy <= ny-2 and all 9 cells are
+ *   valid. */
+emx_status emx_compute_normals(emx_map* map, void* stream);
+
+/* Traversability filter (Sec. II-G).  The paper's trained network is not
+ * given; this is a 3x3 cross-correlation 1->8 with bias, then ReLU, then a 1x1
+ * conv 8->1 with bias, with no output activation.
+ *   d_weights: device float32[89]: w1[8][1][3][3] (PyTorch conv layout),
+ *              b1[8], w2[8], b2[1].
+ *   T = b2 + sum_c w2[c] * max(b1[c] + sum_{dy,dx} w1[c][dy+1][dx+1]*h[iy+dy][ix+dx], 0)
+ *   NaN where the normal is NaN (border or any of the 9 cells invalid). */
+emx_status emx_traversability(emx_map* map, const float* d_weights, void* stream);
+
+/* Device pointer of a layer of the current buffer set. */
+emx_status emx_layer(emx_map* map, int32_t layer, void** d_ptr);
+
+/* Host-side geometry of a map.  Out-pointers may be NULL. */
+emx_status emx_map_info(emx_map* map, int32_t* cgx, int32_t* cgy, int64_t* t0_ms);
+
+/* Copy the layers out to (or in from) a packed device buffer of
+ * emx_export_bytes() bytes, in the format described there. */
+emx_status emx_export_state(emx_map* map, void* d_dst, void* stream);
+emx_status emx_import_state(emx_map* map, const void* d_src, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EMX_H */

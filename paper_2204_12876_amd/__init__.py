@@ -1,0 +1,186 @@
+"""MI355X-native GPU elevation-map fusion (arXiv 2204.12876 hot path).
+
+The library is ``libemx.so``, a C ABI over hand-written HIP kernels for gfx950;
+its calls are declared in include/emx.h.  This package binds it with ctypes:
+  * ``_emx`` mirrors the C calls one-to-one;
+  * ``ElevationMap`` holds one map's device state in torch tensors and forwards
+    each method to the C call of the same name, on torch's current stream.
+Nothing here computes any part of the path.  Without the built library or a
+GPU every call raises.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _emx
+from ._emx import EmxError, make_params  # noqa: F401
+
+__all__ = ["ElevationMap", "EmxError", "make_params", "lib_path", "aligned_empty"]
+
+lib_path = _emx.LIB_PATH
+
+
+def _require_gpu(device):
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2204_12876_amd needs a ROCm GPU; none is visible")
+    _emx.lib()
+    return torch.device(device if device is not None else "cuda")
+
+
+def aligned_empty(nbytes: int, device, align: int = 256) -> torch.Tensor:
+    """A uint8 device tensor of ``nbytes`` whose data pointer is ``align``-aligned."""
+    raw = torch.empty(max(1, nbytes) + align, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % align
+    return raw[off:off + max(1, nbytes)]
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _f32(t: torch.Tensor, device) -> torch.Tensor:
+    if t.dtype != torch.float32 or t.device != device or not t.is_contiguous():
+        raise ValueError("point arrays must be contiguous float32 tensors on the map's device")
+    return t
+
+
+class ElevationMap:
+    """One robot-centric map.  Its state lives in a caller-side torch buffer."""
+
+    def __init__(self, params: dict, cx: float = 0.0, cy: float = 0.0, t0_ms: int = 0,
+                 device=None):
+        self.device = _require_gpu(device)
+        self.params = dict(params)
+        self.p = make_params(params)
+        self.nx, self.ny = self.p.nx, self.p.ny
+        nbytes = _emx.state_bytes(self.p)
+        if nbytes == 0:
+            raise EmxError(_emx.EMX_EINVAL, _emx.last_error())
+        self._state = aligned_empty(nbytes, self.device)
+        self._scratch = None
+        self._scratch_bytes = 0
+        self.handle = _emx.init_map(self.p, float(cx), float(cy), int(t0_ms),
+                                    self._state.data_ptr(), nbytes, _stream(self.device))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _emx.free_map(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------- calls
+    def _frame(self, x, y, z, pose, t_ms):
+        x, y, z = (_f32(t, self.device) for t in (x, y, z))
+        n = x.numel()
+        if y.numel() != n or z.numel() != n:
+            raise ValueError("x, y, z differ in length")
+        return _emx.make_frame(x.data_ptr(), y.data_ptr(), z.data_ptr(), n, pose, t_ms), n
+
+    def scratch(self, n: int) -> torch.Tensor:
+        need = _emx.scratch_bytes(self.p, n)
+        if self._scratch is None or self._scratch_bytes < need:
+            self._scratch = aligned_empty(need, self.device)
+            self._scratch_bytes = need
+        return self._scratch
+
+    def move_map(self, cx: float, cy: float):
+        _emx.move_map(self.handle, float(cx), float(cy), _stream(self.device))
+
+    def fuse_points(self, x, y, z, pose, t_ms: int, out_cell: torch.Tensor = None,
+                    out_accept: torch.Tensor = None, scratch: torch.Tensor = None):
+        f, n = self._frame(x, y, z, pose, t_ms)
+        s = scratch if scratch is not None else self.scratch(n)
+        if out_cell is not None and (out_cell.dtype != torch.int32 or out_cell.numel() < n):
+            raise ValueError("out_cell must be int32 with n elements")
+        if out_accept is not None and (out_accept.dtype != torch.uint8 or out_accept.numel() < n):
+            raise ValueError("out_accept must be uint8 with n elements")
+        _emx.fuse_points(self.handle, f, s.data_ptr(), s.numel(),
+                         out_cell.data_ptr() if out_cell is not None else 0,
+                         out_accept.data_ptr() if out_accept is not None else 0,
+                         _stream(self.device))
+
+    def clear_visibility(self, x, y, z, pose, t_ms: int, out_cleared: torch.Tensor = None):
+        f, _ = self._frame(x, y, z, pose, t_ms)
+        if out_cleared is not None and (out_cleared.dtype != torch.uint8
+                                        or out_cleared.numel() < self.nx * self.ny):
+            raise ValueError("out_cleared must be uint8 with nx*ny elements")
+        _emx.clear_visibility(self.handle, f,
+                              out_cleared.data_ptr() if out_cleared is not None else 0,
+                              _stream(self.device))
+
+    def compute_normals(self):
+        _emx.compute_normals(self.handle, _stream(self.device))
+
+    def traversability(self, weights: torch.Tensor):
+        if weights.dtype != torch.float32 or weights.numel() != 89 or weights.device != self.device:
+            raise ValueError("weights must be 89 float32 values on the map's device")
+        _emx.traversability(self.handle, weights.contiguous().data_ptr(), _stream(self.device))
+
+    # ----------------------------------------------------------------- state
+    def layer(self, layer_id: int) -> torch.Tensor:
+        """A [ny, nx] view of one layer of the current buffer set."""
+        ptr = _emx.layer(self.handle, layer_id)
+        off = ptr - self._state.data_ptr()
+        C = self.nx * self.ny
+        if layer_id == _emx.LAYER_VALID:
+            return self._state[off:off + C].view(self.ny, self.nx)
+        dt = torch.int32 if layer_id == _emx.LAYER_TIME else torch.float32
+        return self._state[off:off + 4 * C].view(dt).view(self.ny, self.nx)
+
+    def info(self):
+        return _emx.map_info(self.handle)
+
+    def export_state(self) -> torch.Tensor:
+        out = aligned_empty(_emx.export_bytes(self.p), self.device)
+        _emx.export_state(self.handle, out.data_ptr(), _stream(self.device))
+        return out
+
+    def import_state(self, packed: torch.Tensor):
+        if packed.numel() < _emx.export_bytes(self.p) or packed.device != self.device:
+            raise ValueError("packed state too small or on the wrong device")
+        packed = packed.contiguous()
+        _emx.import_state(self.handle, packed.data_ptr(), _stream(self.device))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def state_numpy(self) -> dict:
+        """Layers copied to host numpy arrays (synchronises the stream)."""
+        b = self.export_state().cpu().numpy()
+        return unpack_state(b, self.nx, self.ny)
+
+    def load_numpy(self, h, v, t_upd, valid, nrm, trav):
+        """Overwrite the layers from host arrays (stage-synchronised testing)."""
+        self.import_state(torch.from_numpy(pack_state(h, v, t_upd, valid, nrm, trav)).to(
+            self.device))
+
+
+def pack_state(h, v, t_upd, valid, nrm, trav) -> np.ndarray:
+    """Host packing in the export format: h, v, t, nx, ny, nz, trav, valid."""
+    parts = [np.ascontiguousarray(h, np.float32).view(np.uint8).ravel(),
+             np.ascontiguousarray(v, np.float32).view(np.uint8).ravel(),
+             np.ascontiguousarray(t_upd, np.int32).view(np.uint8).ravel(),
+             np.ascontiguousarray(nrm[0], np.float32).view(np.uint8).ravel(),
+             np.ascontiguousarray(nrm[1], np.float32).view(np.uint8).ravel(),
+             np.ascontiguousarray(nrm[2], np.float32).view(np.uint8).ravel(),
+             np.ascontiguousarray(trav, np.float32).view(np.uint8).ravel(),
+             np.ascontiguousarray(valid, np.uint8).ravel()]
+    return np.concatenate(parts)
+
+
+def unpack_state(b: np.ndarray, nx: int, ny: int) -> dict:
+    C = nx * ny
+    out = {}
+    off = 0
+    for name, dt in [("h", np.float32), ("v", np.float32), ("t_upd", np.int32),
+                     ("nx", np.float32), ("ny", np.float32), ("nz", np.float32),
+                     ("trav", np.float32)]:
+        out[name] = b[off:off + 4 * C].view(dt).reshape(ny, nx).copy()
+        off += 4 * C
+    out["valid"] = b[off:off + C].reshape(ny, nx).copy()
+    out["nrm"] = np.stack([out["nx"], out["ny"], out["nz"]])
+    return out

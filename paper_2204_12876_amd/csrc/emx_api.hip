@@ -1,0 +1,363 @@
+// C ABI of libemx.so: argument checks, map handles, state layout and launch
+// sequencing.  Everything device-side is enqueued on the caller's stream; the
+// library never allocates device memory.
+#include <math.h>
+#include <stdarg.h>
+#include <string.h>
+
+#include <cstdio>
+#include <new>
+#include <string>
+
+#include "emx.h"
+#include "emx_kernels.h"
+
+using namespace emx;
+
+namespace {
+
+thread_local std::string g_err;
+
+emx_status fail(emx_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+emx_status fail(emx_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+emx_status hip_fail(hipError_t e, const char* what) {
+  return fail(EMX_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int kMaxSide = 16384;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+emx_status check_params(const emx_params* p) {
+  if (!p) return fail(EMX_EINVAL, "params is NULL");
+  if (p->nx < 3 || p->ny < 3 || p->nx > kMaxSide || p->ny > kMaxSide)
+    return fail(EMX_EINVAL, "nx, ny must lie in [3, %d] (got %d, %d)", kMaxSide, p->nx, p->ny);
+  if (!isfinite(p->resolution) || p->resolution < 1e-6 || p->resolution > 1e6)
+    return fail(EMX_EINVAL, "resolution must lie in [1e-6, 1e6] m");
+  if (!isfinite(p->init_height)) return fail(EMX_EINVAL, "init_height must be finite");
+  if (!finite_pos(p->init_variance)) return fail(EMX_EINVAL, "init_variance must be > 0");
+  if (!finite_pos(p->noise_alpha)) return fail(EMX_EINVAL, "noise_alpha must be > 0");
+  if (!finite_pos(p->min_range)) return fail(EMX_EINVAL, "min_range must be > 0");
+  const float rmin2 = (float)((double)p->min_range * (double)p->min_range);
+  const float sp2min = p->noise_alpha * rmin2;
+  if (!(sp2min >= 1.17549435e-38f) || !isfinite(sp2min))
+    return fail(EMX_EINVAL, "noise_alpha * min_range^2 must be a normal float32");
+  if (!isfinite(p->gate_k) || p->gate_k < 0.0f) return fail(EMX_EINVAL, "gate_k must be >= 0");
+  if (!finite_pos(p->ray_step)) return fail(EMX_EINVAL, "ray_step must be > 0");
+  if (!isfinite((float)(1.0 / (double)p->ray_step)))
+    return fail(EMX_EINVAL, "1/ray_step overflows float32");
+  if (!isfinite(p->clear_normal_alpha) || p->clear_normal_alpha < 0.0f)
+    return fail(EMX_EINVAL, "clear_normal_alpha must be >= 0");
+  if (p->clear_min_age_ms < 0) return fail(EMX_EINVAL, "clear_min_age_ms must be >= 0");
+  return EMX_OK;
+}
+
+Consts make_consts(const emx_params& p) {
+  Consts c;
+  c.inv_r = (float)(1.0 / p.resolution);
+  c.rmin2 = (float)((double)p.min_range * (double)p.min_range);
+  c.k2 = (float)((double)p.gate_k * (double)p.gate_k);
+  c.alpha = p.noise_alpha;
+  c.an2 = (float)((double)p.clear_normal_alpha * (double)p.clear_normal_alpha);
+  c.inv_step = (float)(1.0 / (double)p.ray_step);
+  c.inv6r = (float)(1.0 / (6.0 * p.resolution));
+  c.h_init = p.init_height;
+  c.v_init = p.init_variance;
+  c.nx = p.nx;
+  c.ny = p.ny;
+  c.nxf = (float)p.nx;
+  c.nyf = (float)p.ny;
+  c.tau = p.clear_min_age_ms;
+  return c;
+}
+
+// One buffer set: seven 4-byte layers then two byte layers, each 256-aligned.
+size_t set_layout(const emx_params& p, char* base, Layers* L) {
+  const size_t C = (size_t)p.nx * (size_t)p.ny;
+  const size_t l4 = align256(C * 4);
+  const size_t l1 = align256(C);
+  if (L && base) {
+    L->h = (float*)(base + 0 * l4);
+    L->v = (float*)(base + 1 * l4);
+    L->t = (int32_t*)(base + 2 * l4);
+    L->nx = (float*)(base + 3 * l4);
+    L->ny = (float*)(base + 4 * l4);
+    L->nz = (float*)(base + 5 * l4);
+    L->trav = (float*)(base + 6 * l4);
+    L->valid = (uint8_t*)(base + 7 * l4);
+    L->mark = (uint8_t*)(base + 7 * l4 + l1);
+  }
+  return 7 * l4 + 2 * l1;
+}
+
+}  // namespace
+
+struct emx_map {
+  emx_params p;
+  Consts c;
+  int64_t cgx, cgy;
+  int64_t t0;
+  char* state;
+  size_t set_bytes;
+  int cur;
+  Layers sets[2];
+};
+
+namespace {
+
+emx_status check_map(const emx_map* m) {
+  if (!m) return fail(EMX_EINVAL, "map is NULL");
+  if (!m->state) return fail(EMX_ESTATE, "map has no state");
+  return EMX_OK;
+}
+
+bool center_cell(double c, double r, int64_t* out) {
+  const double q = floor(c / r);
+  if (!isfinite(q) || fabs(q) > 1073741824.0) return false;
+  *out = (int64_t)q;
+  return true;
+}
+
+emx_status make_pose(const emx_map* m, const emx_frame* f, Pose32* P, int32_t* t_now) {
+  for (int k = 0; k < 12; ++k)
+    if (!isfinite(f->pose[k])) return fail(EMX_EINVAL, "pose has a non-finite entry");
+  const double ox = (double)(m->cgx - m->p.nx / 2) * m->p.resolution;
+  const double oy = (double)(m->cgy - m->p.ny / 2) * m->p.resolution;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P->R[i * 3 + j] = (float)f->pose[i * 4 + j];
+  P->t[0] = (float)(f->pose[3] - ox);
+  P->t[1] = (float)(f->pose[7] - oy);
+  P->t[2] = (float)f->pose[11];
+  if (!isfinite(P->t[0]) || !isfinite(P->t[1]) || !isfinite(P->t[2]))
+    return fail(EMX_EINVAL, "map-local translation overflows float32");
+  const int64_t dt = f->t_ms - m->t0;
+  if (dt < 0 || dt > 2147483647LL)
+    return fail(EMX_EINVAL, "t_ms - t0 must lie in [0, 2^31) (got %lld)", (long long)dt);
+  *t_now = (int32_t)dt;
+  return EMX_OK;
+}
+
+emx_status check_frame(const emx_frame* f) {
+  if (!f) return fail(EMX_EINVAL, "frame is NULL");
+  if (f->n < 0 || f->n > 2147483647LL) return fail(EMX_EINVAL, "n must lie in [0, 2^31)");
+  if (f->n > 0 && (!f->x || !f->y || !f->z)) return fail(EMX_EINVAL, "point arrays are NULL");
+  return EMX_OK;
+}
+
+int tiles_of(const emx_params& p) { return tiles_x_of(p.nx) * tiles_y_of(p.ny); }
+
+}  // namespace
+
+extern "C" {
+
+const char* emx_version(void) { return "emx 0.1.0 gfx950"; }
+
+const char* emx_last_error(void) { return g_err.c_str(); }
+
+emx_status emx_params_check(const emx_params* params) { return check_params(params); }
+
+size_t emx_state_bytes(const emx_params* params) {
+  if (check_params(params) != EMX_OK) return 0;
+  return 2 * set_layout(*params, nullptr, nullptr);
+}
+
+size_t emx_scratch_bytes(const emx_params* params, int64_t max_points) {
+  if (check_params(params) != EMX_OK) return 0;
+  if (max_points < 0 || max_points > 2147483647LL) {
+    fail(EMX_EINVAL, "max_points must lie in [0, 2^31)");
+    return 0;
+  }
+  return fuse_scratch_layout(max_points, tiles_of(*params), nullptr, nullptr);
+}
+
+size_t emx_export_bytes(const emx_params* params) {
+  if (check_params(params) != EMX_OK) return 0;
+  return (size_t)29 * (size_t)params->nx * (size_t)params->ny;
+}
+
+emx_status emx_init_map(const emx_params* params, double cx, double cy, int64_t t0_ms,
+                        void* d_state, size_t state_bytes, void* stream, emx_map** out) {
+  emx_status s = check_params(params);
+  if (s != EMX_OK) return s;
+  if (!out) return fail(EMX_EINVAL, "out is NULL");
+  if (!d_state) return fail(EMX_EINVAL, "d_state is NULL");
+  if (((uintptr_t)d_state & 255u) != 0) return fail(EMX_EINVAL, "d_state must be 256-byte aligned");
+  const size_t need = emx_state_bytes(params);
+  if (state_bytes < need)
+    return fail(EMX_ENOMEM, "state buffer has %zu bytes, needs %zu", state_bytes, need);
+  int64_t cgx, cgy;
+  if (!center_cell(cx, params->resolution, &cgx) || !center_cell(cy, params->resolution, &cgy))
+    return fail(EMX_EINVAL, "map centre out of range");
+  emx_map* m = new (std::nothrow) emx_map;
+  if (!m) return fail(EMX_ENOMEM, "host allocation failed");
+  m->p = *params;
+  m->c = make_consts(*params);
+  m->cgx = cgx;
+  m->cgy = cgy;
+  m->t0 = t0_ms;
+  m->state = (char*)d_state;
+  m->set_bytes = set_layout(*params, nullptr, nullptr);
+  set_layout(*params, m->state, &m->sets[0]);
+  set_layout(*params, m->state + m->set_bytes, &m->sets[1]);
+  m->cur = 0;
+  hipError_t e = launch_fill_prior(m->c, m->sets[0], (hipStream_t)stream);
+  if (e != hipSuccess) {
+    delete m;
+    return hip_fail(e, "init_map");
+  }
+  *out = m;
+  return EMX_OK;
+}
+
+emx_status emx_free_map(emx_map* map) {
+  if (!map) return fail(EMX_EINVAL, "map is NULL");
+  delete map;
+  return EMX_OK;
+}
+
+emx_status emx_move_map(emx_map* m, double cx, double cy, void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  int64_t ngx, ngy;
+  if (!center_cell(cx, m->p.resolution, &ngx) || !center_cell(cy, m->p.resolution, &ngy))
+    return fail(EMX_EINVAL, "map centre out of range");
+  int64_t sx = ngx - m->cgx, sy = ngy - m->cgy;
+  if (sx == 0 && sy == 0) return EMX_OK;
+  const int64_t lim = (int64_t)kMaxSide + 1;
+  const int isx = (int)(sx > lim ? lim : (sx < -lim ? -lim : sx));
+  const int isy = (int)(sy > lim ? lim : (sy < -lim ? -lim : sy));
+  const int nxt = 1 - m->cur;
+  hipError_t e = launch_move(m->c, m->sets[m->cur], m->sets[nxt], isx, isy, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "move_map");
+  m->cur = nxt;
+  m->cgx = ngx;
+  m->cgy = ngy;
+  return EMX_OK;
+}
+
+emx_status emx_fuse_points(emx_map* m, const emx_frame* f, void* d_scratch, size_t scratch_bytes,
+                           int32_t* d_out_cell, uint8_t* d_out_accept, void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if ((s = check_frame(f)) != EMX_OK) return s;
+  Pose32 P;
+  int32_t t_now;
+  if ((s = make_pose(m, f, &P, &t_now)) != EMX_OK) return s;
+  if (f->n == 0) return EMX_OK;
+  const int T = tiles_of(m->p);
+  const size_t need = fuse_scratch_layout(f->n, T, nullptr, nullptr);
+  if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
+  if (((uintptr_t)d_scratch & 255u) != 0)
+    return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
+  if (scratch_bytes < need)
+    return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
+  FuseScratch fs;
+  fuse_scratch_layout(f->n, T, (char*)d_scratch, &fs);
+  hipError_t e = launch_fuse(f->x, f->y, f->z, f->n, P, m->c, m->sets[m->cur], t_now, d_out_cell,
+                             d_out_accept, fs, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "fuse_points");
+  return EMX_OK;
+}
+
+emx_status emx_clear_visibility(emx_map* m, const emx_frame* f, uint8_t* d_out_cleared,
+                                void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if ((s = check_frame(f)) != EMX_OK) return s;
+  Pose32 P;
+  int32_t t_now;
+  if ((s = make_pose(m, f, &P, &t_now)) != EMX_OK) return s;
+  hipError_t e = launch_clear(f->x, f->y, f->z, f->n, P, m->c, m->sets[m->cur], t_now,
+                              d_out_cleared, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "clear_visibility");
+  return EMX_OK;
+}
+
+emx_status emx_compute_normals(emx_map* m, void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  hipError_t e = launch_normals(m->c, m->sets[m->cur], (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "compute_normals");
+  return EMX_OK;
+}
+
+emx_status emx_traversability(emx_map* m, const float* d_weights, void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if (!d_weights) return fail(EMX_EINVAL, "d_weights is NULL");
+  hipError_t e = launch_trav(m->c, m->sets[m->cur], d_weights, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "traversability");
+  return EMX_OK;
+}
+
+emx_status emx_layer(emx_map* m, int32_t layer, void** d_ptr) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if (!d_ptr) return fail(EMX_EINVAL, "d_ptr is NULL");
+  const Layers& L = m->sets[m->cur];
+  void* p = nullptr;
+  switch (layer) {
+    case EMX_LAYER_HEIGHT: p = L.h; break;
+    case EMX_LAYER_VARIANCE: p = L.v; break;
+    case EMX_LAYER_TIME: p = L.t; break;
+    case EMX_LAYER_NORMAL_X: p = L.nx; break;
+    case EMX_LAYER_NORMAL_Y: p = L.ny; break;
+    case EMX_LAYER_NORMAL_Z: p = L.nz; break;
+    case EMX_LAYER_TRAV: p = L.trav; break;
+    case EMX_LAYER_VALID: p = L.valid; break;
+    default: return fail(EMX_EINVAL, "unknown layer %d", layer);
+  }
+  *d_ptr = p;
+  return EMX_OK;
+}
+
+emx_status emx_map_info(emx_map* m, int32_t* cgx, int32_t* cgy, int64_t* t0_ms) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if (cgx) *cgx = (int32_t)m->cgx;
+  if (cgy) *cgy = (int32_t)m->cgy;
+  if (t0_ms) *t0_ms = m->t0;
+  return EMX_OK;
+}
+
+static emx_status copy_state(emx_map* m, char* packed, bool out, hipStream_t st) {
+  const Layers& L = m->sets[m->cur];
+  const size_t C = (size_t)m->p.nx * (size_t)m->p.ny;
+  void* lay[8] = {L.h, L.v, L.t, L.nx, L.ny, L.nz, L.trav, L.valid};
+  size_t off = 0;
+  for (int k = 0; k < 8; ++k) {
+    const size_t bytes = (k < 7 ? 4 : 1) * C;
+    hipError_t e = out ? hipMemcpyAsync(packed + off, lay[k], bytes, hipMemcpyDeviceToDevice, st)
+                       : hipMemcpyAsync(lay[k], packed + off, bytes, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, out ? "export_state" : "import_state");
+    off += bytes;
+  }
+  return EMX_OK;
+}
+
+emx_status emx_export_state(emx_map* m, void* d_dst, void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if (!d_dst) return fail(EMX_EINVAL, "d_dst is NULL");
+  return copy_state(m, (char*)d_dst, true, (hipStream_t)stream);
+}
+
+emx_status emx_import_state(emx_map* m, const void* d_src, void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if (!d_src) return fail(EMX_EINVAL, "d_src is NULL");
+  return copy_state(m, (char*)d_src, false, (hipStream_t)stream);
+}
+
+}  // extern "C"

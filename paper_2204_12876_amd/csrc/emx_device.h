@@ -1,0 +1,114 @@
+// Device-side definitions shared by the emx kernels (gfx950, wave64).
+//
+// Every file of this library is compiled with -ffp-contract=off and correctly
+// rounded float32 division/sqrt.  Kernels that take decisions (binning, gate,
+// ray samples, clearing predicate) rely on that to reproduce the operation
+// order the ABI documents exactly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace emx {
+
+// Points per fusion chunk.  This fixes the float32 summation order of the fused
+// sums, so it is a constant of the library, not a tunable.
+constexpr int kChunk = 2048;
+constexpr int kChunkLog = 11;
+// Map tiles of 32x32 cells own the per-cell merge.
+constexpr int kTileLog = 5;
+constexpr int kTile = 1 << kTileLog;
+constexpr int kTileCells = kTile * kTile;
+
+// One buffer set of map layers, row-major [ny][nx].
+struct Layers {
+  float* h;
+  float* v;
+  int32_t* t;
+  float* nx;
+  float* ny;
+  float* nz;
+  float* trav;
+  uint8_t* valid;
+  uint8_t* mark;  // clearing marks; all zero between calls
+};
+
+// Float32 constants derived once on the host from emx_params.
+struct Consts {
+  float inv_r;     // float32(1/r)
+  float rmin2;     // float32(min_range^2)
+  float k2;        // float32(gate_k^2)
+  float alpha;     // noise_alpha
+  float an2;       // float32(clear_normal_alpha^2)
+  float inv_step;  // float32(1/ray_step)
+  float inv6r;     // float32(1/(6 r))
+  float h_init;
+  float v_init;
+  float nxf, nyf;  // nx, ny as float (exact)
+  int nx, ny;
+  int32_t tau;     // clear_min_age_ms
+};
+
+// Sensor -> map-local transform, float32.
+struct Pose32 {
+  float R[9];
+  float t[3];
+};
+
+struct PointEval {
+  float xm, ym, zm, d2, sp2;
+  bool valid;
+};
+
+// Transform, range and noise of one sensor-frame point, in the ABI's order.
+__device__ __forceinline__ PointEval eval_point(const Pose32& P, const Consts& c, float xs,
+                                                float ys, float zs) {
+  PointEval e;
+  e.xm = ((P.R[0] * xs + P.R[1] * ys) + P.R[2] * zs) + P.t[0];
+  e.ym = ((P.R[3] * xs + P.R[4] * ys) + P.R[5] * zs) + P.t[1];
+  e.zm = ((P.R[6] * xs + P.R[7] * ys) + P.R[8] * zs) + P.t[2];
+  e.d2 = (xs * xs + ys * ys) + zs * zs;
+  e.sp2 = c.alpha * e.d2;
+  e.valid = isfinite(xs) && isfinite(ys) && isfinite(zs) && isfinite(e.d2) &&
+            (e.d2 >= c.rmin2) && isfinite(e.sp2);
+  return e;
+}
+
+// Half-open binning of map-local float32 coordinates; false outside.
+__device__ __forceinline__ bool bin_xy(float xm, float ym, const Consts& c, int& ix, int& iy) {
+  const float fx = xm * c.inv_r;
+  const float fy = ym * c.inv_r;
+  if (!(fx >= 0.0f && fx < c.nxf && fy >= 0.0f && fy < c.nyf)) return false;
+  ix = (int)floorf(fx);
+  iy = (int)floorf(fy);
+  return true;
+}
+
+// ---------------------------------------------------------------- block scans
+// Exclusive prefix sum of one int per thread over a block of NT threads.
+// `sm` holds NT/64 ints.  Contains two barriers; every thread must call it.
+template <int NT>
+__device__ __forceinline__ int block_exclusive_sum(int v, int& total, int* sm) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sm[wid] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const int s = sm[w];
+    pre += (w < wid) ? s : 0;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + x - v;
+}
+
+}  // namespace emx

@@ -1,0 +1,468 @@
+// Height fusion (Sec. II-C, Eq. 1 and Eq. 2) as a deterministic two-pass
+// sort-and-reduce, with no float atomics.
+//
+// Pass 1, k_fuse_chunk: one workgroup per chunk of kChunk consecutive points.
+//   - Takes the per-point decisions: transform, range, bin, and the Mahalanobis
+//     gate against the frame-start prior.
+//   - Compacts the accepted points and sorts them in LDS by (tile, cell in tile,
+//     point index).
+//   - A segmented scan reduces each cell's run to one partial: sum 1/sp2 and
+//     sum zm/sp2.
+//   - Writes the partials, grouped by tile, and a dense tile directory row for
+//     the chunk.
+// Pass 2, k_fuse_tile: one workgroup per 32x32-cell map tile.
+//   - Gathers the tile's partials from every chunk that touched it.
+//   - Orders them by (cell, chunk) with LDS occupancy bitmasks and popcount
+//     ranks.
+//   - Adds each cell's partials in chunk order and applies the information-form
+//     update once per touched cell.
+//
+// The float32 sums therefore run in an order fixed by the frame alone.  The
+// order within a chunk is a fixed scan tree over the sorted run, and chunks
+// are added in index order.  So results are bitwise identical from run to run
+// and independent of how pass 2 batches its work.
+#include "emx_kernels.h"
+
+namespace emx {
+
+namespace {
+
+constexpr int kNT1 = 256;                 // pass-1 threads
+constexpr int kPer1 = kChunk / kNT1;      // points per thread
+constexpr uint64_t kNoKey = ~0ull;
+
+struct Seg {
+  float w, wz;
+  int f;  // a segment head lies inside the span
+};
+
+// a precedes b
+__device__ __forceinline__ Seg seg_op(const Seg& a, const Seg& b) {
+  if (b.f) return b;
+  Seg r;
+  r.w = a.w + b.w;
+  r.wz = a.wz + b.wz;
+  r.f = a.f;
+  return r;
+}
+
+// Exclusive segmented scan over the block; `sm` holds NT/64 Seg.
+template <int NT>
+__device__ __forceinline__ Seg block_exclusive_seg(Seg v, Seg* sm) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  Seg x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    Seg y;
+    y.w = __shfl_up(x.w, o, 64);
+    y.wz = __shfl_up(x.wz, o, 64);
+    y.f = __shfl_up(x.f, o, 64);
+    if (lane >= o) x = seg_op(y, x);
+  }
+  if (lane == 63) sm[wid] = x;
+  Seg ex;
+  ex.w = __shfl_up(x.w, 1, 64);
+  ex.wz = __shfl_up(x.wz, 1, 64);
+  ex.f = __shfl_up(x.f, 1, 64);
+  if (lane == 0) {
+    ex.w = 0.0f;
+    ex.wz = 0.0f;
+    ex.f = 0;
+  }
+  __syncthreads();
+  Seg pre;
+  pre.w = 0.0f;
+  pre.wz = 0.0f;
+  pre.f = 0;
+  for (int w = 0; w < wid; ++w) pre = seg_op(pre, sm[w]);
+  __syncthreads();
+  return seg_op(pre, ex);
+}
+
+// In-place ascending bitonic sort of n (power of two) keys in LDS.
+template <int NT>
+__device__ __forceinline__ void bitonic_sort(uint64_t* s, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int q = threadIdx.x; q < (n >> 1); q += NT) {
+        const int lo = 2 * q - (q & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t a = s[lo];
+        const uint64_t b = s[hi];
+        if ((a > b) == up) {
+          s[lo] = b;
+          s[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+struct ChunkArgs {
+  const float* x;
+  const float* y;
+  const float* z;
+  int64_t n;
+  Pose32 P;
+  Consts c;
+  const float* h;
+  const float* v;
+  int32_t* out_cell;
+  uint8_t* out_accept;
+  FuseScratch s;
+  int tiles_x;
+  int T;
+};
+
+__global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
+  __shared__ uint64_t s_key[kChunk];
+  __shared__ float s_w[kChunk];
+  __shared__ float s_wz[kChunk];
+  __shared__ uint32_t s_seg[kChunk];   // (tile << kTileLog*2 | local) of record r
+  __shared__ int s_isum[kNT1 / 64];
+  __shared__ Seg s_seg_sm[kNT1 / 64];
+
+  const int tid = threadIdx.x;
+  const int64_t chunk = blockIdx.x;
+  const int64_t base = chunk * kChunk;
+  uint32_t* drow = a.s.dir + chunk * (int64_t)a.T;
+  for (int t = tid; t < a.T; t += kNT1) drow[t] = 0u;
+
+  // ---- per-point decisions
+  uint64_t key[kPer1];
+  int nmine = 0;
+#pragma unroll
+  for (int j = 0; j < kPer1; ++j) {
+    const int p = j * kNT1 + tid;
+    const int64_t i = base + p;
+    key[j] = kNoKey;
+    if (i < a.n) {
+      const PointEval e = eval_point(a.P, a.c, a.x[i], a.y[i], a.z[i]);
+      int cell = -1;
+      bool acc = false;
+      int ix = 0, iy = 0;
+      if (e.valid && bin_xy(e.xm, e.ym, a.c, ix, iy)) {
+        cell = iy * a.c.nx + ix;
+        const float h0 = a.h[cell];
+        const float v0 = a.v[cell];
+        const float d = e.zm - h0;
+        acc = (d * d) <= (a.c.k2 * (v0 + e.sp2));
+      }
+      if (a.out_cell) a.out_cell[i] = cell;
+      if (a.out_accept) a.out_accept[i] = acc ? 1 : 0;
+      if (acc) {
+        const float w = 1.0f / e.sp2;
+        s_w[p] = w;
+        s_wz[p] = w * e.zm;
+        const uint32_t tile = (uint32_t)((iy >> kTileLog) * a.tiles_x + (ix >> kTileLog));
+        const uint32_t local = (uint32_t)(((iy & (kTile - 1)) << kTileLog) | (ix & (kTile - 1)));
+        key[j] = ((uint64_t)tile << (2 * kTileLog + 12)) | ((uint64_t)local << 12) | (uint64_t)p;
+        ++nmine;
+      }
+    }
+  }
+
+  // ---- compact accepted keys
+  int nacc = 0;
+  int off = block_exclusive_sum<kNT1>(nmine, nacc, s_isum);
+#pragma unroll
+  for (int j = 0; j < kPer1; ++j)
+    if (key[j] != kNoKey) s_key[off++] = key[j];
+  if (nacc == 0) return;  // uniform: the directory row stays zero
+  int sn = 2;
+  while (sn < nacc) sn <<= 1;
+  for (int q = nacc + tid; q < sn; q += kNT1) s_key[q] = kNoKey;
+  __syncthreads();
+
+  // ---- sort by (tile, local, point)
+  bitonic_sort<kNT1>(s_key, sn);
+
+  // ---- segmented reduction of each (tile, local) run
+  const int per = (nacc + kNT1 - 1) / kNT1;
+  const int q0 = min(nacc, tid * per);
+  const int q1 = min(nacc, q0 + per);
+  Seg agg;
+  agg.w = 0.0f;
+  agg.wz = 0.0f;
+  agg.f = 0;
+  int heads = 0;
+  for (int q = q0; q < q1; ++q) {
+    const uint64_t k = s_key[q];
+    const bool head = (q == 0) || ((s_key[q - 1] >> 12) != (k >> 12));
+    const int p = (int)(k & 0xFFF);
+    Seg x;
+    x.w = s_w[p];
+    x.wz = s_wz[p];
+    x.f = head ? 1 : 0;
+    agg = seg_op(agg, x);
+    heads += head ? 1 : 0;
+  }
+  int nrec = 0;
+  const int rbase = block_exclusive_sum<kNT1>(heads, nrec, s_isum);
+  const Seg carry = block_exclusive_seg<kNT1>(agg, s_seg_sm);
+  {
+    float rw = carry.w, rwz = carry.wz;
+    int r = rbase - 1;
+    for (int q = q0; q < q1; ++q) {
+      const uint64_t k = s_key[q];
+      const uint64_t sk = k >> 12;
+      const bool head = (q == 0) || ((s_key[q - 1] >> 12) != sk);
+      const bool tail = (q == nacc - 1) || ((s_key[q + 1] >> 12) != sk);
+      const int p = (int)(k & 0xFFF);
+      if (head) {
+        rw = 0.0f;
+        rwz = 0.0f;
+        ++r;
+      }
+      rw = rw + s_w[p];
+      rwz = rwz + s_wz[p];
+      if (tail) {
+        const int64_t o = base + r;
+        a.s.rec_local[o] = (uint16_t)(sk & (kTileCells - 1));
+        a.s.rec_w[o] = rw;
+        a.s.rec_wz[o] = rwz;
+        s_seg[r] = (uint32_t)sk;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- directory: first record and record count of each touched tile
+  for (int r = tid; r < nrec; r += kNT1) {
+    const uint32_t tile = s_seg[r] >> (2 * kTileLog);
+    if (r > 0 && (s_seg[r - 1] >> (2 * kTileLog)) == tile) continue;
+    int lo = r, hi = nrec;  // first record of a later tile
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((s_seg[mid] >> (2 * kTileLog)) == tile) lo = mid + 1;
+      else hi = mid;
+    }
+    drow[tile] = ((uint32_t)r << 16) | (uint32_t)(lo - r);
+  }
+}
+
+// ------------------------------------------------------------------ pass 2
+constexpr int kNT2 = 256;
+constexpr int kGroup = 64;     // chunks merged per LDS round (one bit each)
+constexpr int kCap = 4096;     // partials held in LDS per round
+constexpr int kWin = kNT2;     // directory entries read per window
+
+struct TileArgs {
+  FuseScratch s;
+  int B;
+  int T;
+  int tiles_x;
+  Consts c;
+  Layers L;
+  int32_t t_now;
+};
+
+__global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
+  __shared__ float acc_w[kTileCells];
+  __shared__ float acc_wz[kTileCells];
+  __shared__ uint64_t mask[kTileCells];
+  __shared__ uint32_t lstart[kTileCells];
+  __shared__ uint8_t hit[kTileCells];
+  __shared__ uint32_t e_chunk[kWin];
+  __shared__ uint32_t e_start[kWin];
+  __shared__ uint32_t e_cnt[kWin];
+  __shared__ uint32_t g_off[kGroup + 1];
+  __shared__ uint32_t u_le[kCap];
+  __shared__ float u_w[kCap];
+  __shared__ float u_wz[kCap];
+  __shared__ float o_w[kCap];
+  __shared__ float o_wz[kCap];
+  __shared__ int s_isum[kNT2 / 64];
+  __shared__ int s_g1, s_tot;
+
+  constexpr int kLoc = kTileCells / kNT2;  // locals per thread
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x;
+  for (int l = tid; l < kTileCells; l += kNT2) {
+    acc_w[l] = 0.0f;
+    acc_wz[l] = 0.0f;
+    hit[l] = 0;
+  }
+
+  for (int k0 = 0; k0 < a.B; k0 += kWin) {
+    const int kk = k0 + tid;
+    const uint32_t d = (kk < a.B) ? a.s.dir[(int64_t)kk * a.T + t] : 0u;
+    int L = 0;
+    const int pos = block_exclusive_sum<kNT2>(d != 0u ? 1 : 0, L, s_isum);
+    if (d != 0u) {
+      e_chunk[pos] = (uint32_t)kk;
+      e_start[pos] = d >> 16;
+      e_cnt[pos] = d & 0xFFFFu;
+    }
+    __syncthreads();
+    int g0 = 0;
+    while (g0 < L) {
+      if (tid == 0) {
+        uint32_t tot = 0;
+        int g = g0;
+        while (g < L && g - g0 < kGroup && tot + e_cnt[g] <= (uint32_t)kCap) {
+          g_off[g - g0] = tot;
+          tot += e_cnt[g];
+          ++g;
+        }
+        g_off[g - g0] = tot;
+        s_g1 = g;
+        s_tot = (int)tot;
+      }
+      for (int l = tid; l < kTileCells; l += kNT2) mask[l] = 0ull;
+      __syncthreads();
+      const int g1 = s_g1;
+      const int tot = s_tot;
+      const int ng = g1 - g0;
+      // gather this round's partials and mark which chunk holds which cell
+      for (int p = tid; p < tot; p += kNT2) {
+        int lo = 0, hi = ng;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (g_off[mid] <= (uint32_t)p) lo = mid;
+          else hi = mid;
+        }
+        const int e = lo;
+        const int64_t idx = (int64_t)e_chunk[g0 + e] * kChunk + e_start[g0 + e] + (p - g_off[e]);
+        const uint32_t local = a.s.rec_local[idx];
+        u_le[p] = (local << 8) | (uint32_t)e;
+        u_w[p] = a.s.rec_w[idx];
+        u_wz[p] = a.s.rec_wz[idx];
+        atomicOr((unsigned long long*)&mask[local], 1ull << e);
+      }
+      __syncthreads();
+      // start of each cell's run in (cell, chunk) order
+      int cnt[kLoc];
+      int mine = 0;
+#pragma unroll
+      for (int j = 0; j < kLoc; ++j) {
+        cnt[j] = __popcll(mask[tid * kLoc + j]);
+        mine += cnt[j];
+      }
+      int all = 0;
+      int run = block_exclusive_sum<kNT2>(mine, all, s_isum);
+#pragma unroll
+      for (int j = 0; j < kLoc; ++j) {
+        lstart[tid * kLoc + j] = (uint32_t)run;
+        run += cnt[j];
+      }
+      __syncthreads();
+      for (int p = tid; p < tot; p += kNT2) {
+        const uint32_t le = u_le[p];
+        const uint32_t local = le >> 8;
+        const uint32_t e = le & 0xFFu;
+        const uint64_t below = (e == 0) ? 0ull : (mask[local] & ((1ull << e) - 1ull));
+        const uint32_t dst = lstart[local] + (uint32_t)__popcll(below);
+        o_w[dst] = u_w[p];
+        o_wz[dst] = u_wz[p];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kLoc; ++j) {
+        const int l = tid * kLoc + j;
+        if (cnt[j] == 0) continue;
+        float aw = acc_w[l], awz = acc_wz[l];
+        const uint32_t s0 = lstart[l];
+        for (int r = 0; r < cnt[j]; ++r) {
+          aw = aw + o_w[s0 + r];
+          awz = awz + o_wz[s0 + r];
+        }
+        acc_w[l] = aw;
+        acc_wz[l] = awz;
+        hit[l] = 1;
+      }
+      __syncthreads();
+      g0 = g1;
+    }
+  }
+  __syncthreads();
+
+  // ---- information-form update of every touched cell
+  const int tx = t % a.tiles_x;
+  const int ty = t / a.tiles_x;
+  for (int l = tid; l < kTileCells; l += kNT2) {
+    if (!hit[l]) continue;
+    const int ix = (tx << kTileLog) + (l & (kTile - 1));
+    const int iy = (ty << kTileLog) + (l >> kTileLog);
+    const int64_t cell = (int64_t)iy * a.c.nx + ix;
+    const float h0 = a.L.h[cell];
+    const float v0 = a.L.v[cell];
+    const float W = (1.0f / v0) + acc_w[l];
+    const float v1 = 1.0f / W;
+    const float h1 = ((h0 / v0) + acc_wz[l]) * v1;
+    a.L.h[cell] = h1;
+    a.L.v[cell] = v1;
+    a.L.t[cell] = a.t_now;
+    a.L.valid[cell] = 1;
+  }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int tiles_x_of(int nx) { return (nx + kTile - 1) >> kTileLog; }
+int tiles_y_of(int ny) { return (ny + kTile - 1) >> kTileLog; }
+
+size_t fuse_scratch_layout(int64_t max_points, int T, char* base, FuseScratch* out) {
+  const int64_t B = (max_points + kChunk - 1) / kChunk;
+  const size_t nrec = (size_t)B * kChunk;
+  size_t off = 0;
+  const size_t o_local = off;
+  off = align256(off + nrec * sizeof(uint16_t));
+  const size_t o_w = off;
+  off = align256(off + nrec * sizeof(float));
+  const size_t o_wz = off;
+  off = align256(off + nrec * sizeof(float));
+  const size_t o_dir = off;
+  off = align256(off + (size_t)B * (size_t)T * sizeof(uint32_t));
+  if (out && base) {
+    out->rec_local = (uint16_t*)(base + o_local);
+    out->rec_w = (float*)(base + o_w);
+    out->rec_wz = (float*)(base + o_wz);
+    out->dir = (uint32_t*)(base + o_dir);
+  }
+  return off;
+}
+
+hipError_t launch_fuse(const float* x, const float* y, const float* z, int64_t n,
+                       const Pose32& P, const Consts& c, const Layers& L, int32_t t_now,
+                       int32_t* out_cell, uint8_t* out_accept, const FuseScratch& s,
+                       hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int tx = tiles_x_of(c.nx);
+  const int T = tx * tiles_y_of(c.ny);
+  const int B = (int)((n + kChunk - 1) / kChunk);
+  ChunkArgs a1;
+  a1.x = x;
+  a1.y = y;
+  a1.z = z;
+  a1.n = n;
+  a1.P = P;
+  a1.c = c;
+  a1.h = L.h;
+  a1.v = L.v;
+  a1.out_cell = out_cell;
+  a1.out_accept = out_accept;
+  a1.s = s;
+  a1.tiles_x = tx;
+  a1.T = T;
+  hipLaunchKernelGGL(k_fuse_chunk, dim3(B), dim3(kNT1), 0, stream, a1);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  TileArgs a2;
+  a2.s = s;
+  a2.B = B;
+  a2.T = T;
+  a2.tiles_x = tx;
+  a2.c = c;
+  a2.L = L;
+  a2.t_now = t_now;
+  hipLaunchKernelGGL(k_fuse_tile, dim3(T), dim3(kNT2), 0, stream, a2);
+  return hipGetLastError();
+}
+
+}  // namespace emx

@@ -1,0 +1,43 @@
+// Host-side launchers of the emx kernels (internal to libemx.so).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "emx_device.h"
+
+namespace emx {
+
+// ------------------------------------------------------------------ fusion
+struct FuseScratch {
+  uint16_t* rec_local;  // [B * kChunk] cell within its tile of each per-chunk partial
+  float* rec_w;         // [B * kChunk] chunk partial of sum 1/sp2
+  float* rec_wz;        // [B * kChunk] chunk partial of sum zm/sp2
+  uint32_t* dir;        // [B * T]  (start << 16 | count) of a tile's partials in a chunk
+};
+
+// Scratch layout for frames of up to max_points; returns total bytes.
+size_t fuse_scratch_layout(int64_t max_points, int T, char* base, FuseScratch* out);
+
+int tiles_x_of(int nx);
+int tiles_y_of(int ny);
+
+hipError_t launch_fuse(const float* x, const float* y, const float* z, int64_t n,
+                       const Pose32& P, const Consts& c, const Layers& L, int32_t t_now,
+                       int32_t* out_cell, uint8_t* out_accept, const FuseScratch& s,
+                       hipStream_t stream);
+
+// ---------------------------------------------------------------- clearing
+hipError_t launch_clear(const float* x, const float* y, const float* z, int64_t n,
+                        const Pose32& P, const Consts& c, const Layers& L, int32_t t_now,
+                        uint8_t* out_cleared, hipStream_t stream);
+
+// --------------------------------------------------------------- per cell
+hipError_t launch_fill_prior(const Consts& c, const Layers& L, hipStream_t stream);
+hipError_t launch_move(const Consts& c, const Layers& src, const Layers& dst, int sx, int sy,
+                       hipStream_t stream);
+hipError_t launch_normals(const Consts& c, const Layers& L, hipStream_t stream);
+hipError_t launch_trav(const Consts& c, const Layers& L, const float* weights,
+                       hipStream_t stream);
+
+}  // namespace emx

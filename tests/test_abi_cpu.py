@@ -1,0 +1,62 @@
+"""The C ABI on the host: the library loads, exports every declared symbol, and
+rejects bad parameters before touching the GPU."""
+import ctypes
+
+import pytest
+
+from paper_2204_12876_amd import _emx
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _emx.lib()
+
+
+def test_every_header_symbol_is_exported(L):
+    names = _emx.header_symbols()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_emx._SIGS), "binding and header disagree"
+
+
+def test_version_and_sizes(L):
+    assert L.emx_version().startswith(b"emx")
+    p = _emx.make_params(dict(nx=400, ny=400, resolution=0.04))
+    assert _emx.params_check(p) == 0
+    C = 400 * 400
+    sb = _emx.state_bytes(p)
+    assert sb >= 2 * 30 * C and sb % 256 == 0
+    assert _emx.export_bytes(p) == 29 * C
+    assert _emx.scratch_bytes(p, 0) == 0
+    s1 = _emx.scratch_bytes(p, 300000)
+    assert s1 >= 300000 * 10
+    assert _emx.scratch_bytes(p, 600000) > s1
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 2), ("ny", 16385), ("resolution", 0.0), ("resolution", float("nan")),
+    ("init_variance", 0.0), ("noise_alpha", -1.0), ("min_range", 0.0), ("gate_k", -1.0),
+    ("ray_step", 0.0), ("clear_normal_alpha", -0.1), ("clear_min_age_ms", -1),
+])
+def test_bad_params_rejected(L, field, value):
+    d = dict(nx=64, ny=64, resolution=0.04)
+    d[field] = value
+    p = _emx.make_params(d)
+    assert _emx.params_check(p) == _emx.EMX_EINVAL
+    assert _emx.state_bytes(p) == 0
+    assert len(_emx.last_error()) > 0
+
+
+def test_init_map_argument_checks_need_no_gpu(L):
+    p = _emx.make_params(dict(nx=64, ny=64, resolution=0.04))
+    h = ctypes.c_void_p()
+    assert L.emx_init_map(ctypes.byref(p), 0.0, 0.0, 0, None, 10**8, None, ctypes.byref(h)) \
+        == _emx.EMX_EINVAL
+    assert "d_state" in _emx.last_error()
+    assert L.emx_init_map(ctypes.byref(p), 0.0, 0.0, 0, ctypes.c_void_p(4096), 16, None,
+                          ctypes.byref(h)) == _emx.EMX_ENOMEM
+    assert L.emx_init_map(ctypes.byref(p), 0.0, 0.0, 0, ctypes.c_void_p(4100), 10**8, None,
+                          ctypes.byref(h)) == _emx.EMX_EINVAL          # misaligned
+    assert L.emx_fuse_points(None, None, None, 0, None, None, None) == _emx.EMX_EINVAL
+    assert L.emx_layer(None, 0, ctypes.byref(h)) == _emx.EMX_EINVAL
