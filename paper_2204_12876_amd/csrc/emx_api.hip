@@ -82,11 +82,14 @@ Consts make_consts(const emx_params& p) {
   return c;
 }
 
-// One buffer set: seven 4-byte layers then two byte layers, each 256-aligned.
+// One buffer set: seven 4-byte layers, two byte layers, then the clearing
+// block maxima; each 256-aligned.
 size_t set_layout(const emx_params& p, char* base, Layers* L) {
   const size_t C = (size_t)p.nx * (size_t)p.ny;
   const size_t l4 = align256(C * 4);
   const size_t l1 = align256(C);
+  const int bl = block_log_of(p.nx, p.ny);
+  const size_t lb = align256((size_t)blocks_of(p.nx, bl) * blocks_of(p.ny, bl) * 4);
   if (L && base) {
     L->h = (float*)(base + 0 * l4);
     L->v = (float*)(base + 1 * l4);
@@ -97,8 +100,9 @@ size_t set_layout(const emx_params& p, char* base, Layers* L) {
     L->trav = (float*)(base + 6 * l4);
     L->valid = (uint8_t*)(base + 7 * l4);
     L->mark = (uint8_t*)(base + 7 * l4 + l1);
+    L->cmax = (float*)(base + 7 * l4 + 2 * l1);
   }
-  return 7 * l4 + 2 * l1;
+  return 7 * l4 + 2 * l1 + lb;
 }
 
 }  // namespace

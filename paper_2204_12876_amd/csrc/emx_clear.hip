@@ -103,9 +103,54 @@ struct MarchArgs {
   Consts c;
   Layers L;
   int32_t t_now;
+  int bl;      // block side 2^bl cells
+  int bx, nb;  // blocks per map row, blocks in the map
 };
 
+// A cell can be removed only if it is valid, older than the minimum age and
+// has a normal.  cmax[b] is the largest height of such a cell in block b
+// (-inf if none).  A sample at height q.z >= cmax[b] passes above every cell
+// of the block that could be removed (removal needs h > q.z), so the march
+// skips it without reading the cell.  This is exact pruning.
+__device__ __forceinline__ bool clearable(const Layers& L, int64_t c, int32_t t_now, int32_t tau) {
+  return L.valid[c] && (((int64_t)t_now - (int64_t)L.t[c]) > (int64_t)tau) && !isnan(L.nz[c]);
+}
+
+struct PrepArgs {
+  Consts c;
+  Layers L;
+  int32_t t_now;
+  int bl, bx, by;
+};
+
+// One wave per block of 2^bl x 2^bl cells.
+__global__ __launch_bounds__(kNTc) void k_clear_prep(PrepArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * (kNTc / 64) + (threadIdx.x >> 6);
+  if (b >= a.bx * a.by) return;  // whole wave leaves together
+  const int side = 1 << a.bl;
+  const int x0 = (b % a.bx) << a.bl;
+  const int y0 = (b / a.bx) << a.bl;
+  float v = -INFINITY;
+  for (int j = lane; j < side * side; j += 64) {
+    const int ix = x0 + (j & (side - 1));
+    const int iy = y0 + (j >> a.bl);
+    if (ix < a.c.nx && iy < a.c.ny) {
+      const int64_t c = (int64_t)iy * a.c.nx + ix;
+      if (clearable(a.L, c, a.t_now, a.c.tau)) v = fmaxf(v, a.L.h[c]);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  if (lane == 0) a.L.cmax[b] = v;
+}
+
+constexpr int kUnroll = 4;
+
 __global__ __launch_bounds__(kNTc) void k_clear_march(MarchArgs a) {
+  extern __shared__ float s_cmax[];
+  for (int j = threadIdx.x; j < a.nb; j += kNTc) s_cmax[j] = a.L.cmax[j];
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kNTc + threadIdx.x;
   if (i >= a.n) return;
   const PointEval e = eval_point(a.P, a.c, a.x[i], a.y[i], a.z[i]);
@@ -134,23 +179,41 @@ __global__ __launch_bounds__(kNTc) void k_clear_march(MarchArgs a) {
   const int k1 = min(hx, hy);
 
   const float an2dd = a.c.an2 * ((r.dx * r.dx + r.dy * r.dy) + r.dz * r.dz);
-  const int32_t t_now = a.t_now;
-  for (int k = k0; k <= k1; ++k) {
-    float qx, qy, qz;
-    sample(r, k, qx, qy, qz);
-    int ix, iy;
-    if (!bin_xy(qx, qy, a.c, ix, iy)) continue;
-    const int cell = iy * a.c.nx + ix;
-    if (cell == end_cell) continue;
-    if (!a.L.valid[cell]) continue;
-    const float hd = a.L.h[cell] - qz;
-    if (!(hd > 0.0f)) continue;
-    if (!((hd * hd) > a.L.v[cell])) continue;
-    if (!(((int64_t)t_now - (int64_t)a.L.t[cell]) > (int64_t)a.c.tau)) continue;
-    const float nz = a.L.nz[cell];
-    if (isnan(nz)) continue;
-    const float dot = (r.dx * a.L.nx[cell] + r.dy * a.L.ny[cell]) + r.dz * nz;
-    if ((dot * dot) > an2dd) a.L.mark[cell] = 1;
+  const int bl = a.bl;
+  for (int k = k0; k <= k1; k += kUnroll) {
+    int cell[kUnroll];
+    float qz[kUnroll];
+    bool hit[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      float qx, qy;
+      sample(r, k + u, qx, qy, qz[u]);
+      int ix, iy;
+      cell[u] = -1;
+      hit[u] = false;
+      if (k + u <= k1 && bin_xy(qx, qy, a.c, ix, iy)) {
+        cell[u] = iy * a.c.nx + ix;
+        hit[u] = qz[u] < s_cmax[(iy >> bl) * a.bx + (ix >> bl)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (!hit[u] || cell[u] == end_cell) continue;
+      const int c = cell[u];
+      // one round trip: every field the test may need
+      const uint8_t vc = a.L.valid[c];
+      const int32_t tc = a.L.t[c];
+      const float hc = a.L.h[c];
+      const float varc = a.L.v[c];
+      const float nxc = a.L.nx[c];
+      const float nyc = a.L.ny[c];
+      const float nzc = a.L.nz[c];
+      const float hd = hc - qz[u];
+      if (!vc || !(((int64_t)a.t_now - (int64_t)tc) > (int64_t)a.c.tau) || isnan(nzc)) continue;
+      if (!(hd > 0.0f) || !((hd * hd) > varc)) continue;
+      const float dot = (r.dx * nxc + r.dy * nyc) + r.dz * nzc;
+      if ((dot * dot) > an2dd) a.L.mark[c] = 1;
+    }
   }
 }
 
@@ -181,6 +244,18 @@ hipError_t launch_clear(const float* x, const float* y, const float* z, int64_t 
                         uint8_t* out_cleared, hipStream_t stream) {
   const int64_t cells = (int64_t)c.nx * c.ny;
   if (n > 0) {
+    PrepArgs pa;
+    pa.c = c;
+    pa.L = L;
+    pa.t_now = t_now;
+    pa.bl = block_log_of(c.nx, c.ny);
+    pa.bx = blocks_of(c.nx, pa.bl);
+    pa.by = blocks_of(c.ny, pa.bl);
+    const int nb = pa.bx * pa.by;
+    hipLaunchKernelGGL(k_clear_prep, dim3((nb + kNTc / 64 - 1) / (kNTc / 64)), dim3(kNTc), 0,
+                       stream, pa);
+    hipError_t err0 = hipGetLastError();
+    if (err0 != hipSuccess) return err0;
     MarchArgs a;
     a.x = x;
     a.y = y;
@@ -190,8 +265,11 @@ hipError_t launch_clear(const float* x, const float* y, const float* z, int64_t 
     a.c = c;
     a.L = L;
     a.t_now = t_now;
-    hipLaunchKernelGGL(k_clear_march, dim3((unsigned)((n + kNTc - 1) / kNTc)), dim3(kNTc), 0,
-                       stream, a);
+    a.bl = pa.bl;
+    a.bx = pa.bx;
+    a.nb = nb;
+    hipLaunchKernelGGL(k_clear_march, dim3((unsigned)((n + kNTc - 1) / kNTc)), dim3(kNTc),
+                       (size_t)nb * sizeof(float), stream, a);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }

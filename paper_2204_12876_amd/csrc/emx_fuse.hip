@@ -4,10 +4,9 @@
 // Pass 1, k_fuse_chunk: one workgroup per chunk of kChunk consecutive points.
 //   - Takes the per-point decisions: transform, range, bin, and the Mahalanobis
 //     gate against the frame-start prior.
-//   - Compacts the accepted points and sorts them in LDS by (tile, cell in tile,
-//     point index).
-//   - A segmented scan reduces each cell's run to one partial: sum 1/sp2 and
-//     sum zm/sp2.
+//   - Sorts the accepted points in LDS by (tile, cell in tile, point index).
+//   - Each cell's run is reduced to one partial, sum 1/sp2 and sum zm/sp2,
+//     added left to right in point order.
 //   - Writes the partials, grouped by tile, and a dense tile directory row for
 //     the chunk.
 // Pass 2, k_fuse_tile: one workgroup per 32x32-cell map tile.
@@ -17,86 +16,61 @@
 //   - Adds each cell's partials in chunk order and applies the information-form
 //     update once per touched cell.
 //
-// The float32 sums therefore run in an order fixed by the frame alone.  The
-// order within a chunk is a fixed scan tree over the sorted run, and chunks
-// are added in index order.  So results are bitwise identical from run to run
-// and independent of how pass 2 batches its work.
+// The float32 sums therefore run in an order fixed by the frame alone: left
+// to right over a cell's points within each chunk, then chunk partials in chunk
+// order.  Results are bitwise identical from run to run, whatever the tile
+// size, grid shape or batching of pass 2.
 #include "emx_kernels.h"
 
 namespace emx {
 
 namespace {
 
-constexpr int kNT1 = 256;                 // pass-1 threads
-constexpr int kPer1 = kChunk / kNT1;      // points per thread
+constexpr int kNT1 = 1024;                // pass-1 threads: two keys each
 constexpr uint64_t kNoKey = ~0ull;
 
-struct Seg {
-  float w, wz;
-  int f;  // a segment head lies inside the span
-};
-
-// a precedes b
-__device__ __forceinline__ Seg seg_op(const Seg& a, const Seg& b) {
-  if (b.f) return b;
-  Seg r;
-  r.w = a.w + b.w;
-  r.wz = a.wz + b.wz;
-  r.f = a.f;
-  return r;
-}
-
-// Exclusive segmented scan over the block; `sm` holds NT/64 Seg.
-template <int NT>
-__device__ __forceinline__ Seg block_exclusive_seg(Seg v, Seg* sm) {
-  const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  Seg x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    Seg y;
-    y.w = __shfl_up(x.w, o, 64);
-    y.wz = __shfl_up(x.wz, o, 64);
-    y.f = __shfl_up(x.f, o, 64);
-    if (lane >= o) x = seg_op(y, x);
-  }
-  if (lane == 63) sm[wid] = x;
-  Seg ex;
-  ex.w = __shfl_up(x.w, 1, 64);
-  ex.wz = __shfl_up(x.wz, 1, 64);
-  ex.f = __shfl_up(x.f, 1, 64);
-  if (lane == 0) {
-    ex.w = 0.0f;
-    ex.wz = 0.0f;
-    ex.f = 0;
-  }
-  __syncthreads();
-  Seg pre;
-  pre.w = 0.0f;
-  pre.wz = 0.0f;
-  pre.f = 0;
-  for (int w = 0; w < wid; ++w) pre = seg_op(pre, sm[w]);
-  __syncthreads();
-  return seg_op(pre, ex);
-}
-
-// In-place ascending bitonic sort of n (power of two) keys in LDS.
-template <int NT>
-__device__ __forceinline__ void bitonic_sort(uint64_t* s, int n) {
-  for (int size = 2; size <= n; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int q = threadIdx.x; q < (n >> 1); q += NT) {
-        const int lo = 2 * q - (q & (stride - 1));
+// Ascending bitonic sort of the block's 2 * kNT1 keys.  Thread t holds the
+// keys of sorted positions 2t and 2t+1 in (a, b).
+//   - Compare-exchanges across waves (stride >= 128) go through LDS.
+//   - Strides 2..64 pair lanes of one wave: they use lane shuffles.
+//   - Stride 1 stays within the thread.
+__device__ __forceinline__ void bitonic_sort_regs(uint64_t& a, uint64_t& b, uint64_t* s) {
+  const int tid = threadIdx.x;
+  const int i0 = 2 * tid;
+  for (int size = 2; size <= 2 * kNT1; size <<= 1) {
+    int stride = size >> 1;
+    if (stride >= 128) {
+      s[i0] = a;
+      s[i0 + 1] = b;
+      __syncthreads();
+      for (; stride >= 128; stride >>= 1) {
+        const int lo = 2 * tid - (tid & (stride - 1));
         const int hi = lo + stride;
         const bool up = (lo & size) == 0;
-        const uint64_t a = s[lo];
-        const uint64_t b = s[hi];
-        if ((a > b) == up) {
-          s[lo] = b;
-          s[hi] = a;
+        const uint64_t x = s[lo];
+        const uint64_t y = s[hi];
+        if ((x > y) == up) {
+          s[lo] = y;
+          s[hi] = x;
         }
+        __syncthreads();
       }
+      a = s[i0];
+      b = s[i0 + 1];
       __syncthreads();
+    }
+    const bool up = (i0 & size) == 0;
+    for (; stride >= 2; stride >>= 1) {
+      const uint64_t pa = __shfl_xor(a, stride >> 1, 64);
+      const uint64_t pb = __shfl_xor(b, stride >> 1, 64);
+      const bool keep_min = (((i0 & stride) == 0) == up);
+      a = keep_min ? (a < pa ? a : pa) : (a < pa ? pa : a);
+      b = keep_min ? (b < pb ? b : pb) : (b < pb ? pb : b);
+    }
+    if ((a > b) == up) {
+      const uint64_t t = a;
+      a = b;
+      b = t;
     }
   }
 }
@@ -121,9 +95,8 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
   __shared__ uint64_t s_key[kChunk];
   __shared__ float s_w[kChunk];
   __shared__ float s_wz[kChunk];
-  __shared__ uint32_t s_seg[kChunk];   // (tile << kTileLog*2 | local) of record r
+  __shared__ uint32_t s_seg[kChunk];   // (tile << 2*kTileLog | local) of record r
   __shared__ int s_isum[kNT1 / 64];
-  __shared__ Seg s_seg_sm[kNT1 / 64];
 
   const int tid = threadIdx.x;
   const int64_t chunk = blockIdx.x;
@@ -131,11 +104,11 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
   uint32_t* drow = a.s.dir + chunk * (int64_t)a.T;
   for (int t = tid; t < a.T; t += kNT1) drow[t] = 0u;
 
-  // ---- per-point decisions
-  uint64_t key[kPer1];
+  // ---- per-point decisions; thread t takes points t and t + kNT1
+  uint64_t key[2];
   int nmine = 0;
 #pragma unroll
-  for (int j = 0; j < kPer1; ++j) {
+  for (int j = 0; j < 2; ++j) {
     const int p = j * kNT1 + tid;
     const int64_t i = base + p;
     key[j] = kNoKey;
@@ -164,69 +137,48 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
       }
     }
   }
-
-  // ---- compact accepted keys
   int nacc = 0;
-  int off = block_exclusive_sum<kNT1>(nmine, nacc, s_isum);
-#pragma unroll
-  for (int j = 0; j < kPer1; ++j)
-    if (key[j] != kNoKey) s_key[off++] = key[j];
+  (void)block_exclusive_sum<kNT1>(nmine, nacc, s_isum);
   if (nacc == 0) return;  // uniform: the directory row stays zero
-  int sn = 2;
-  while (sn < nacc) sn <<= 1;
-  for (int q = nacc + tid; q < sn; q += kNT1) s_key[q] = kNoKey;
+
+  // ---- sort by (tile, local, point); invalid keys sort last
+  bitonic_sort_regs(key[0], key[1], s_key);
+  s_key[2 * tid] = key[0];
+  s_key[2 * tid + 1] = key[1];
   __syncthreads();
 
-  // ---- sort by (tile, local, point)
-  bitonic_sort<kNT1>(s_key, sn);
-
-  // ---- segmented reduction of each (tile, local) run
-  const int per = (nacc + kNT1 - 1) / kNT1;
-  const int q0 = min(nacc, tid * per);
-  const int q1 = min(nacc, q0 + per);
-  Seg agg;
-  agg.w = 0.0f;
-  agg.wz = 0.0f;
-  agg.f = 0;
+  // ---- one partial per (tile, local) run, summed left to right in point order
+  // by the thread that holds the run's first key.  The sum depends only on the
+  // run, never on where it landed in the sorted array.
   int heads = 0;
-  for (int q = q0; q < q1; ++q) {
-    const uint64_t k = s_key[q];
-    const bool head = (q == 0) || ((s_key[q - 1] >> 12) != (k >> 12));
-    const int p = (int)(k & 0xFFF);
-    Seg x;
-    x.w = s_w[p];
-    x.wz = s_wz[p];
-    x.f = head ? 1 : 0;
-    agg = seg_op(agg, x);
-    heads += head ? 1 : 0;
+  bool hd[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int q = 2 * tid + j;
+    hd[j] = q < nacc && (q == 0 || (s_key[q - 1] >> 12) != (s_key[q] >> 12));
+    heads += hd[j] ? 1 : 0;
   }
   int nrec = 0;
-  const int rbase = block_exclusive_sum<kNT1>(heads, nrec, s_isum);
-  const Seg carry = block_exclusive_seg<kNT1>(agg, s_seg_sm);
-  {
-    float rw = carry.w, rwz = carry.wz;
-    int r = rbase - 1;
-    for (int q = q0; q < q1; ++q) {
-      const uint64_t k = s_key[q];
-      const uint64_t sk = k >> 12;
-      const bool head = (q == 0) || ((s_key[q - 1] >> 12) != sk);
-      const bool tail = (q == nacc - 1) || ((s_key[q + 1] >> 12) != sk);
-      const int p = (int)(k & 0xFFF);
-      if (head) {
-        rw = 0.0f;
-        rwz = 0.0f;
-        ++r;
-      }
-      rw = rw + s_w[p];
-      rwz = rwz + s_wz[p];
-      if (tail) {
-        const int64_t o = base + r;
-        a.s.rec_local[o] = (uint16_t)(sk & (kTileCells - 1));
-        a.s.rec_w[o] = rw;
-        a.s.rec_wz[o] = rwz;
-        s_seg[r] = (uint32_t)sk;
-      }
+  int r = block_exclusive_sum<kNT1>(heads, nrec, s_isum);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (!hd[j]) continue;
+    const int q = 2 * tid + j;
+    const uint64_t sk = s_key[q] >> 12;
+    const int p0 = (int)(s_key[q] & 0xFFF);
+    float rw = s_w[p0];
+    float rwz = s_wz[p0];
+    for (int qq = q + 1; qq < nacc && (s_key[qq] >> 12) == sk; ++qq) {
+      const int pp = (int)(s_key[qq] & 0xFFF);
+      rw = rw + s_w[pp];
+      rwz = rwz + s_wz[pp];
     }
+    const int64_t o = base + r;
+    a.s.rec_local[o] = (uint16_t)(sk & (kTileCells - 1));
+    a.s.rec_w[o] = rw;
+    a.s.rec_wz[o] = rwz;
+    s_seg[r] = (uint32_t)sk;
+    ++r;
   }
   __syncthreads();
 
@@ -269,14 +221,14 @@ __global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
   __shared__ uint32_t e_chunk[kWin];
   __shared__ uint32_t e_start[kWin];
   __shared__ uint32_t e_cnt[kWin];
-  __shared__ uint32_t g_off[kGroup + 1];
+  __shared__ uint32_t e_pre[kWin + 1];
   __shared__ uint32_t u_le[kCap];
   __shared__ float u_w[kCap];
   __shared__ float u_wz[kCap];
   __shared__ float o_w[kCap];
   __shared__ float o_wz[kCap];
   __shared__ int s_isum[kNT2 / 64];
-  __shared__ int s_g1, s_tot;
+  __shared__ int s_g1;
 
   constexpr int kLoc = kTileCells / kNT2;  // locals per thread
   const int tid = threadIdx.x;
@@ -288,6 +240,7 @@ __global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
   }
 
   for (int k0 = 0; k0 < a.B; k0 += kWin) {
+    // compact the chunks of this window that touched the tile, in chunk order
     const int kk = k0 + tid;
     const uint32_t d = (kk < a.B) ? a.s.dir[(int64_t)kk * a.T + t] : 0u;
     int L = 0;
@@ -298,35 +251,40 @@ __global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
       e_cnt[pos] = d & 0xFFFFu;
     }
     __syncthreads();
+    if (L == 0) continue;
+    int totw = 0;
+    const int pre = block_exclusive_sum<kNT2>(tid < L ? (int)e_cnt[tid] : 0, totw, s_isum);
+    if (tid < L) e_pre[tid] = (uint32_t)pre;
+    if (tid == 0) e_pre[L] = (uint32_t)totw;
+    __syncthreads();
     int g0 = 0;
     while (g0 < L) {
+      // largest group [g0, g1): at most kGroup chunks and kCap partials
       if (tid == 0) {
-        uint32_t tot = 0;
-        int g = g0;
-        while (g < L && g - g0 < kGroup && tot + e_cnt[g] <= (uint32_t)kCap) {
-          g_off[g - g0] = tot;
-          tot += e_cnt[g];
-          ++g;
+        int lo = g0 + 1, hi = min(L, g0 + kGroup);
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (e_pre[mid] - e_pre[g0] <= (uint32_t)kCap) lo = mid;
+          else hi = mid - 1;
         }
-        g_off[g - g0] = tot;
-        s_g1 = g;
-        s_tot = (int)tot;
+        s_g1 = lo;
       }
       for (int l = tid; l < kTileCells; l += kNT2) mask[l] = 0ull;
       __syncthreads();
       const int g1 = s_g1;
-      const int tot = s_tot;
-      const int ng = g1 - g0;
+      const uint32_t pbase = e_pre[g0];
+      const int tot = (int)(e_pre[g1] - pbase);
       // gather this round's partials and mark which chunk holds which cell
       for (int p = tid; p < tot; p += kNT2) {
-        int lo = 0, hi = ng;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (g_off[mid] <= (uint32_t)p) lo = mid;
-          else hi = mid;
+        const uint32_t gp = pbase + (uint32_t)p;
+        int lo = g0, hi = g1 - 1;  // last entry whose prefix is <= gp
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (e_pre[mid] <= gp) lo = mid;
+          else hi = mid - 1;
         }
-        const int e = lo;
-        const int64_t idx = (int64_t)e_chunk[g0 + e] * kChunk + e_start[g0 + e] + (p - g_off[e]);
+        const int e = lo - g0;
+        const int64_t idx = (int64_t)e_chunk[lo] * kChunk + e_start[lo] + (gp - e_pre[lo]);
         const uint32_t local = a.s.rec_local[idx];
         u_le[p] = (local << 8) | (uint32_t)e;
         u_w[p] = a.s.rec_w[idx];
