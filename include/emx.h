@@ -112,8 +112,9 @@ emx_status emx_params_check(const emx_params* params);
  * move_map writes into.  Returns 0 for invalid parameters. */
 size_t emx_state_bytes(const emx_params* params);
 
-/* Device scratch bytes emx_fuse_points needs for frames of up to max_points
- * points.  Returns 0 for invalid parameters or max_points < 0. */
+/* Device scratch bytes emx_fuse_points and emx_clear_visibility need for
+ * frames of up to max_points points (one buffer serves both calls, which use
+ * it in turn).  Returns 0 for invalid parameters or max_points < 0. */
 size_t emx_scratch_bytes(const emx_params* params, int64_t max_points);
 
 /* Bytes of the packed export format: the layers in identifier order, each
@@ -189,9 +190,11 @@ emx_status emx_fuse_points(emx_map* map, const emx_frame* frame, void* d_scratch
  * Rays test the state as it was when the call started.  Afterwards each
  * marked cell returns to (init_height, init_variance) and becomes invalid.
  * Normals and traversability are left for the next per-cell pass.
+ *   d_scratch:     >= emx_scratch_bytes(params, frame->n) bytes, 256-aligned;
+ *                  may be NULL when n = 0.
  *   d_out_cleared: optional uint8[nx*ny], set to 1 for removed cells, 0 else. */
-emx_status emx_clear_visibility(emx_map* map, const emx_frame* frame,
-                                uint8_t* d_out_cleared, void* stream);
+emx_status emx_clear_visibility(emx_map* map, const emx_frame* frame, void* d_scratch,
+                                size_t scratch_bytes, uint8_t* d_out_cleared, void* stream);
 
 /* Surface normal per cell (Sec. II-A, "normal calculation").
  *   The normal is the least-squares plane fit on the 3x3 window (Prewitt

@@ -105,12 +105,14 @@ class ElevationMap:
                          out_accept.data_ptr() if out_accept is not None else 0,
                          _stream(self.device))
 
-    def clear_visibility(self, x, y, z, pose, t_ms: int, out_cleared: torch.Tensor = None):
-        f, _ = self._frame(x, y, z, pose, t_ms)
+    def clear_visibility(self, x, y, z, pose, t_ms: int, out_cleared: torch.Tensor = None,
+                         scratch: torch.Tensor = None):
+        f, n = self._frame(x, y, z, pose, t_ms)
+        s = scratch if scratch is not None else self.scratch(n)
         if out_cleared is not None and (out_cleared.dtype != torch.uint8
                                         or out_cleared.numel() < self.nx * self.ny):
             raise ValueError("out_cleared must be uint8 with nx*ny elements")
-        _emx.clear_visibility(self.handle, f,
+        _emx.clear_visibility(self.handle, f, s.data_ptr(), s.numel(),
                               out_cleared.data_ptr() if out_cleared is not None else 0,
                               _stream(self.device))
 

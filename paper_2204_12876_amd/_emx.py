@@ -59,7 +59,8 @@ _SIGS = {
     "emx_move_map": (c_int32, [c_void_p, c_double, c_double, c_void_p]),
     "emx_fuse_points": (c_int32, [c_void_p, POINTER(Frame), c_void_p, c_size_t, c_void_p,
                                   c_void_p, c_void_p]),
-    "emx_clear_visibility": (c_int32, [c_void_p, POINTER(Frame), c_void_p, c_void_p]),
+    "emx_clear_visibility": (c_int32, [c_void_p, POINTER(Frame), c_void_p, c_size_t, c_void_p,
+                                       c_void_p]),
     "emx_compute_normals": (c_int32, [c_void_p, c_void_p]),
     "emx_traversability": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "emx_layer": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
@@ -170,9 +171,10 @@ def fuse_points(h: int, f: Frame, d_scratch: int, nbytes: int, d_out_cell: int,
                                 c_void_p(stream)))
 
 
-def clear_visibility(h: int, f: Frame, d_out_cleared: int, stream: int):
-    check(lib().emx_clear_visibility(c_void_p(h), byref(f), c_void_p(d_out_cleared or None),
-                                     c_void_p(stream)))
+def clear_visibility(h: int, f: Frame, d_scratch: int, nbytes: int, d_out_cleared: int,
+                     stream: int):
+    check(lib().emx_clear_visibility(c_void_p(h), byref(f), c_void_p(d_scratch or None), nbytes,
+                                     c_void_p(d_out_cleared or None), c_void_p(stream)))
 
 
 def compute_normals(h: int, stream: int):

@@ -107,6 +107,9 @@ size_t set_layout(const emx_params& p, char* base, Layers* L) {
 
 }  // namespace
 
+// Per-map control words after the two buffer sets: [0] clearing queue counter.
+constexpr int kCtlWords = 64;
+
 struct emx_map {
   emx_params p;
   Consts c;
@@ -116,6 +119,8 @@ struct emx_map {
   size_t set_bytes;
   int cur;
   Layers sets[2];
+  uint32_t* ctl;
+  int march_grid;
 };
 
 namespace {
@@ -161,6 +166,16 @@ emx_status check_frame(const emx_frame* f) {
 
 int tiles_of(const emx_params& p) { return tiles_x_of(p.nx) * tiles_y_of(p.ny); }
 
+// Persistent grids: a few workgroups per compute unit of the current device.
+int march_grid_for_device() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return 4 * cus;
+}
+
 }  // namespace
 
 extern "C" {
@@ -173,7 +188,7 @@ emx_status emx_params_check(const emx_params* params) { return check_params(para
 
 size_t emx_state_bytes(const emx_params* params) {
   if (check_params(params) != EMX_OK) return 0;
-  return 2 * set_layout(*params, nullptr, nullptr);
+  return 2 * set_layout(*params, nullptr, nullptr) + kCtlWords * sizeof(uint32_t);
 }
 
 size_t emx_scratch_bytes(const emx_params* params, int64_t max_points) {
@@ -182,7 +197,9 @@ size_t emx_scratch_bytes(const emx_params* params, int64_t max_points) {
     fail(EMX_EINVAL, "max_points must lie in [0, 2^31)");
     return 0;
   }
-  return fuse_scratch_layout(max_points, tiles_of(*params), nullptr, nullptr);
+  const size_t f = fuse_scratch_layout(max_points, tiles_of(*params), nullptr, nullptr);
+  const size_t c = clear_scratch_layout(max_points, nullptr, nullptr);
+  return f > c ? f : c;
 }
 
 size_t emx_export_bytes(const emx_params* params) {
@@ -215,7 +232,9 @@ emx_status emx_init_map(const emx_params* params, double cx, double cy, int64_t 
   set_layout(*params, m->state, &m->sets[0]);
   set_layout(*params, m->state + m->set_bytes, &m->sets[1]);
   m->cur = 0;
-  hipError_t e = launch_fill_prior(m->c, m->sets[0], (hipStream_t)stream);
+  m->ctl = (uint32_t*)(m->state + 2 * m->set_bytes);
+  m->march_grid = march_grid_for_device();
+  hipError_t e = launch_fill_prior(m->c, m->sets[0], m->ctl, kCtlWords, (hipStream_t)stream);
   if (e != hipSuccess) {
     delete m;
     return hip_fail(e, "init_map");
@@ -274,16 +293,26 @@ emx_status emx_fuse_points(emx_map* m, const emx_frame* f, void* d_scratch, size
   return EMX_OK;
 }
 
-emx_status emx_clear_visibility(emx_map* m, const emx_frame* f, uint8_t* d_out_cleared,
-                                void* stream) {
+emx_status emx_clear_visibility(emx_map* m, const emx_frame* f, void* d_scratch,
+                                size_t scratch_bytes, uint8_t* d_out_cleared, void* stream) {
   emx_status s = check_map(m);
   if (s != EMX_OK) return s;
   if ((s = check_frame(f)) != EMX_OK) return s;
   Pose32 P;
   int32_t t_now;
   if ((s = make_pose(m, f, &P, &t_now)) != EMX_OK) return s;
-  hipError_t e = launch_clear(f->x, f->y, f->z, f->n, P, m->c, m->sets[m->cur], t_now,
-                              d_out_cleared, (hipStream_t)stream);
+  ClearScratch cs = {nullptr, nullptr, nullptr};
+  if (f->n > 0) {
+    const size_t need = clear_scratch_layout(f->n, nullptr, nullptr);
+    if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
+    if (((uintptr_t)d_scratch & 255u) != 0)
+      return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
+    if (scratch_bytes < need)
+      return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
+    clear_scratch_layout(f->n, (char*)d_scratch, &cs);
+  }
+  hipError_t e = launch_clear(f->x, f->y, f->z, f->n, P, m->c, m->sets[m->cur], t_now, cs,
+                              m->ctl, d_out_cleared, m->march_grid, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "clear_visibility");
   return EMX_OK;
 }

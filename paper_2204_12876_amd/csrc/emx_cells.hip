@@ -16,10 +16,13 @@ struct FillArgs {
   Consts c;
   Layers L;
   int64_t cells;
+  uint32_t* ctl;
+  int nctl;
 };
 
 __global__ __launch_bounds__(kNTf) void k_fill_prior(FillArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kNTf + threadIdx.x;
+  if (i < a.nctl) a.ctl[i] = 0u;
   if (i >= a.cells) return;
   const float qnan = __builtin_nanf("");
   a.L.h[i] = a.c.h_init;
@@ -202,11 +205,14 @@ __global__ __launch_bounds__(kNTf) void k_trav(StencilArgs a) {
 
 }  // namespace
 
-hipError_t launch_fill_prior(const Consts& c, const Layers& L, hipStream_t stream) {
+hipError_t launch_fill_prior(const Consts& c, const Layers& L, uint32_t* ctl, int nctl,
+                             hipStream_t stream) {
   FillArgs a;
   a.c = c;
   a.L = L;
   a.cells = (int64_t)c.nx * c.ny;
+  a.ctl = ctl;
+  a.nctl = ctl ? nctl : 0;
   hipLaunchKernelGGL(k_fill_prior, dim3((unsigned)((a.cells + kNTf - 1) / kNTf)), dim3(kNTf), 0,
                      stream, a);
   return hipGetLastError();

@@ -1,18 +1,33 @@
 // Visibility clean-up by ray casting (Sec. II-E, Eq. 3 and Eq. 4).
 //
-// k_clear_march: one thread per point.  The thread walks the samples of the
-// sensor->point ray and marks every cell that the ray passes below.
-//   - The samples are q_k = o + (k/K) d for k = 1..K-1, in float32.
-//   - A sample's cell is in the map over a contiguous range of k, because
-//     q_k.x and q_k.y are monotone in k: each is a correctly rounded chain of
-//     monotone operations.  So the thread first finds that range exactly,
-//     using the very sample evaluation it then loops over.  Rays reaching far
-//     beyond the map cost only their in-map samples.
-//   - Marks are idempotent byte stores: no atomics, no ordering.
+// The samples of a ray are q_k = o + (k/K) d for k = 1..K-1, in float32.
+// Their number varies from 0 to a few hundred per ray, so one thread per ray
+// leaves the long rays on the critical path.  The work is therefore split in
+// three launches:
+//
+// k_clear_setup, two roles in one grid:
+//   - Block role: per block of 2^b x 2^b cells, the largest height of a cell
+//     that a ray could still remove: valid, older than the minimum age, with a
+//     normal.  It is -inf if there is none.
+//   - Ray role, one thread per point:
+//       - the ray's exact in-map range of k.  A sample's cell is in the map over
+//         a contiguous range of k, because q_k.x and q_k.y are monotone in k:
+//         each is a correctly rounded chain of monotone operations.  The range
+//         is found by binary search with the very sample evaluation the march
+//         uses.
+//       - the range is cut into segments of kSeg samples, queued with one
+//         integer atomic per wave.  A ray that would overflow the bounded
+//         queue is marched in place instead.
+// k_clear_march: a persistent grid drains the queue, one segment per thread.
+//   - A sample at height q.z >= the block maximum passes above every cell that
+//     could be removed, since removal needs h > q.z.  It is skipped without
+//     reading the cell: exact pruning.
+//   - Marks are idempotent byte stores, so the queue order never shows in the
+//     result.
 //   - The state is only read, so every ray sees the state as it was when the
 //     call started.
-// k_clear_apply: one pass over the cells.  It resets marked cells to the prior,
-// reports the marks and clears them for the next call.
+// k_clear_apply: resets marked cells to the prior, reports and clears the
+// marks, and rewinds the queue counter for the next call.
 #include "emx_kernels.h"
 
 namespace emx {
@@ -20,6 +35,8 @@ namespace emx {
 namespace {
 
 constexpr int kNTc = 256;
+constexpr int kSeg = 32;          // samples per queued segment
+constexpr int kQueuePerRay = 4;   // queue capacity, in segments per point
 
 struct Ray {
   float ox, oy, oz;
@@ -27,21 +44,13 @@ struct Ray {
   float Kf;
 };
 
-__device__ __forceinline__ void sample(const Ray& r, int k, float& qx, float& qy, float& qz) {
-  const float t = (float)k / r.Kf;
-  qx = r.ox + t * r.dx;
-  qy = r.oy + t * r.dy;
-  qz = r.oz + t * r.dz;
-}
+__device__ __forceinline__ float t_of(const Ray& r, int k) { return (float)k / r.Kf; }
 
-// f(k) = q_k.x * inv_r, exactly as binning computes it
-__device__ __forceinline__ float fx_of(const Ray& r, int k, float inv_r) {
-  const float t = (float)k / r.Kf;
-  return (r.ox + t * r.dx) * inv_r;
-}
-__device__ __forceinline__ float fy_of(const Ray& r, int k, float inv_r) {
-  const float t = (float)k / r.Kf;
-  return (r.oy + t * r.dy) * inv_r;
+// f(k) = q_k.x * inv_r (or .y), exactly as binning computes it
+template <bool kIsX>
+__device__ __forceinline__ float f_of(const Ray& r, int k, float inv_r) {
+  const float t = t_of(r, k);
+  return kIsX ? (r.ox + t * r.dx) * inv_r : (r.oy + t * r.dy) * inv_r;
 }
 
 // Range [lo, hi] of k in [1, K-1] where 0 <= f(k) < lim, for f monotone in k
@@ -49,52 +58,42 @@ __device__ __forceinline__ float fy_of(const Ray& r, int k, float inv_r) {
 template <bool kIsX>
 __device__ __forceinline__ void axis_range(const Ray& r, int K, float inv_r, float lim, bool inc,
                                            int& lo, int& hi) {
-  auto f = [&](int k) { return kIsX ? fx_of(r, k, inv_r) : fy_of(r, k, inv_r); };
   auto in = [&](int k) {
-    const float v = f(k);
+    const float v = f_of<kIsX>(r, k, inv_r);
     return v >= 0.0f && v < lim;
   };
   lo = 1;
   hi = K - 1;
   if (in(lo) && in(hi)) return;
-  // "v >= 0" and "v < lim" are each monotone; find where each holds.
-  if (inc) {
-    // v >= 0 turns true at some k; v < lim turns false at some k
-    int a = 1, b = K;  // first k with f(k) >= 0, K if none
-    while (a < b) {
-      const int m = (a + b) >> 1;
-      if (f(m) >= 0.0f) b = m;
-      else a = m + 1;
-    }
-    lo = a;
-    a = 0;
-    b = K - 1;  // last k with f(k) < lim, 0 if none
-    while (a < b) {
-      const int m = (a + b + 1) >> 1;
-      if (f(m) < lim) a = m;
-      else b = m - 1;
-    }
-    hi = a;
-  } else {
-    int a = 1, b = K;  // first k with f(k) < lim
-    while (a < b) {
-      const int m = (a + b) >> 1;
-      if (f(m) < lim) b = m;
-      else a = m + 1;
-    }
-    lo = a;
-    a = 0;
-    b = K - 1;  // last k with f(k) >= 0
-    while (a < b) {
-      const int m = (a + b + 1) >> 1;
-      if (f(m) >= 0.0f) a = m;
-      else b = m - 1;
-    }
-    hi = a;
+  // "v >= 0" and "v < lim" are each monotone in k: find where each holds.
+  // P(k) = (inc ? f >= 0 : f < lim) turns true once; Q(k) = (inc ? f < lim :
+  // f >= 0) turns false once.
+  int a = 1, b = K;  // first k with P(k), K if none
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    const float v = f_of<kIsX>(r, m, inv_r);
+    if (inc ? (v >= 0.0f) : (v < lim)) b = m;
+    else a = m + 1;
   }
+  lo = a;
+  a = 0;
+  b = K - 1;  // last k with Q(k), 0 if none
+  while (a < b) {
+    const int m = (a + b + 1) >> 1;
+    const float v = f_of<kIsX>(r, m, inv_r);
+    if (inc ? (v < lim) : (v >= 0.0f)) a = m;
+    else b = m - 1;
+  }
+  hi = a;
 }
 
-struct MarchArgs {
+// A cell can be removed only if it is valid, older than the minimum age and
+// has a normal.
+__device__ __forceinline__ bool clearable(const Layers& L, int64_t c, int32_t t_now, int32_t tau) {
+  return L.valid[c] && (((int64_t)t_now - (int64_t)L.t[c]) > (int64_t)tau) && !isnan(L.nz[c]);
+}
+
+struct ClearArgs {
   const float* x;
   const float* y;
   const float* z;
@@ -103,117 +102,152 @@ struct MarchArgs {
   Consts c;
   Layers L;
   int32_t t_now;
-  int bl;      // block side 2^bl cells
-  int bx, nb;  // blocks per map row, blocks in the map
+  int bl;          // block side 2^bl cells
+  int bx, by, nb;  // blocks per map row / column / total
+  int nprep;       // workgroups of the block role
+  ClearScratch s;
+  uint32_t* counter;  // queued segments
+  int64_t qcap;       // queue capacity (segments)
 };
 
-// A cell can be removed only if it is valid, older than the minimum age and
-// has a normal.  cmax[b] is the largest height of such a cell in block b
-// (-inf if none).  A sample at height q.z >= cmax[b] passes above every cell
-// of the block that could be removed (removal needs h > q.z), so the march
-// skips it without reading the cell.  This is exact pruning.
-__device__ __forceinline__ bool clearable(const Layers& L, int64_t c, int32_t t_now, int32_t tau) {
-  return L.valid[c] && (((int64_t)t_now - (int64_t)L.t[c]) > (int64_t)tau) && !isnan(L.nz[c]);
-}
-
-struct PrepArgs {
-  Consts c;
-  Layers L;
-  int32_t t_now;
-  int bl, bx, by;
-};
-
-// One wave per block of 2^bl x 2^bl cells.
-__global__ __launch_bounds__(kNTc) void k_clear_prep(PrepArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int b = blockIdx.x * (kNTc / 64) + (threadIdx.x >> 6);
-  if (b >= a.bx * a.by) return;  // whole wave leaves together
-  const int side = 1 << a.bl;
-  const int x0 = (b % a.bx) << a.bl;
-  const int y0 = (b / a.bx) << a.bl;
-  float v = -INFINITY;
-  for (int j = lane; j < side * side; j += 64) {
-    const int ix = x0 + (j & (side - 1));
-    const int iy = y0 + (j >> a.bl);
-    if (ix < a.c.nx && iy < a.c.ny) {
-      const int64_t c = (int64_t)iy * a.c.nx + ix;
-      if (clearable(a.L, c, a.t_now, a.c.tau)) v = fmaxf(v, a.L.h[c]);
-    }
+// Test samples k in [ka, kb] of ray r against the map.  cm holds the block
+// maxima; with cm == nullptr every sample is tested (same result, no pruning).
+__device__ __forceinline__ void march_range(const ClearArgs& a, const Ray& r, int ka, int kb,
+                                            int end_cell, const float* cm) {
+  const float an2dd = a.c.an2 * ((r.dx * r.dx + r.dy * r.dy) + r.dz * r.dz);
+  const int bl = a.bl;
+  for (int k = ka; k <= kb; ++k) {
+    const float t = t_of(r, k);
+    const float qx = r.ox + t * r.dx;
+    const float qy = r.oy + t * r.dy;
+    const float qz = r.oz + t * r.dz;
+    int ix, iy;
+    if (!bin_xy(qx, qy, a.c, ix, iy)) continue;
+    if (cm && !(qz < cm[(iy >> bl) * a.bx + (ix >> bl)])) continue;
+    const int c = iy * a.c.nx + ix;
+    if (c == end_cell) continue;
+    // one round trip: every field the test may need
+    const uint8_t vc = a.L.valid[c];
+    const int32_t tc = a.L.t[c];
+    const float hc = a.L.h[c];
+    const float varc = a.L.v[c];
+    const float nxc = a.L.nx[c];
+    const float nyc = a.L.ny[c];
+    const float nzc = a.L.nz[c];
+    const float hd = hc - qz;
+    if (!vc || !(((int64_t)a.t_now - (int64_t)tc) > (int64_t)a.c.tau) || isnan(nzc)) continue;
+    if (!(hd > 0.0f) || !((hd * hd) > varc)) continue;
+    const float dot = (r.dx * nxc + r.dy * nyc) + r.dz * nzc;
+    if ((dot * dot) > an2dd) a.L.mark[c] = 1;
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  if (lane == 0) a.L.cmax[b] = v;
 }
 
-constexpr int kUnroll = 4;
-
-__global__ __launch_bounds__(kNTc) void k_clear_march(MarchArgs a) {
-  extern __shared__ float s_cmax[];
-  for (int j = threadIdx.x; j < a.nb; j += kNTc) s_cmax[j] = a.L.cmax[j];
-  __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * kNTc + threadIdx.x;
-  if (i >= a.n) return;
-  const PointEval e = eval_point(a.P, a.c, a.x[i], a.y[i], a.z[i]);
-  if (!e.valid) return;
+__global__ __launch_bounds__(kNTc) void k_clear_setup(ClearArgs a) {
+  const int lane = threadIdx.x & 63;
+  if ((int)blockIdx.x < a.nprep) {
+    // ---- block role: one wave per block of cells
+    const int b = blockIdx.x * (kNTc / 64) + (threadIdx.x >> 6);
+    if (b >= a.nb) return;  // whole wave leaves together
+    const int side = 1 << a.bl;
+    const int x0 = (b % a.bx) << a.bl;
+    const int y0 = (b / a.bx) << a.bl;
+    float v = -INFINITY;
+    for (int j = lane; j < side * side; j += 64) {
+      const int ix = x0 + (j & (side - 1));
+      const int iy = y0 + (j >> a.bl);
+      if (ix < a.c.nx && iy < a.c.ny) {
+        const int64_t c = (int64_t)iy * a.c.nx + ix;
+        if (clearable(a.L, c, a.t_now, a.c.tau)) v = fmaxf(v, a.L.h[c]);
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    if (lane == 0) a.L.cmax[b] = v;
+    return;
+  }
+  // ---- ray role
+  const int64_t i = (int64_t)(blockIdx.x - a.nprep) * kNTc + threadIdx.x;
   Ray r;
   r.ox = a.P.t[0];
   r.oy = a.P.t[1];
   r.oz = a.P.t[2];
-  r.dx = e.xm - r.ox;
-  r.dy = e.ym - r.oy;
-  r.dz = e.zm - r.oz;
-  const float m = fmaxf(fabsf(r.dx), fabsf(r.dy));
-  const float ks = m * a.c.inv_step;
-  if (!(ks < 16777216.0f)) return;
-  const int K = (int)ceilf(ks);
-  if (K < 2) return;
-  r.Kf = (float)K;
-  int ex = -1, ey = -1;
-  const bool end_in = bin_xy(e.xm, e.ym, a.c, ex, ey);
-  const int end_cell = end_in ? ey * a.c.nx + ex : -1;
-
-  int lx, hx, ly, hy;
-  axis_range<true>(r, K, a.c.inv_r, a.c.nxf, r.dx >= 0.0f, lx, hx);
-  axis_range<false>(r, K, a.c.inv_r, a.c.nyf, r.dy >= 0.0f, ly, hy);
-  const int k0 = max(lx, ly);
-  const int k1 = min(hx, hy);
-
-  const float an2dd = a.c.an2 * ((r.dx * r.dx + r.dy * r.dy) + r.dz * r.dz);
-  const int bl = a.bl;
-  for (int k = k0; k <= k1; k += kUnroll) {
-    int cell[kUnroll];
-    float qz[kUnroll];
-    bool hit[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      float qx, qy;
-      sample(r, k + u, qx, qy, qz[u]);
-      int ix, iy;
-      cell[u] = -1;
-      hit[u] = false;
-      if (k + u <= k1 && bin_xy(qx, qy, a.c, ix, iy)) {
-        cell[u] = iy * a.c.nx + ix;
-        hit[u] = qz[u] < s_cmax[(iy >> bl) * a.bx + (ix >> bl)];
+  r.dx = r.dy = r.dz = 0.0f;
+  r.Kf = 1.0f;
+  int k0 = 1, k1 = 0, end_cell = -1;
+  if (i < a.n) {
+    const PointEval e = eval_point(a.P, a.c, a.x[i], a.y[i], a.z[i]);
+    r.dx = e.xm - r.ox;
+    r.dy = e.ym - r.oy;
+    r.dz = e.zm - r.oz;
+    const float m = fmaxf(fabsf(r.dx), fabsf(r.dy));
+    const float ks = m * a.c.inv_step;
+    if (e.valid && ks < 16777216.0f) {
+      const int K = (int)ceilf(ks);
+      if (K >= 2) {
+        r.Kf = (float)K;
+        int ex, ey;
+        if (bin_xy(e.xm, e.ym, a.c, ex, ey)) end_cell = ey * a.c.nx + ex;
+        int lx, hx, ly, hy;
+        axis_range<true>(r, K, a.c.inv_r, a.c.nxf, r.dx >= 0.0f, lx, hx);
+        axis_range<false>(r, K, a.c.inv_r, a.c.nyf, r.dy >= 0.0f, ly, hy);
+        k0 = max(lx, ly);
+        k1 = min(hx, hy);
       }
     }
+  }
+  const int ns = k1 >= k0 ? k1 - k0 + 1 : 0;
+  const int nseg = (ns + kSeg - 1) / kSeg;
+  // wave-aggregated reservation of queue slots
+  int x = nseg;
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      if (!hit[u] || cell[u] == end_cell) continue;
-      const int c = cell[u];
-      // one round trip: every field the test may need
-      const uint8_t vc = a.L.valid[c];
-      const int32_t tc = a.L.t[c];
-      const float hc = a.L.h[c];
-      const float varc = a.L.v[c];
-      const float nxc = a.L.nx[c];
-      const float nyc = a.L.ny[c];
-      const float nzc = a.L.nz[c];
-      const float hd = hc - qz[u];
-      if (!vc || !(((int64_t)a.t_now - (int64_t)tc) > (int64_t)a.c.tau) || isnan(nzc)) continue;
-      if (!(hd > 0.0f) || !((hd * hd) > varc)) continue;
-      const float dot = (r.dx * nxc + r.dy * nyc) + r.dz * nzc;
-      if ((dot * dot) > an2dd) a.L.mark[c] = 1;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  const int wtot = __shfl(x, 63, 64);
+  uint32_t wbase = 0;
+  if (lane == 0 && wtot > 0) wbase = atomicAdd(a.counter, (uint32_t)wtot);
+  wbase = __shfl(wbase, 0, 64);
+  if (nseg == 0) return;
+  const int64_t first = (int64_t)wbase + (x - nseg);
+  if (first + nseg <= a.qcap) {
+    a.s.ray[i] = make_float4(r.dx, r.dy, r.dz, r.Kf);
+    a.s.ray_end[i] = end_cell;
+    for (int sgi = 0; sgi < nseg; ++sgi) {
+      const int ka = k0 + sgi * kSeg;
+      const int cnt = min(kSeg, k1 - ka + 1);
+      a.s.queue[first + sgi] = make_uint2((uint32_t)i, ((uint32_t)ka << 8) | (uint32_t)cnt);
     }
+  } else {
+    // queue full: leave empty entries in any reserved slots and march here,
+    // unpruned (the block maxima are still being written by this launch)
+    for (int64_t q = first; q < first + nseg && q < a.qcap; ++q)
+      a.s.queue[q] = make_uint2(0u, 0u);
+    march_range(a, r, k0, k1, end_cell, nullptr);
+  }
+}
+
+__global__ __launch_bounds__(kNTc) void k_clear_march(ClearArgs a) {
+  extern __shared__ float s_cmax[];
+  for (int j = threadIdx.x; j < a.nb; j += kNTc) s_cmax[j] = a.L.cmax[j];
+  __syncthreads();
+  const int64_t total = min((int64_t)*a.counter, a.qcap);
+  Ray r;
+  r.ox = a.P.t[0];
+  r.oy = a.P.t[1];
+  r.oz = a.P.t[2];
+  for (int64_t q = (int64_t)blockIdx.x * kNTc + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * kNTc) {
+    const uint2 e = a.s.queue[q];
+    const int cnt = (int)(e.y & 255u);
+    if (cnt == 0) continue;
+    const int ka = (int)(e.y >> 8);
+    const float4 d = a.s.ray[e.x];
+    r.dx = d.x;
+    r.dy = d.y;
+    r.dz = d.z;
+    r.Kf = d.w;
+    march_range(a, r, ka, ka + cnt - 1, a.s.ray_end[e.x], s_cmax);
   }
 }
 
@@ -222,10 +256,12 @@ struct ApplyArgs {
   Layers L;
   int64_t cells;
   uint8_t* out;
+  uint32_t* counter;
 };
 
 __global__ __launch_bounds__(kNTc) void k_clear_apply(ApplyArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kNTc + threadIdx.x;
+  if (i == 0) *a.counter = 0u;
   if (i >= a.cells) return;
   const uint8_t m = a.L.mark[i];
   if (a.out) a.out[i] = m;
@@ -237,26 +273,34 @@ __global__ __launch_bounds__(kNTc) void k_clear_apply(ApplyArgs a) {
   }
 }
 
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 }  // namespace
+
+size_t clear_scratch_layout(int64_t max_points, char* base, ClearScratch* out) {
+  const size_t n = (size_t)max_points;
+  size_t off = 0;
+  const size_t o_ray = off;
+  off = align256(off + n * sizeof(float4));
+  const size_t o_end = off;
+  off = align256(off + n * sizeof(int32_t));
+  const size_t o_q = off;
+  off = align256(off + n * kQueuePerRay * sizeof(uint2));
+  if (out && base) {
+    out->ray = (float4*)(base + o_ray);
+    out->ray_end = (int32_t*)(base + o_end);
+    out->queue = (uint2*)(base + o_q);
+  }
+  return off;
+}
 
 hipError_t launch_clear(const float* x, const float* y, const float* z, int64_t n,
                         const Pose32& P, const Consts& c, const Layers& L, int32_t t_now,
-                        uint8_t* out_cleared, hipStream_t stream) {
+                        const ClearScratch& s, uint32_t* counter, uint8_t* out_cleared,
+                        int march_grid, hipStream_t stream) {
   const int64_t cells = (int64_t)c.nx * c.ny;
   if (n > 0) {
-    PrepArgs pa;
-    pa.c = c;
-    pa.L = L;
-    pa.t_now = t_now;
-    pa.bl = block_log_of(c.nx, c.ny);
-    pa.bx = blocks_of(c.nx, pa.bl);
-    pa.by = blocks_of(c.ny, pa.bl);
-    const int nb = pa.bx * pa.by;
-    hipLaunchKernelGGL(k_clear_prep, dim3((nb + kNTc / 64 - 1) / (kNTc / 64)), dim3(kNTc), 0,
-                       stream, pa);
-    hipError_t err0 = hipGetLastError();
-    if (err0 != hipSuccess) return err0;
-    MarchArgs a;
+    ClearArgs a;
     a.x = x;
     a.y = y;
     a.z = z;
@@ -265,12 +309,21 @@ hipError_t launch_clear(const float* x, const float* y, const float* z, int64_t 
     a.c = c;
     a.L = L;
     a.t_now = t_now;
-    a.bl = pa.bl;
-    a.bx = pa.bx;
-    a.nb = nb;
-    hipLaunchKernelGGL(k_clear_march, dim3((unsigned)((n + kNTc - 1) / kNTc)), dim3(kNTc),
-                       (size_t)nb * sizeof(float), stream, a);
+    a.bl = block_log_of(c.nx, c.ny);
+    a.bx = blocks_of(c.nx, a.bl);
+    a.by = blocks_of(c.ny, a.bl);
+    a.nb = a.bx * a.by;
+    a.nprep = (a.nb + kNTc / 64 - 1) / (kNTc / 64);
+    a.s = s;
+    a.counter = counter;
+    a.qcap = n * kQueuePerRay;
+    const unsigned nray = (unsigned)((n + kNTc - 1) / kNTc);
+    hipLaunchKernelGGL(k_clear_setup, dim3((unsigned)a.nprep + nray), dim3(kNTc), 0, stream, a);
     hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_clear_march, dim3((unsigned)march_grid), dim3(kNTc),
+                       (size_t)a.nb * sizeof(float), stream, a);
+    err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
   ApplyArgs b;
@@ -278,6 +331,7 @@ hipError_t launch_clear(const float* x, const float* y, const float* z, int64_t 
   b.L = L;
   b.cells = cells;
   b.out = out_cleared;
+  b.counter = counter;
   hipLaunchKernelGGL(k_clear_apply, dim3((unsigned)((cells + kNTc - 1) / kNTc)), dim3(kNTc), 0,
                      stream, b);
   return hipGetLastError();

@@ -34,14 +34,14 @@ struct Layers {
   float* cmax;    // per 8x8 block: max height over cells a ray may clear (transient)
 };
 
-// Clearing prunes samples by square blocks of 2^b cells, b in [3, 5]: the
+// Clearing prunes samples by square blocks of 2^b cells, b >= 3: the
 // smallest b whose block grid fits kMaxBlkBytes, so that it can sit in LDS.
 constexpr int kMaxBlkBytes = 48 * 1024;
 __host__ __device__ inline int blocks_of(int n, int b) { return (n + (1 << b) - 1) >> b; }
 __host__ __device__ inline int block_log_of(int nx, int ny) {
-  for (int b = 3; b < 5; ++b)
-    if ((long long)blocks_of(nx, b) * blocks_of(ny, b) * 4 <= kMaxBlkBytes) return b;
-  return 5;
+  int b = 3;
+  while ((long long)blocks_of(nx, b) * blocks_of(ny, b) * 4 > kMaxBlkBytes) ++b;
+  return b;
 }
 
 // Float32 constants derived once on the host from emx_params.

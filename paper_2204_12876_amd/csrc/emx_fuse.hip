@@ -5,8 +5,8 @@
 //   - Takes the per-point decisions: transform, range, bin, and the Mahalanobis
 //     gate against the frame-start prior.
 //   - Sorts the accepted points in LDS by (tile, cell in tile, point index).
-//   - Each cell's run is reduced to one partial, sum 1/sp2 and sum zm/sp2,
-//     added left to right in point order.
+//   - Each cell's run is reduced to one partial, sum 1/sp2 and sum zm/sp2, by
+//     a pairwise tree aligned to the run start.
 //   - Writes the partials, grouped by tile, and a dense tile directory row for
 //     the chunk.
 // Pass 2, k_fuse_tile: one workgroup per 32x32-cell map tile.
@@ -16,9 +16,9 @@
 //   - Adds each cell's partials in chunk order and applies the information-form
 //     update once per touched cell.
 //
-// The float32 sums therefore run in an order fixed by the frame alone: left
-// to right over a cell's points within each chunk, then chunk partials in chunk
-// order.  Results are bitwise identical from run to run, whatever the tile
+// The float32 sums therefore run in an order fixed by the frame alone: a
+// pairwise tree over a cell's points in point order within each chunk, then
+// chunk partials left to right in chunk order.  Results are bitwise identical from run to run, whatever the tile
 // size, grid shape or batching of pass 2.
 #include "emx_kernels.h"
 
@@ -96,6 +96,9 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
   __shared__ float s_w[kChunk];
   __shared__ float s_wz[kChunk];
   __shared__ uint32_t s_seg[kChunk];   // (tile << 2*kTileLog | local) of record r
+  __shared__ float s_vw[kChunk];       // per-key values in sorted order (tree sums)
+  __shared__ float s_vwz[kChunk];
+  __shared__ int16_t s_head[kChunk];   // position of each key's run head
   __shared__ int s_isum[kNT1 / 64];
 
   const int tid = threadIdx.x;
@@ -147,36 +150,102 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
   s_key[2 * tid + 1] = key[1];
   __syncthreads();
 
-  // ---- one partial per (tile, local) run, summed left to right in point order
-  // by the thread that holds the run's first key.  The sum depends only on the
-  // run, never on where it landed in the sorted array.
+  // ---- one partial per (tile, local) run.  Each run is reduced by a pairwise
+  // tree aligned to the run's first key: at level L the key at offset j
+  // (j a multiple of 2^(L+1)) absorbs the key at j + 2^L if that one is in the
+  // run.  The tree depends only on the run's length, never on where the run
+  // landed in the sorted array.
   int heads = 0;
-  bool hd[2];
+  int hpos[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int q = 2 * tid + j;
-    hd[j] = q < nacc && (q == 0 || (s_key[q - 1] >> 12) != (s_key[q] >> 12));
-    heads += hd[j] ? 1 : 0;
+    const bool h = q < nacc && (q == 0 || (s_key[q - 1] >> 12) != (s_key[q] >> 12));
+    hpos[j] = h ? q : -1;
+    heads += h ? 1 : 0;
+  }
+  // run head of every key: inclusive max-scan of head positions
+  {
+    int m0 = hpos[0];
+    int m1 = max(hpos[0], hpos[1]);
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    int x = m1;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x = max(x, y);
+    }
+    if (lane == 63) s_isum[wid] = x;
+    int ex = __shfl_up(x, 1, 64);
+    if (lane == 0) ex = -1;
+    __syncthreads();
+    int pre = -1;
+    for (int w = 0; w < wid; ++w) pre = max(pre, s_isum[w]);
+    __syncthreads();
+    ex = max(ex, pre);
+    s_head[2 * tid] = (int16_t)max(ex, m0);
+    s_head[2 * tid + 1] = (int16_t)max(ex, m1);
+    // values in sorted order
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int q = 2 * tid + j;
+      if (q < nacc) {
+        const int p = (int)(s_key[q] & 0xFFF);
+        s_vw[q] = s_w[p];
+        s_vwz[q] = s_wz[p];
+      }
+    }
+  }
+  __syncthreads();
+  // tree levels: ceil(log2(longest run)); a partner is in the run iff it
+  // has the same head
+  int levels = 0;
+  {
+    int longest = 0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int q = 2 * tid + j;
+      if (q < nacc && (q == nacc - 1 || s_head[q + 1] != s_head[q]))
+        longest = max(longest, q - (int)s_head[q] + 1);
+    }
+    int all = 0;
+    const int lane = tid & 63;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) longest = max(longest, __shfl_xor(longest, o, 64));
+    if (lane == 0) s_isum[tid >> 6] = longest;
+    __syncthreads();
+    for (int w = 0; w < kNT1 / 64; ++w) all = max(all, s_isum[w]);
+    __syncthreads();
+    while ((1 << levels) < all) ++levels;
+  }
+  for (int L = 0; L < levels; ++L) {
+    const int st = 1 << L;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int q = 2 * tid + j;
+      if (q >= nacc) continue;
+      const int off = q - (int)s_head[q];
+      if ((off & (2 * st - 1)) != 0) continue;
+      const int pq = q + st;
+      if (pq < nacc && s_head[pq] == s_head[q]) {
+        s_vw[q] = s_vw[q] + s_vw[pq];
+        s_vwz[q] = s_vwz[q] + s_vwz[pq];
+      }
+    }
+    __syncthreads();
   }
   int nrec = 0;
   int r = block_exclusive_sum<kNT1>(heads, nrec, s_isum);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    if (!hd[j]) continue;
-    const int q = 2 * tid + j;
+    if (hpos[j] < 0) continue;
+    const int q = hpos[j];
     const uint64_t sk = s_key[q] >> 12;
-    const int p0 = (int)(s_key[q] & 0xFFF);
-    float rw = s_w[p0];
-    float rwz = s_wz[p0];
-    for (int qq = q + 1; qq < nacc && (s_key[qq] >> 12) == sk; ++qq) {
-      const int pp = (int)(s_key[qq] & 0xFFF);
-      rw = rw + s_w[pp];
-      rwz = rwz + s_wz[pp];
-    }
     const int64_t o = base + r;
     a.s.rec_local[o] = (uint16_t)(sk & (kTileCells - 1));
-    a.s.rec_w[o] = rw;
-    a.s.rec_wz[o] = rwz;
+    a.s.rec_w[o] = s_vw[q];
+    a.s.rec_wz[o] = s_vwz[q];
     s_seg[r] = (uint32_t)sk;
     ++r;
   }

@@ -28,12 +28,25 @@ hipError_t launch_fuse(const float* x, const float* y, const float* z, int64_t n
                        hipStream_t stream);
 
 // ---------------------------------------------------------------- clearing
+struct ClearScratch {
+  float4* ray;       // [n] (dx, dy, dz, K) of each queued ray
+  int32_t* ray_end;  // [n] end point's cell or -1
+  uint2* queue;      // [4n] (ray, k_start << 8 | count) segments
+};
+
+size_t clear_scratch_layout(int64_t max_points, char* base, ClearScratch* out);
+
+// `counter` (one uint32 in the map's control block) must be zero on entry;
+// the call leaves it zero.
 hipError_t launch_clear(const float* x, const float* y, const float* z, int64_t n,
                         const Pose32& P, const Consts& c, const Layers& L, int32_t t_now,
-                        uint8_t* out_cleared, hipStream_t stream);
+                        const ClearScratch& s, uint32_t* counter, uint8_t* out_cleared,
+                        int march_grid, hipStream_t stream);
 
 // --------------------------------------------------------------- per cell
-hipError_t launch_fill_prior(const Consts& c, const Layers& L, hipStream_t stream);
+// Fills L with the prior and zeroes ctl[0..nctl).
+hipError_t launch_fill_prior(const Consts& c, const Layers& L, uint32_t* ctl, int nctl,
+                             hipStream_t stream);
 hipError_t launch_move(const Consts& c, const Layers& src, const Layers& dst, int sx, int sy,
                        hipStream_t stream);
 hipError_t launch_normals(const Consts& c, const Layers& L, hipStream_t stream);
