@@ -107,8 +107,9 @@ size_t set_layout(const emx_params& p, char* base, Layers* L) {
 
 }  // namespace
 
-// Per-map control words after the two buffer sets: [0] clearing queue counter.
-constexpr int kCtlWords = 64;
+// Per-map control words after the two buffer sets: the clearing sub-queue
+// counters (64 counters, 128 bytes apart).
+constexpr int kCtlWords = 64 * 32;
 
 struct emx_map {
   emx_params p;

@@ -15,9 +15,10 @@
 //         each is a correctly rounded chain of monotone operations.  The range
 //         is found by binary search with the very sample evaluation the march
 //         uses.
-//       - the range is cut into segments of kSeg samples, queued with one
-//         integer atomic per wave.  A ray that would overflow the bounded
-//         queue is marched in place instead.
+//       - the range is cut into segments of kSeg samples.  Each workgroup
+//         reserves its segments with one integer atomic, in one of kSubQ
+//         sub-queues, so no counter is contended.  A ray that would overflow
+//         its bounded sub-queue is marched in place instead.
 // k_clear_march: a persistent grid drains the queue, one segment per thread.
 //   - A sample at height q.z >= the block maximum passes above every cell that
 //     could be removed, since removal needs h > q.z.  It is skipped without
@@ -27,7 +28,7 @@
 //   - The state is only read, so every ray sees the state as it was when the
 //     call started.
 // k_clear_apply: resets marked cells to the prior, reports and clears the
-// marks, and rewinds the queue counter for the next call.
+// marks, and rewinds the queue counters for the next call.
 #include "emx_kernels.h"
 
 namespace emx {
@@ -37,14 +38,25 @@ namespace {
 constexpr int kNTc = 256;
 constexpr int kSeg = 32;          // samples per queued segment
 constexpr int kQueuePerRay = 4;   // queue capacity, in segments per point
+constexpr int kSubQ = 64;         // sub-queues, each with its own counter
+constexpr int kCtrStride = 32;    // counters 128 bytes apart
 
 struct Ray {
   float ox, oy, oz;
   float dx, dy, dz;
   float Kf;
+  double rK;  // 1/K, correctly rounded in double
 };
 
-__device__ __forceinline__ float t_of(const Ray& r, int k) { return (float)k / r.Kf; }
+// t = float32(k / K), correctly rounded, without a float32 division.
+// For integers 1 <= k < K < 2^24, k/K lies more than 2^-49 (relative) from
+// every float32 rounding boundary: a boundary is an odd multiple of half an
+// ulp, and k/K equal to one would need K > k >= 2^24.  The double product
+// k * RN(1/K) carries at most 2^-52 relative error, so it rounds to the same
+// float32 as k/K.
+__device__ __forceinline__ float t_of(const Ray& r, int k) {
+  return (float)((double)k * r.rK);
+}
 
 // f(k) = q_k.x * inv_r (or .y), exactly as binning computes it
 template <bool kIsX>
@@ -106,8 +118,8 @@ struct ClearArgs {
   int bx, by, nb;  // blocks per map row / column / total
   int nprep;       // workgroups of the block role
   ClearScratch s;
-  uint32_t* counter;  // queued segments
-  int64_t qcap;       // queue capacity (segments)
+  uint32_t* counter;  // kSubQ counters of queued segments, kCtrStride apart
+  int64_t qcap;       // capacity of each sub-queue (segments)
 };
 
 // Test samples k in [ka, kb] of ray r against the map.  cm holds the block
@@ -173,6 +185,7 @@ __global__ __launch_bounds__(kNTc) void k_clear_setup(ClearArgs a) {
   r.oz = a.P.t[2];
   r.dx = r.dy = r.dz = 0.0f;
   r.Kf = 1.0f;
+  r.rK = 1.0;
   int k0 = 1, k1 = 0, end_cell = -1;
   if (i < a.n) {
     const PointEval e = eval_point(a.P, a.c, a.x[i], a.y[i], a.z[i]);
@@ -185,6 +198,7 @@ __global__ __launch_bounds__(kNTc) void k_clear_setup(ClearArgs a) {
       const int K = (int)ceilf(ks);
       if (K >= 2) {
         r.Kf = (float)K;
+        r.rK = 1.0 / (double)K;
         int ex, ey;
         if (bin_xy(e.xm, e.ym, a.c, ex, ey)) end_cell = ey * a.c.nx + ex;
         int lx, hx, ly, hy;
@@ -197,48 +211,64 @@ __global__ __launch_bounds__(kNTc) void k_clear_setup(ClearArgs a) {
   }
   const int ns = k1 >= k0 ? k1 - k0 + 1 : 0;
   const int nseg = (ns + kSeg - 1) / kSeg;
-  // wave-aggregated reservation of queue slots
-  int x = nseg;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  const int wtot = __shfl(x, 63, 64);
-  uint32_t wbase = 0;
-  if (lane == 0 && wtot > 0) wbase = atomicAdd(a.counter, (uint32_t)wtot);
-  wbase = __shfl(wbase, 0, 64);
+  // one reservation per workgroup, in the sub-queue of this workgroup
+  __shared__ int s_isum[kNTc / 64];
+  __shared__ uint32_t s_base;
+  int wtot = 0;
+  const int off = block_exclusive_sum<kNTc>(nseg, wtot, s_isum);
+  const int sub = (int)((blockIdx.x - a.nprep) % kSubQ);
+  if (threadIdx.x == 0) s_base = wtot > 0 ? atomicAdd(a.counter + sub * kCtrStride, (uint32_t)wtot) : 0u;
+  __syncthreads();
   if (nseg == 0) return;
-  const int64_t first = (int64_t)wbase + (x - nseg);
+  const int64_t first = (int64_t)s_base + off;
+  uint2* q = a.s.queue + (int64_t)sub * a.qcap;
   if (first + nseg <= a.qcap) {
     a.s.ray[i] = make_float4(r.dx, r.dy, r.dz, r.Kf);
     a.s.ray_end[i] = end_cell;
     for (int sgi = 0; sgi < nseg; ++sgi) {
       const int ka = k0 + sgi * kSeg;
       const int cnt = min(kSeg, k1 - ka + 1);
-      a.s.queue[first + sgi] = make_uint2((uint32_t)i, ((uint32_t)ka << 8) | (uint32_t)cnt);
+      q[first + sgi] = make_uint2((uint32_t)i, ((uint32_t)ka << 8) | (uint32_t)cnt);
     }
   } else {
-    // queue full: leave empty entries in any reserved slots and march here,
-    // unpruned (the block maxima are still being written by this launch)
-    for (int64_t q = first; q < first + nseg && q < a.qcap; ++q)
-      a.s.queue[q] = make_uint2(0u, 0u);
+    // sub-queue full: leave empty entries in any reserved slots and march
+    // here, unpruned (the block maxima are still being written by this launch)
+    for (int64_t e = first; e < first + nseg && e < a.qcap; ++e) q[e] = make_uint2(0u, 0u);
     march_range(a, r, k0, k1, end_cell, nullptr);
   }
 }
 
 __global__ __launch_bounds__(kNTc) void k_clear_march(ClearArgs a) {
   extern __shared__ float s_cmax[];
+  __shared__ int64_t s_qoff[kSubQ + 1];
   for (int j = threadIdx.x; j < a.nb; j += kNTc) s_cmax[j] = a.L.cmax[j];
+  if (threadIdx.x < 64) {
+    // prefix of the sub-queue fill levels (kSubQ == 64: one wave)
+    const int64_t c = min((int64_t)a.counter[threadIdx.x * kCtrStride], a.qcap);
+    int64_t x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t y = __shfl_up(x, o, 64);
+      if ((int)threadIdx.x >= o) x += y;
+    }
+    s_qoff[threadIdx.x + 1] = x;
+    if (threadIdx.x == 0) s_qoff[0] = 0;
+  }
   __syncthreads();
-  const int64_t total = min((int64_t)*a.counter, a.qcap);
+  const int64_t total = s_qoff[kSubQ];
   Ray r;
   r.ox = a.P.t[0];
   r.oy = a.P.t[1];
   r.oz = a.P.t[2];
-  for (int64_t q = (int64_t)blockIdx.x * kNTc + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * kNTc) {
-    const uint2 e = a.s.queue[q];
+  for (int64_t g = (int64_t)blockIdx.x * kNTc + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * kNTc) {
+    int lo = 0, hi = kSubQ - 1;  // sub-queue holding global entry g
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_qoff[mid] <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint2 e = a.s.queue[(int64_t)lo * a.qcap + (g - s_qoff[lo])];
     const int cnt = (int)(e.y & 255u);
     if (cnt == 0) continue;
     const int ka = (int)(e.y >> 8);
@@ -247,6 +277,7 @@ __global__ __launch_bounds__(kNTc) void k_clear_march(ClearArgs a) {
     r.dy = d.y;
     r.dz = d.z;
     r.Kf = d.w;
+    r.rK = 1.0 / (double)d.w;
     march_range(a, r, ka, ka + cnt - 1, a.s.ray_end[e.x], s_cmax);
   }
 }
@@ -261,7 +292,7 @@ struct ApplyArgs {
 
 __global__ __launch_bounds__(kNTc) void k_clear_apply(ApplyArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kNTc + threadIdx.x;
-  if (i == 0) *a.counter = 0u;
+  if (i < kSubQ) a.counter[i * kCtrStride] = 0u;
   if (i >= a.cells) return;
   const uint8_t m = a.L.mark[i];
   if (a.out) a.out[i] = m;
@@ -285,7 +316,7 @@ size_t clear_scratch_layout(int64_t max_points, char* base, ClearScratch* out) {
   const size_t o_end = off;
   off = align256(off + n * sizeof(int32_t));
   const size_t o_q = off;
-  off = align256(off + n * kQueuePerRay * sizeof(uint2));
+  off = align256(off + (size_t)kSubQ * ((n * kQueuePerRay + kSubQ - 1) / kSubQ) * sizeof(uint2));
   if (out && base) {
     out->ray = (float4*)(base + o_ray);
     out->ray_end = (int32_t*)(base + o_end);
@@ -316,7 +347,7 @@ hipError_t launch_clear(const float* x, const float* y, const float* z, int64_t 
     a.nprep = (a.nb + kNTc / 64 - 1) / (kNTc / 64);
     a.s = s;
     a.counter = counter;
-    a.qcap = n * kQueuePerRay;
+    a.qcap = (n * kQueuePerRay + kSubQ - 1) / kSubQ;
     const unsigned nray = (unsigned)((n + kNTc - 1) / kNTc);
     hipLaunchKernelGGL(k_clear_setup, dim3((unsigned)a.nprep + nray), dim3(kNTc), 0, stream, a);
     hipError_t err = hipGetLastError();

@@ -10,11 +10,11 @@
 //   - Writes the partials, grouped by tile, and a dense tile directory row for
 //     the chunk.
 // Pass 2, k_fuse_tile: one workgroup per 32x32-cell map tile.
-//   - Gathers the tile's partials from every chunk that touched it.
-//   - Orders them by (cell, chunk) with LDS occupancy bitmasks and popcount
-//     ranks.
-//   - Adds each cell's partials in chunk order and applies the information-form
-//     update once per touched cell.
+//   - Stages the tile's partials from every chunk that touched it in LDS.
+//   - Adds them chunk by chunk.  A chunk holds at most one partial per cell,
+//     so each chunk's partials go to the cells in parallel, and every cell
+//     sees its partials in chunk order.
+//   - Applies the information-form update once per touched cell.
 //
 // The float32 sums therefore run in an order fixed by the frame alone: a
 // pairwise tree over a cell's points in point order within each chunk, then
@@ -267,7 +267,6 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
 
 // ------------------------------------------------------------------ pass 2
 constexpr int kNT2 = 256;
-constexpr int kGroup = 64;     // chunks merged per LDS round (one bit each)
 constexpr int kCap = 4096;     // partials held in LDS per round
 constexpr int kWin = kNT2;     // directory entries read per window
 
@@ -284,22 +283,17 @@ struct TileArgs {
 __global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
   __shared__ float acc_w[kTileCells];
   __shared__ float acc_wz[kTileCells];
-  __shared__ uint64_t mask[kTileCells];
-  __shared__ uint32_t lstart[kTileCells];
   __shared__ uint8_t hit[kTileCells];
   __shared__ uint32_t e_chunk[kWin];
   __shared__ uint32_t e_start[kWin];
   __shared__ uint32_t e_cnt[kWin];
   __shared__ uint32_t e_pre[kWin + 1];
-  __shared__ uint32_t u_le[kCap];
+  __shared__ uint16_t u_l[kCap];
   __shared__ float u_w[kCap];
   __shared__ float u_wz[kCap];
-  __shared__ float o_w[kCap];
-  __shared__ float o_wz[kCap];
   __shared__ int s_isum[kNT2 / 64];
   __shared__ int s_g1;
 
-  constexpr int kLoc = kTileCells / kNT2;  // locals per thread
   const int tid = threadIdx.x;
   const int t = blockIdx.x;
   for (int l = tid; l < kTileCells; l += kNT2) {
@@ -328,9 +322,9 @@ __global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
     __syncthreads();
     int g0 = 0;
     while (g0 < L) {
-      // largest group [g0, g1): at most kGroup chunks and kCap partials
+      // largest group [g0, g1) whose partials fit in LDS
       if (tid == 0) {
-        int lo = g0 + 1, hi = min(L, g0 + kGroup);
+        int lo = g0 + 1, hi = L;
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
           if (e_pre[mid] - e_pre[g0] <= (uint32_t)kCap) lo = mid;
@@ -338,12 +332,11 @@ __global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
         }
         s_g1 = lo;
       }
-      for (int l = tid; l < kTileCells; l += kNT2) mask[l] = 0ull;
       __syncthreads();
       const int g1 = s_g1;
       const uint32_t pbase = e_pre[g0];
       const int tot = (int)(e_pre[g1] - pbase);
-      // gather this round's partials and mark which chunk holds which cell
+      // stage this group's partials in LDS, in (chunk, cell) order
       for (int p = tid; p < tot; p += kNT2) {
         const uint32_t gp = pbase + (uint32_t)p;
         int lo = g0, hi = g1 - 1;  // last entry whose prefix is <= gp
@@ -352,56 +345,25 @@ __global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
           if (e_pre[mid] <= gp) lo = mid;
           else hi = mid - 1;
         }
-        const int e = lo - g0;
         const int64_t idx = (int64_t)e_chunk[lo] * kChunk + e_start[lo] + (gp - e_pre[lo]);
-        const uint32_t local = a.s.rec_local[idx];
-        u_le[p] = (local << 8) | (uint32_t)e;
+        u_l[p] = a.s.rec_local[idx];
         u_w[p] = a.s.rec_w[idx];
         u_wz[p] = a.s.rec_wz[idx];
-        atomicOr((unsigned long long*)&mask[local], 1ull << e);
       }
       __syncthreads();
-      // start of each cell's run in (cell, chunk) order
-      int cnt[kLoc];
-      int mine = 0;
-#pragma unroll
-      for (int j = 0; j < kLoc; ++j) {
-        cnt[j] = __popcll(mask[tid * kLoc + j]);
-        mine += cnt[j];
-      }
-      int all = 0;
-      int run = block_exclusive_sum<kNT2>(mine, all, s_isum);
-#pragma unroll
-      for (int j = 0; j < kLoc; ++j) {
-        lstart[tid * kLoc + j] = (uint32_t)run;
-        run += cnt[j];
-      }
-      __syncthreads();
-      for (int p = tid; p < tot; p += kNT2) {
-        const uint32_t le = u_le[p];
-        const uint32_t local = le >> 8;
-        const uint32_t e = le & 0xFFu;
-        const uint64_t below = (e == 0) ? 0ull : (mask[local] & ((1ull << e) - 1ull));
-        const uint32_t dst = lstart[local] + (uint32_t)__popcll(below);
-        o_w[dst] = u_w[p];
-        o_wz[dst] = u_wz[p];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < kLoc; ++j) {
-        const int l = tid * kLoc + j;
-        if (cnt[j] == 0) continue;
-        float aw = acc_w[l], awz = acc_wz[l];
-        const uint32_t s0 = lstart[l];
-        for (int r = 0; r < cnt[j]; ++r) {
-          aw = aw + o_w[s0 + r];
-          awz = awz + o_wz[s0 + r];
+      // chunk by chunk: a chunk holds at most one partial per cell, so its
+      // partials are added to the cells in parallel; chunks go in order
+      for (int g = g0; g < g1; ++g) {
+        const int p0 = (int)(e_pre[g] - pbase);
+        const int p1 = (int)(e_pre[g + 1] - pbase);
+        for (int p = p0 + tid; p < p1; p += kNT2) {
+          const int l = u_l[p];
+          acc_w[l] = acc_w[l] + u_w[p];
+          acc_wz[l] = acc_wz[l] + u_wz[p];
+          hit[l] = 1;
         }
-        acc_w[l] = aw;
-        acc_wz[l] = awz;
-        hit[l] = 1;
+        __syncthreads();
       }
-      __syncthreads();
       g0 = g1;
     }
   }

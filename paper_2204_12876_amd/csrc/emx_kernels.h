@@ -31,13 +31,13 @@ hipError_t launch_fuse(const float* x, const float* y, const float* z, int64_t n
 struct ClearScratch {
   float4* ray;       // [n] (dx, dy, dz, K) of each queued ray
   int32_t* ray_end;  // [n] end point's cell or -1
-  uint2* queue;      // [4n] (ray, k_start << 8 | count) segments
+  uint2* queue;      // ~[4n] (ray, k_start << 8 | count) segments, in sub-queues
 };
 
 size_t clear_scratch_layout(int64_t max_points, char* base, ClearScratch* out);
 
-// `counter` (one uint32 in the map's control block) must be zero on entry;
-// the call leaves it zero.
+// `counter` (64 uint32 counters, 32 words apart, in the map's control block)
+// must be zero on entry; the call leaves it zero.
 hipError_t launch_clear(const float* x, const float* y, const float* z, int64_t n,
                         const Pose32& P, const Consts& c, const Layers& L, int32_t t_now,
                         const ClearScratch& s, uint32_t* counter, uint8_t* out_cleared,
