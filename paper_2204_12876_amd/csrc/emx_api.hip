@@ -174,7 +174,7 @@ int march_grid_for_device() {
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus <= 0)
     cus = 256;
-  return 4 * cus;
+  return 8 * cus;
 }
 
 }  // namespace

@@ -122,35 +122,56 @@ struct ClearArgs {
   int64_t qcap;       // capacity of each sub-queue (segments)
 };
 
+// The full removal test of sample q (height qz) in cell c.
+__device__ __forceinline__ void test_cell(const ClearArgs& a, const Ray& r, int c, float qz,
+                                          float an2dd) {
+  // one round trip: every field the test may need
+  const uint8_t vc = a.L.valid[c];
+  const int32_t tc = a.L.t[c];
+  const float hc = a.L.h[c];
+  const float varc = a.L.v[c];
+  const float nxc = a.L.nx[c];
+  const float nyc = a.L.ny[c];
+  const float nzc = a.L.nz[c];
+  const float hd = hc - qz;
+  if (!vc || !(((int64_t)a.t_now - (int64_t)tc) > (int64_t)a.c.tau) || isnan(nzc)) return;
+  if (!(hd > 0.0f) || !((hd * hd) > varc)) return;
+  const float dot = (r.dx * nxc + r.dy * nyc) + r.dz * nzc;
+  if ((dot * dot) > an2dd) a.L.mark[c] = 1;
+}
+
+constexpr int kUnroll = 4;
+
 // Test samples k in [ka, kb] of ray r against the map.  cm holds the block
 // maxima; with cm == nullptr every sample is tested (same result, no pruning).
+// kUnroll samples at a time: their cells and block maxima are found without
+// branches, so the block-maximum loads issue together.
 __device__ __forceinline__ void march_range(const ClearArgs& a, const Ray& r, int ka, int kb,
                                             int end_cell, const float* cm) {
   const float an2dd = a.c.an2 * ((r.dx * r.dx + r.dy * r.dy) + r.dz * r.dz);
   const int bl = a.bl;
-  for (int k = ka; k <= kb; ++k) {
-    const float t = t_of(r, k);
-    const float qx = r.ox + t * r.dx;
-    const float qy = r.oy + t * r.dy;
-    const float qz = r.oz + t * r.dz;
-    int ix, iy;
-    if (!bin_xy(qx, qy, a.c, ix, iy)) continue;
-    if (cm && !(qz < cm[(iy >> bl) * a.bx + (ix >> bl)])) continue;
-    const int c = iy * a.c.nx + ix;
-    if (c == end_cell) continue;
-    // one round trip: every field the test may need
-    const uint8_t vc = a.L.valid[c];
-    const int32_t tc = a.L.t[c];
-    const float hc = a.L.h[c];
-    const float varc = a.L.v[c];
-    const float nxc = a.L.nx[c];
-    const float nyc = a.L.ny[c];
-    const float nzc = a.L.nz[c];
-    const float hd = hc - qz;
-    if (!vc || !(((int64_t)a.t_now - (int64_t)tc) > (int64_t)a.c.tau) || isnan(nzc)) continue;
-    if (!(hd > 0.0f) || !((hd * hd) > varc)) continue;
-    const float dot = (r.dx * nxc + r.dy * nyc) + r.dz * nzc;
-    if ((dot * dot) > an2dd) a.L.mark[c] = 1;
+  for (int k = ka; k <= kb; k += kUnroll) {
+    int cell[kUnroll];
+    float qz[kUnroll];
+    bool cand[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const float t = t_of(r, k + u);
+      const float qx = r.ox + t * r.dx;
+      const float qy = r.oy + t * r.dy;
+      qz[u] = r.oz + t * r.dz;
+      const float fx = qx * a.c.inv_r;
+      const float fy = qy * a.c.inv_r;
+      const bool in = (k + u <= kb) && fx >= 0.0f && fx < a.c.nxf && fy >= 0.0f && fy < a.c.nyf;
+      const int ix = in ? (int)floorf(fx) : 0;
+      const int iy = in ? (int)floorf(fy) : 0;
+      cell[u] = iy * a.c.nx + ix;
+      const float m = cm ? cm[(iy >> bl) * a.bx + (ix >> bl)] : INFINITY;
+      cand[u] = in && (qz[u] < m) && cell[u] != end_cell;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (cand[u]) test_cell(a, r, cell[u], qz[u], an2dd);
   }
 }
 

@@ -27,14 +27,18 @@ namespace emx {
 namespace {
 
 constexpr int kNT1 = 1024;                // pass-1 threads: two keys each
-constexpr uint64_t kNoKey = ~0ull;
+constexpr int kPBits = 11;                // point index within the chunk
+constexpr int kSegBits = 2 * kTileLog;    // local cell within the tile
+// 32-bit keys hold (tile, local, point) while tile * kTileCells < 2^21.
+constexpr int64_t kMaxCells32 = (int64_t)1 << (32 - kPBits);
 
 // Ascending bitonic sort of the block's 2 * kNT1 keys.  Thread t holds the
 // keys of sorted positions 2t and 2t+1 in (a, b).
 //   - Compare-exchanges across waves (stride >= 128) go through LDS.
 //   - Strides 2..64 pair lanes of one wave: they use lane shuffles.
 //   - Stride 1 stays within the thread.
-__device__ __forceinline__ void bitonic_sort_regs(uint64_t& a, uint64_t& b, uint64_t* s) {
+template <typename KeyT>
+__device__ __forceinline__ void bitonic_sort_regs(KeyT& a, KeyT& b, KeyT* s) {
   const int tid = threadIdx.x;
   const int i0 = 2 * tid;
   for (int size = 2; size <= 2 * kNT1; size <<= 1) {
@@ -47,8 +51,8 @@ __device__ __forceinline__ void bitonic_sort_regs(uint64_t& a, uint64_t& b, uint
         const int lo = 2 * tid - (tid & (stride - 1));
         const int hi = lo + stride;
         const bool up = (lo & size) == 0;
-        const uint64_t x = s[lo];
-        const uint64_t y = s[hi];
+        const KeyT x = s[lo];
+        const KeyT y = s[hi];
         if ((x > y) == up) {
           s[lo] = y;
           s[hi] = x;
@@ -61,14 +65,14 @@ __device__ __forceinline__ void bitonic_sort_regs(uint64_t& a, uint64_t& b, uint
     }
     const bool up = (i0 & size) == 0;
     for (; stride >= 2; stride >>= 1) {
-      const uint64_t pa = __shfl_xor(a, stride >> 1, 64);
-      const uint64_t pb = __shfl_xor(b, stride >> 1, 64);
+      const KeyT pa = __shfl_xor(a, stride >> 1, 64);
+      const KeyT pb = __shfl_xor(b, stride >> 1, 64);
       const bool keep_min = (((i0 & stride) == 0) == up);
       a = keep_min ? (a < pa ? a : pa) : (a < pa ? pa : a);
       b = keep_min ? (b < pb ? b : pb) : (b < pb ? pb : b);
     }
     if ((a > b) == up) {
-      const uint64_t t = a;
+      const KeyT t = a;
       a = b;
       b = t;
     }
@@ -91,8 +95,10 @@ struct ChunkArgs {
   int T;
 };
 
+template <typename KeyT>
 __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
-  __shared__ uint64_t s_key[kChunk];
+  constexpr KeyT kNoKey = (KeyT)~(KeyT)0;
+  __shared__ KeyT s_key[kChunk];
   __shared__ float s_w[kChunk];
   __shared__ float s_wz[kChunk];
   __shared__ uint32_t s_seg[kChunk];   // (tile << 2*kTileLog | local) of record r
@@ -108,7 +114,7 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
   for (int t = tid; t < a.T; t += kNT1) drow[t] = 0u;
 
   // ---- per-point decisions; thread t takes points t and t + kNT1
-  uint64_t key[2];
+  KeyT key[2];
   int nmine = 0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -135,7 +141,8 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
         s_wz[p] = w * e.zm;
         const uint32_t tile = (uint32_t)((iy >> kTileLog) * a.tiles_x + (ix >> kTileLog));
         const uint32_t local = (uint32_t)(((iy & (kTile - 1)) << kTileLog) | (ix & (kTile - 1)));
-        key[j] = ((uint64_t)tile << (2 * kTileLog + 12)) | ((uint64_t)local << 12) | (uint64_t)p;
+        const KeyT seg = ((KeyT)tile << kSegBits) | (KeyT)local;
+        key[j] = (seg << kPBits) | (KeyT)p;
         ++nmine;
       }
     }
@@ -160,7 +167,7 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int q = 2 * tid + j;
-    const bool h = q < nacc && (q == 0 || (s_key[q - 1] >> 12) != (s_key[q] >> 12));
+    const bool h = q < nacc && (q == 0 || (s_key[q - 1] >> kPBits) != (s_key[q] >> kPBits));
     hpos[j] = h ? q : -1;
     heads += h ? 1 : 0;
   }
@@ -191,7 +198,7 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
     for (int j = 0; j < 2; ++j) {
       const int q = 2 * tid + j;
       if (q < nacc) {
-        const int p = (int)(s_key[q] & 0xFFF);
+        const int p = (int)(s_key[q] & (KeyT)(kChunk - 1));
         s_vw[q] = s_w[p];
         s_vwz[q] = s_wz[p];
       }
@@ -241,12 +248,12 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
   for (int j = 0; j < 2; ++j) {
     if (hpos[j] < 0) continue;
     const int q = hpos[j];
-    const uint64_t sk = s_key[q] >> 12;
+    const uint32_t sk = (uint32_t)(s_key[q] >> kPBits);
     const int64_t o = base + r;
     a.s.rec_local[o] = (uint16_t)(sk & (kTileCells - 1));
     a.s.rec_w[o] = s_vw[q];
     a.s.rec_wz[o] = s_vwz[q];
-    s_seg[r] = (uint32_t)sk;
+    s_seg[r] = sk;
     ++r;
   }
   __syncthreads();
@@ -351,19 +358,26 @@ __global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
         u_wz[p] = a.s.rec_wz[idx];
       }
       __syncthreads();
-      // chunk by chunk: a chunk holds at most one partial per cell, so its
-      // partials are added to the cells in parallel; chunks go in order
-      for (int g = g0; g < g1; ++g) {
-        const int p0 = (int)(e_pre[g] - pbase);
-        const int p1 = (int)(e_pre[g + 1] - pbase);
-        for (int p = p0 + tid; p < p1; p += kNT2) {
-          const int l = u_l[p];
-          acc_w[l] = acc_w[l] + u_w[p];
-          acc_wz[l] = acc_wz[l] + u_wz[p];
-          hit[l] = 1;
+      // chunk by chunk.  A chunk holds at most one partial per cell, and wave w
+      // owns the cells l with l % 4 == w: each wave walks every chunk segment in
+      // chunk order and adds its own cells' partials.  Program order within the
+      // wave keeps chunk order, so no block barrier is needed between chunks.
+      {
+        const int wid = tid >> 6;
+        const int lane = tid & 63;
+        for (int g = g0; g < g1; ++g) {
+          const int p0 = (int)(e_pre[g] - pbase);
+          const int p1 = (int)(e_pre[g + 1] - pbase);
+          for (int p = p0 + lane; p < p1; p += 64) {
+            const int l = u_l[p];
+            if ((l & (kNT2 / 64 - 1)) != wid) continue;
+            acc_w[l] = acc_w[l] + u_w[p];
+            acc_wz[l] = acc_wz[l] + u_wz[p];
+            hit[l] = 1;
+          }
         }
-        __syncthreads();
       }
+      __syncthreads();
       g0 = g1;
     }
   }
@@ -439,7 +453,10 @@ hipError_t launch_fuse(const float* x, const float* y, const float* z, int64_t n
   a1.s = s;
   a1.tiles_x = tx;
   a1.T = T;
-  hipLaunchKernelGGL(k_fuse_chunk, dim3(B), dim3(kNT1), 0, stream, a1);
+  if ((int64_t)T * kTileCells <= kMaxCells32)
+    hipLaunchKernelGGL(k_fuse_chunk<uint32_t>, dim3(B), dim3(kNT1), 0, stream, a1);
+  else
+    hipLaunchKernelGGL(k_fuse_chunk<uint64_t>, dim3(B), dim3(kNT1), 0, stream, a1);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   TileArgs a2;

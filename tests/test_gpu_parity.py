@@ -138,6 +138,26 @@ def test_fuse_ragged_tiles_spread(dev):
     m.close()
 
 
+def test_fuse_large_map_wide_keys(dev):
+    """A map of more than 2^21 cells (sort keys of 64 bits)."""
+    _say("fuse large map")
+    rng = np.random.default_rng(13)
+    params = dict(nx=1500, ny=1480, resolution=0.02, noise_alpha=1e-3, gate_k=3.0, min_range=0.01)
+    p = O.Params.from_dict(params)
+    m = _map(params, dev)
+    st = O.init_map(p, 0.0, 0.0, 0)
+    n = 60000
+    xs = rng.uniform(-14.9, 14.9, n).astype(F32)
+    ys = rng.uniform(-14.7, 14.7, n).astype(F32)
+    zs = (0.05 * np.cos(xs) - 1.0 + 0.01 * rng.normal(size=n)).astype(F32)
+    xs[:3000] = rng.uniform(0.0, 0.1, 3000).astype(F32)      # a dense corner
+    ys[:3000] = rng.uniform(0.0, 0.1, 3000).astype(F32)
+    r, _, errs = _fuse_check(m, p, st, xs, ys, zs, _pose((0.0, 0.0, 1.0)), 10, dev)
+    assert r.updated.sum() > 10000
+    print("large map worst rel err", errs, flush=True)
+    m.close()
+
+
 def test_fuse_empty_and_all_dropped(dev):
     _say("fuse empty / all dropped")
     params = dict(nx=16, ny=16, resolution=0.1)
