@@ -226,6 +226,67 @@ emx_status emx_map_info(emx_map* map, int32_t* cgx, int32_t* cgy, int64_t* t0_ms
 emx_status emx_export_state(emx_map* map, void* d_dst, void* stream);
 emx_status emx_import_state(emx_map* map, const void* d_src, void* stream);
 
+
+/* ------------------------------------------------------------------ batches
+ * Many maps, each with its own frame, through the whole per-frame path in one
+ * launch sequence (one graph launch when "graph" is on, the default).
+ *   - Stages run in pipeline order for every item: move, fuse, clear, normals,
+ *     traversability.  `stages` selects them per item.
+ *   - Each item's results are bitwise identical to those of the plain calls
+ *     run in the same order on that map: the same kernel bodies do the
+ *     arithmetic, and every float32 sum has a fixed order.
+ *   - The tuning selects only launch geometry (persistent grid sizes) and the
+ *     clearing segment length.  It never changes results. */
+#define EMX_STAGE_MOVE 1u
+#define EMX_STAGE_FUSE 2u
+#define EMX_STAGE_CLEAR 4u
+#define EMX_STAGE_NORMALS 8u
+#define EMX_STAGE_TRAV 16u
+#define EMX_STAGE_ALL 31u
+#define EMX_BATCH_MAX_ITEMS 64
+
+typedef struct emx_batch emx_batch; /* opaque: tables, graphs and tuning */
+
+typedef struct {
+  emx_map* map;           /* each map at most once per batch                   */
+  emx_frame frame;        /* points for FUSE and CLEAR (as emx_fuse_points)    */
+  double cx, cy;          /* MOVE target centre (as emx_move_map)              */
+  const float* d_weights; /* TRAV weights, device float32[89]                  */
+  int32_t* d_out_cell;    /* optional, as emx_fuse_points                      */
+  uint8_t* d_out_accept;  /* optional, as emx_fuse_points                      */
+  uint8_t* d_out_cleared; /* optional, as emx_clear_visibility                 */
+  uint32_t stages;        /* EMX_STAGE_* bits                                  */
+} emx_batch_item;
+
+/* Create a batch executor.  tuning_json: NULL, or a flat JSON object whose
+ * optional integer keys are the persistent grid sizes in workgroups
+ * ("grid_move", "grid_chunk", "grid_tile", "grid_setup", "grid_march",
+ * "grid_apply", "grid_cells"), the clearing segment length "seg" (1..255)
+ * and "graph" (0 runs the launches directly instead of a cached graph).
+ * The executor allocates two pinned host tables and a capture stream. */
+emx_status emx_batch_create(const char* tuning_json, emx_batch** out);
+emx_status emx_batch_destroy(emx_batch* batch); /* waits for its last batch */
+
+/* The executor's tuning as JSON, written to buf (len bytes). */
+emx_status emx_batch_tuning(const emx_batch* batch, char* buf, size_t len);
+
+/* Device scratch bytes for this list of items (1..EMX_BATCH_MAX_ITEMS);
+ * 0 if the list is invalid. */
+size_t emx_batch_scratch_bytes(const emx_batch* batch, const emx_batch_item* items,
+                               int32_t n);
+
+/* Run the batch on `stream`.
+ *   d_scratch: >= emx_batch_scratch_bytes(), 256-aligned.  Its first bytes
+ *              hold the batch's device table.  A graph is cached per scratch
+ *              address, so keep reusing the same buffer.  A scratch buffer
+ *              must not be shared by batches in flight at the same time.
+ *   Every item is checked before anything is enqueued; on an error no map
+ *   changes.  Moves commit the maps' new centres when the call returns OK.
+ *   The call may wait on the host for the batch before last to release its
+ *   pinned table. */
+emx_status emx_pipeline_batch(emx_batch* batch, const emx_batch_item* items, int32_t n,
+                              void* d_scratch, size_t scratch_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,8 @@ import torch
 from . import _emx
 from ._emx import EmxError, make_params  # noqa: F401
 
-__all__ = ["ElevationMap", "EmxError", "make_params", "lib_path", "aligned_empty"]
+__all__ = ["ElevationMap", "PipelineBatch", "BatchEntry", "EmxError", "make_params", "lib_path",
+           "aligned_empty"]
 
 lib_path = _emx.LIB_PATH
 
@@ -159,6 +160,82 @@ class ElevationMap:
         """Overwrite the layers from host arrays (stage-synchronised testing)."""
         self.import_state(torch.from_numpy(pack_state(h, v, t_upd, valid, nrm, trav)).to(
             self.device))
+
+
+class BatchEntry:
+    """One map and its frame for PipelineBatch.run (arguments as the plain calls)."""
+
+    def __init__(self, emap: "ElevationMap", x=None, y=None, z=None, pose=None, t_ms: int = 0,
+                 center=None, weights: torch.Tensor = None, stages: int = _emx.STAGE_ALL,
+                 out_cell: torch.Tensor = None, out_accept: torch.Tensor = None,
+                 out_cleared: torch.Tensor = None):
+        self.map = emap
+        self.x, self.y, self.z = x, y, z
+        self.pose = pose
+        self.t_ms = t_ms
+        self.center = center
+        self.weights = weights
+        self.stages = stages
+        self.out_cell, self.out_accept, self.out_cleared = out_cell, out_accept, out_cleared
+
+    def item(self) -> "_emx.BatchItem":
+        it = _emx.BatchItem()
+        it.map = self.map.handle
+        if self.x is not None:
+            f, _ = self.map._frame(self.x, self.y, self.z, self.pose, self.t_ms)
+            it.frame = f
+        if self.center is not None:
+            it.cx, it.cy = float(self.center[0]), float(self.center[1])
+        elif self.stages & _emx.STAGE_MOVE:
+            raise ValueError("a move needs a centre")
+        if self.weights is not None:
+            it.d_weights = self.weights.data_ptr()
+        for name in ("out_cell", "out_accept", "out_cleared"):
+            t = getattr(self, name)
+            if t is not None:
+                setattr(it, "d_" + name, t.data_ptr())
+        it.stages = int(self.stages)
+        return it
+
+
+class PipelineBatch:
+    """Batched executor: many maps and frames through the whole path in one
+    graph launch (emx_pipeline_batch).  Owns its device scratch (torch)."""
+
+    def __init__(self, tuning: str = None, device=None):
+        self.device = _require_gpu(device)
+        self.handle = _emx.batch_create(tuning)
+        self._scratch = None
+        self._scratch_bytes = 0
+
+    @property
+    def tuning(self) -> str:
+        return _emx.batch_tuning(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _emx.batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, entries):
+        arr = _emx.make_batch_items([e.item() for e in entries])
+        n = len(entries)
+        need = _emx.batch_scratch_bytes(self.handle, arr, n)
+        if need == 0:
+            raise EmxError(_emx.EMX_EINVAL, _emx.last_error())
+        if self._scratch is None or self._scratch_bytes < need:
+            # keep one buffer, generously sized: graphs are cached per scratch address
+            size = max(need, 2 * self._scratch_bytes)
+            self._scratch = aligned_empty(size, self.device)
+            self._scratch_bytes = size
+        _emx.pipeline_batch(self.handle, arr, n, self._scratch.data_ptr(), self._scratch_bytes,
+                            _stream(self.device))
 
 
 def pack_state(h, v, t_upd, valid, nrm, trav) -> np.ndarray:

@@ -9,7 +9,7 @@ import ctypes
 import os
 import re
 from ctypes import (POINTER, Structure, byref, c_char_p, c_double, c_float, c_int32, c_int64,
-                    c_size_t, c_void_p)
+                    c_size_t, c_uint32, c_void_p, create_string_buffer)
 
 import numpy as np
 
@@ -46,6 +46,17 @@ class Frame(Structure):
                 ("pose", c_double * 12), ("t_ms", c_int64)]
 
 
+class BatchItem(Structure):
+    _fields_ = [("map", c_void_p), ("frame", Frame), ("cx", c_double), ("cy", c_double),
+                ("d_weights", c_void_p), ("d_out_cell", c_void_p), ("d_out_accept", c_void_p),
+                ("d_out_cleared", c_void_p), ("stages", c_uint32)]
+
+
+STAGE_MOVE, STAGE_FUSE, STAGE_CLEAR, STAGE_NORMALS, STAGE_TRAV = 1, 2, 4, 8, 16
+STAGE_ALL = 31
+BATCH_MAX_ITEMS = 64
+
+
 _SIGS = {
     "emx_version": (c_char_p, []),
     "emx_last_error": (c_char_p, []),
@@ -67,6 +78,12 @@ _SIGS = {
     "emx_map_info": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int64)]),
     "emx_export_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "emx_import_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "emx_batch_create": (c_int32, [c_char_p, POINTER(c_void_p)]),
+    "emx_batch_destroy": (c_int32, [c_void_p]),
+    "emx_batch_tuning": (c_int32, [c_void_p, c_char_p, c_size_t]),
+    "emx_batch_scratch_bytes": (c_size_t, [c_void_p, POINTER(BatchItem), c_int32]),
+    "emx_pipeline_batch": (c_int32, [c_void_p, POINTER(BatchItem), c_int32, c_void_p, c_size_t,
+                                     c_void_p]),
 }
 
 _lib = None
@@ -203,3 +220,35 @@ def export_state(h: int, d_dst: int, stream: int):
 
 def import_state(h: int, d_src: int, stream: int):
     check(lib().emx_import_state(c_void_p(h), c_void_p(d_src), c_void_p(stream)))
+
+
+def batch_create(tuning_json: str = None) -> int:
+    h = c_void_p()
+    check(lib().emx_batch_create(tuning_json.encode() if tuning_json else None, byref(h)))
+    return h.value
+
+
+def batch_destroy(h: int):
+    check(lib().emx_batch_destroy(c_void_p(h)))
+
+
+def batch_tuning(h: int) -> str:
+    buf = create_string_buffer(512)
+    check(lib().emx_batch_tuning(c_void_p(h), buf, 512))
+    return buf.value.decode()
+
+
+def make_batch_items(items) -> "ctypes.Array":
+    arr = (BatchItem * len(items))()
+    for k, it in enumerate(items):
+        arr[k] = it
+    return arr
+
+
+def batch_scratch_bytes(h: int, arr, n: int) -> int:
+    return lib().emx_batch_scratch_bytes(c_void_p(h), arr, n)
+
+
+def pipeline_batch(h: int, arr, n: int, d_scratch: int, nbytes: int, stream: int):
+    check(lib().emx_pipeline_batch(c_void_p(h), arr, n, c_void_p(d_scratch), nbytes,
+                                   c_void_p(stream)))

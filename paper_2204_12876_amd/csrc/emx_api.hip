@@ -1,6 +1,6 @@
-// C ABI of libemx.so: argument checks, map handles, state layout and launch
-// sequencing.  Everything device-side is enqueued on the caller's stream; the
-// library never allocates device memory.
+// C ABI of libemx.so, plain per-map calls: argument checks, map handles, state
+// layout and launch sequencing.  Everything device-side is enqueued on the
+// caller's stream; the library never allocates device memory.
 #include <math.h>
 #include <stdarg.h>
 #include <string.h>
@@ -9,16 +9,17 @@
 #include <new>
 #include <string>
 
-#include "emx.h"
-#include "emx_kernels.h"
+#include "emx_host.h"
 
-using namespace emx;
+namespace emx {
 
 namespace {
-
 thread_local std::string g_err;
+constexpr int kMaxSide = 16384;
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+}  // namespace
 
-emx_status fail(emx_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 emx_status fail(emx_status code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -29,15 +30,11 @@ emx_status fail(emx_status code, const char* fmt, ...) {
   return code;
 }
 
+const char* last_error_text() { return g_err.c_str(); }
+
 emx_status hip_fail(hipError_t e, const char* what) {
   return fail(EMX_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
-
-constexpr int kMaxSide = 16384;
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 
 emx_status check_params(const emx_params* p) {
   if (!p) return fail(EMX_EINVAL, "params is NULL");
@@ -105,31 +102,16 @@ size_t set_layout(const emx_params& p, char* base, Layers* L) {
   return 7 * l4 + 2 * l1 + lb;
 }
 
-}  // namespace
+int tiles_of(const emx_params& p) { return tiles_x_of(p.nx) * tiles_y_of(p.ny); }
 
-// Per-map control words after the two buffer sets: the clearing sub-queue
-// counters (64 counters, 128 bytes apart).
-constexpr int kCtlWords = 64 * 32;
-
-struct emx_map {
-  emx_params p;
-  Consts c;
-  int64_t cgx, cgy;
-  int64_t t0;
-  char* state;
-  size_t set_bytes;
-  int cur;
-  Layers sets[2];
-  uint32_t* ctl;
-  int march_grid;
-};
-
-namespace {
-
-emx_status check_map(const emx_map* m) {
-  if (!m) return fail(EMX_EINVAL, "map is NULL");
-  if (!m->state) return fail(EMX_ESTATE, "map has no state");
-  return EMX_OK;
+// A persistent grid of per_cu workgroups per compute unit of the current device.
+int persistent_grid(int per_cu) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return per_cu * cus;
 }
 
 bool center_cell(double c, double r, int64_t* out) {
@@ -139,22 +121,9 @@ bool center_cell(double c, double r, int64_t* out) {
   return true;
 }
 
-emx_status make_pose(const emx_map* m, const emx_frame* f, Pose32* P, int32_t* t_now) {
-  for (int k = 0; k < 12; ++k)
-    if (!isfinite(f->pose[k])) return fail(EMX_EINVAL, "pose has a non-finite entry");
-  const double ox = (double)(m->cgx - m->p.nx / 2) * m->p.resolution;
-  const double oy = (double)(m->cgy - m->p.ny / 2) * m->p.resolution;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) P->R[i * 3 + j] = (float)f->pose[i * 4 + j];
-  P->t[0] = (float)(f->pose[3] - ox);
-  P->t[1] = (float)(f->pose[7] - oy);
-  P->t[2] = (float)f->pose[11];
-  if (!isfinite(P->t[0]) || !isfinite(P->t[1]) || !isfinite(P->t[2]))
-    return fail(EMX_EINVAL, "map-local translation overflows float32");
-  const int64_t dt = f->t_ms - m->t0;
-  if (dt < 0 || dt > 2147483647LL)
-    return fail(EMX_EINVAL, "t_ms - t0 must lie in [0, 2^31) (got %lld)", (long long)dt);
-  *t_now = (int32_t)dt;
+emx_status check_map(const emx_map* m) {
+  if (!m) return fail(EMX_EINVAL, "map is NULL");
+  if (!m->state) return fail(EMX_ESTATE, "map has no state");
   return EMX_OK;
 }
 
@@ -165,25 +134,62 @@ emx_status check_frame(const emx_frame* f) {
   return EMX_OK;
 }
 
-int tiles_of(const emx_params& p) { return tiles_x_of(p.nx) * tiles_y_of(p.ny); }
-
-// Persistent grids: a few workgroups per compute unit of the current device.
-int march_grid_for_device() {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus <= 0)
-    cus = 256;
-  return 8 * cus;
+emx_status make_item(const emx_map* m, const emx_frame* f, Item* it) {
+  memset(it, 0, sizeof(Item));
+  it->c = m->c;
+  it->L = m->sets[m->cur];
+  it->Lsrc = m->sets[m->cur];
+  it->tiles_x = tiles_x_of(m->p.nx);
+  it->T = tiles_of(m->p);
+  it->bl = block_log_of(m->p.nx, m->p.ny);
+  it->bx = blocks_of(m->p.nx, it->bl);
+  it->by = blocks_of(m->p.ny, it->bl);
+  it->nb = it->bx * it->by;
+  it->nprep = (it->nb + 3) / 4;
+  if (!f) return EMX_OK;
+  for (int k = 0; k < 12; ++k)
+    if (!isfinite(f->pose[k])) return fail(EMX_EINVAL, "pose has a non-finite entry");
+  const double ox = (double)(m->cgx - m->p.nx / 2) * m->p.resolution;
+  const double oy = (double)(m->cgy - m->p.ny / 2) * m->p.resolution;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) it->P.R[i * 3 + j] = (float)f->pose[i * 4 + j];
+  it->P.t[0] = (float)(f->pose[3] - ox);
+  it->P.t[1] = (float)(f->pose[7] - oy);
+  it->P.t[2] = (float)f->pose[11];
+  if (!isfinite(it->P.t[0]) || !isfinite(it->P.t[1]) || !isfinite(it->P.t[2]))
+    return fail(EMX_EINVAL, "map-local translation overflows float32");
+  const int64_t dt = f->t_ms - m->t0;
+  if (dt < 0 || dt > 2147483647LL)
+    return fail(EMX_EINVAL, "t_ms - t0 must lie in [0, 2^31) (got %lld)", (long long)dt);
+  it->t_now = (int32_t)dt;
+  it->x = f->x;
+  it->y = f->y;
+  it->z = f->z;
+  it->n = f->n;
+  it->B = (int)((f->n + kChunk - 1) / kChunk);
+  return EMX_OK;
 }
 
-}  // namespace
+bool plan_move(const emx_map* m, double cx, double cy, int64_t* ngx, int64_t* ngy, int* sx,
+               int* sy) {
+  if (!center_cell(cx, m->p.resolution, ngx) || !center_cell(cy, m->p.resolution, ngy))
+    return false;
+  const int64_t dx = *ngx - m->cgx, dy = *ngy - m->cgy;
+  const int64_t lim = (int64_t)kMaxSide + 1;
+  *sx = (int)(dx > lim ? lim : (dx < -lim ? -lim : dx));
+  *sy = (int)(dy > lim ? lim : (dy < -lim ? -lim : dy));
+  return true;
+}
+
+}  // namespace emx
+
+using namespace emx;
 
 extern "C" {
 
-const char* emx_version(void) { return "emx 0.1.0 gfx950"; }
+const char* emx_version(void) { return "emx 0.2.0 gfx950"; }
 
-const char* emx_last_error(void) { return g_err.c_str(); }
+const char* emx_last_error(void) { return last_error_text(); }
 
 emx_status emx_params_check(const emx_params* params) { return check_params(params); }
 
@@ -199,7 +205,7 @@ size_t emx_scratch_bytes(const emx_params* params, int64_t max_points) {
     return 0;
   }
   const size_t f = fuse_scratch_layout(max_points, tiles_of(*params), nullptr, nullptr);
-  const size_t c = clear_scratch_layout(max_points, nullptr, nullptr);
+  const size_t c = clear_scratch_layout(max_points, kDefaultSeg, nullptr, nullptr);
   return f > c ? f : c;
 }
 
@@ -234,7 +240,7 @@ emx_status emx_init_map(const emx_params* params, double cx, double cy, int64_t 
   set_layout(*params, m->state + m->set_bytes, &m->sets[1]);
   m->cur = 0;
   m->ctl = (uint32_t*)(m->state + 2 * m->set_bytes);
-  m->march_grid = march_grid_for_device();
+  m->march_grid = persistent_grid(8);
   hipError_t e = launch_fill_prior(m->c, m->sets[0], m->ctl, kCtlWords, (hipStream_t)stream);
   if (e != hipSuccess) {
     delete m;
@@ -254,15 +260,18 @@ emx_status emx_move_map(emx_map* m, double cx, double cy, void* stream) {
   emx_status s = check_map(m);
   if (s != EMX_OK) return s;
   int64_t ngx, ngy;
-  if (!center_cell(cx, m->p.resolution, &ngx) || !center_cell(cy, m->p.resolution, &ngy))
+  int sx, sy;
+  if (!plan_move(m, cx, cy, &ngx, &ngy, &sx, &sy))
     return fail(EMX_EINVAL, "map centre out of range");
-  int64_t sx = ngx - m->cgx, sy = ngy - m->cgy;
   if (sx == 0 && sy == 0) return EMX_OK;
-  const int64_t lim = (int64_t)kMaxSide + 1;
-  const int isx = (int)(sx > lim ? lim : (sx < -lim ? -lim : sx));
-  const int isy = (int)(sy > lim ? lim : (sy < -lim ? -lim : sy));
   const int nxt = 1 - m->cur;
-  hipError_t e = launch_move(m->c, m->sets[m->cur], m->sets[nxt], isx, isy, (hipStream_t)stream);
+  Item it;
+  make_item(m, nullptr, &it);
+  it.Lsrc = m->sets[m->cur];
+  it.L = m->sets[nxt];
+  it.sx = sx;
+  it.sy = sy;
+  hipError_t e = launch_move(it, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "move_map");
   m->cur = nxt;
   m->cgx = ngx;
@@ -275,21 +284,20 @@ emx_status emx_fuse_points(emx_map* m, const emx_frame* f, void* d_scratch, size
   emx_status s = check_map(m);
   if (s != EMX_OK) return s;
   if ((s = check_frame(f)) != EMX_OK) return s;
-  Pose32 P;
-  int32_t t_now;
-  if ((s = make_pose(m, f, &P, &t_now)) != EMX_OK) return s;
+  Item it;
+  if ((s = make_item(m, f, &it)) != EMX_OK) return s;
   if (f->n == 0) return EMX_OK;
-  const int T = tiles_of(m->p);
-  const size_t need = fuse_scratch_layout(f->n, T, nullptr, nullptr);
+  const size_t need = fuse_scratch_layout(f->n, it.T, nullptr, nullptr);
   if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
   if (((uintptr_t)d_scratch & 255u) != 0)
     return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
   if (scratch_bytes < need)
     return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
-  FuseScratch fs;
-  fuse_scratch_layout(f->n, T, (char*)d_scratch, &fs);
-  hipError_t e = launch_fuse(f->x, f->y, f->z, f->n, P, m->c, m->sets[m->cur], t_now, d_out_cell,
-                             d_out_accept, fs, (hipStream_t)stream);
+  fuse_scratch_layout(f->n, it.T, (char*)d_scratch, &it.fs);
+  it.out_cell = d_out_cell;
+  it.out_accept = d_out_accept;
+  it.stages = kStageFuse;
+  hipError_t e = launch_fuse(it, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "fuse_points");
   return EMX_OK;
 }
@@ -299,21 +307,23 @@ emx_status emx_clear_visibility(emx_map* m, const emx_frame* f, void* d_scratch,
   emx_status s = check_map(m);
   if (s != EMX_OK) return s;
   if ((s = check_frame(f)) != EMX_OK) return s;
-  Pose32 P;
-  int32_t t_now;
-  if ((s = make_pose(m, f, &P, &t_now)) != EMX_OK) return s;
-  ClearScratch cs = {nullptr, nullptr, nullptr};
+  Item it;
+  if ((s = make_item(m, f, &it)) != EMX_OK) return s;
   if (f->n > 0) {
-    const size_t need = clear_scratch_layout(f->n, nullptr, nullptr);
+    const size_t need = clear_scratch_layout(f->n, kDefaultSeg, nullptr, nullptr);
     if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
     if (((uintptr_t)d_scratch & 255u) != 0)
       return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
     if (scratch_bytes < need)
       return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
-    clear_scratch_layout(f->n, (char*)d_scratch, &cs);
+    clear_scratch_layout(f->n, kDefaultSeg, (char*)d_scratch, &it.cq);
   }
-  hipError_t e = launch_clear(f->x, f->y, f->z, f->n, P, m->c, m->sets[m->cur], t_now, cs,
-                              m->ctl, d_out_cleared, m->march_grid, (hipStream_t)stream);
+  it.cq.ray_item = nullptr;
+  it.cq.counter = m->ctl;
+  it.cq.seg = kDefaultSeg;
+  it.out_cleared = d_out_cleared;
+  it.stages = kStageClear;
+  hipError_t e = launch_clear(it, m->march_grid, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "clear_visibility");
   return EMX_OK;
 }
@@ -321,7 +331,10 @@ emx_status emx_clear_visibility(emx_map* m, const emx_frame* f, void* d_scratch,
 emx_status emx_compute_normals(emx_map* m, void* stream) {
   emx_status s = check_map(m);
   if (s != EMX_OK) return s;
-  hipError_t e = launch_normals(m->c, m->sets[m->cur], (hipStream_t)stream);
+  Item it;
+  make_item(m, nullptr, &it);
+  it.stages = kStageNormals;
+  hipError_t e = launch_normals(it, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "compute_normals");
   return EMX_OK;
 }
@@ -330,7 +343,11 @@ emx_status emx_traversability(emx_map* m, const float* d_weights, void* stream) 
   emx_status s = check_map(m);
   if (s != EMX_OK) return s;
   if (!d_weights) return fail(EMX_EINVAL, "d_weights is NULL");
-  hipError_t e = launch_trav(m->c, m->sets[m->cur], d_weights, (hipStream_t)stream);
+  Item it;
+  make_item(m, nullptr, &it);
+  it.w = d_weights;
+  it.stages = kStageTrav;
+  hipError_t e = launch_trav(it, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "traversability");
   return EMX_OK;
 }

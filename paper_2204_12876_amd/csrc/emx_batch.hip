@@ -1,0 +1,369 @@
+// Batched pipeline: many maps, each with its own frame, through every stage
+// in one launch sequence.
+//
+// The host fills a Batch table in pinned memory:
+//   - each item's state pointers, geometry and constants;
+//   - per stage, the prefix of work units over the items.
+// One graph then runs:
+//   - a copy of the table into the caller's scratch;
+//   - one persistent launch per stage: move, fusion pass 1, fusion pass 2,
+//     clearing setup, march and apply, then normals + traversability.
+// Every launch has a fixed grid and finds its work in the table, so the
+// captured graph is replayed for every batch that uses the same scratch buffer.
+// Two pinned tables alternate: the host fills one while the other may still
+// be read by the previous batch's copy.
+//
+// The work of each item runs through the same kernel bodies as the plain
+// calls, so every map's results equal those of the plain calls bit for bit.
+#include <stdlib.h>
+#include <string.h>
+
+#include <cstdio>
+#include <new>
+
+#include "emx_host.h"
+
+using namespace emx;
+
+namespace {
+
+struct Tuning {
+  int grid_move = 1024;
+  int grid_chunk = 512;
+  int grid_tile = 512;
+  int grid_setup = 2048;
+  int grid_march = 2048;
+  int grid_apply = 1024;
+  int grid_cells = 1024;
+  int seg = kDefaultSeg;
+  int graph = 1;
+};
+
+// Value of "key": <number> in a flat JSON object; false if absent.
+bool json_int(const char* js, const char* key, int* out) {
+  char pat[64];
+  snprintf(pat, sizeof pat, "\"%s\"", key);
+  const char* p = strstr(js, pat);
+  if (!p) return false;
+  p = strchr(p + strlen(pat), ':');
+  if (!p) return false;
+  char* end = nullptr;
+  const long v = strtol(p + 1, &end, 10);
+  if (end == p + 1) return false;
+  *out = (int)v;
+  return true;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct GraphKey {
+  void* scratch;
+  int key64;
+  int buf;
+};
+
+}  // namespace
+
+struct emx_batch {
+  Tuning tune;
+  Batch* host[2];      // pinned tables, alternating
+  hipEvent_t done[2];  // last launch that read host[i]
+  bool used[2];
+  int next;
+  hipStream_t cap;     // private stream for graph capture
+  static constexpr int kCache = 8;
+  GraphKey keys[kCache];
+  hipGraphExec_t execs[kCache];
+  int ncache;
+};
+
+namespace {
+
+emx_status check_items(const emx_batch_item* items, int32_t n) {
+  if (n < 1 || n > kMaxItems) return fail(EMX_EINVAL, "batch size must lie in [1, %d]", kMaxItems);
+  if (!items) return fail(EMX_EINVAL, "items is NULL");
+  for (int32_t i = 0; i < n; ++i) {
+    emx_status s = check_map(items[i].map);
+    if (s != EMX_OK) return s;
+    if (items[i].stages & ~(uint32_t)EMX_STAGE_ALL)
+      return fail(EMX_EINVAL, "item %d: unknown stage bits", i);
+    if ((items[i].stages & (EMX_STAGE_FUSE | EMX_STAGE_CLEAR)) &&
+        (s = check_frame(&items[i].frame)) != EMX_OK)
+      return s;
+    if ((items[i].stages & EMX_STAGE_TRAV) && !items[i].d_weights)
+      return fail(EMX_EINVAL, "item %d: traversability needs weights", i);
+    for (int32_t j = 0; j < i; ++j)
+      if (items[j].map == items[i].map) return fail(EMX_EINVAL, "map appears twice in a batch");
+  }
+  return EMX_OK;
+}
+
+int64_t frame_points(const emx_batch_item& b) {
+  return (b.stages & (EMX_STAGE_FUSE | EMX_STAGE_CLEAR)) ? b.frame.n : 0;
+}
+
+// Scratch layout: the device table, each item's fusion scratch, then one
+// clearing queue shared by the batch.
+size_t batch_layout(const emx_batch_item* items, int32_t n, int seg, char* base, Batch* tab) {
+  size_t off = align256(sizeof(Batch));
+  int64_t rays = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t np = frame_points(items[i]);
+    if (items[i].stages & EMX_STAGE_FUSE) {
+      const size_t f = fuse_scratch_layout(np, tiles_of(items[i].map->p), nullptr, nullptr);
+      if (tab && base)
+        fuse_scratch_layout(np, tiles_of(items[i].map->p), base + off, &tab->items[i].fs);
+      off = align256(off + f);
+    }
+    if (tab) tab->items[i].ray_base = rays;
+    if (items[i].stages & EMX_STAGE_CLEAR) rays += np;
+  }
+  ClearQueue cq;
+  const size_t c = clear_scratch_layout(rays, seg, base ? base + off : nullptr, &cq);
+  if (tab && base)
+    for (int32_t i = 0; i < n; ++i) {
+      tab->items[i].cq = cq;
+      tab->items[i].cq.counter = nullptr;  // set once the device table's address is known
+    }
+  return off + c;
+}
+
+}  // namespace
+
+extern "C" {
+
+emx_status emx_batch_create(const char* tuning_json, emx_batch** out) {
+  if (!out) return fail(EMX_EINVAL, "out is NULL");
+  emx_batch* b = new (std::nothrow) emx_batch;
+  if (!b) return fail(EMX_ENOMEM, "host allocation failed");
+  b->tune = Tuning();
+  b->tune.grid_march = persistent_grid(8);
+  b->tune.grid_setup = persistent_grid(8);
+  if (tuning_json) {
+    json_int(tuning_json, "grid_move", &b->tune.grid_move);
+    json_int(tuning_json, "grid_chunk", &b->tune.grid_chunk);
+    json_int(tuning_json, "grid_tile", &b->tune.grid_tile);
+    json_int(tuning_json, "grid_setup", &b->tune.grid_setup);
+    json_int(tuning_json, "grid_march", &b->tune.grid_march);
+    json_int(tuning_json, "grid_apply", &b->tune.grid_apply);
+    json_int(tuning_json, "grid_cells", &b->tune.grid_cells);
+    json_int(tuning_json, "seg", &b->tune.seg);
+    json_int(tuning_json, "graph", &b->tune.graph);
+  }
+  const Tuning& t = b->tune;
+  const int grids[] = {t.grid_move, t.grid_chunk, t.grid_tile, t.grid_setup,
+                       t.grid_march, t.grid_apply, t.grid_cells};
+  for (int g : grids)
+    if (g < 1 || g > 65536) {
+      delete b;
+      return fail(EMX_EINVAL, "tuning: grid sizes must lie in [1, 65536]");
+    }
+  if (t.seg < 1 || t.seg > 255) {
+    delete b;
+    return fail(EMX_EINVAL, "tuning: seg must lie in [1, 255]");
+  }
+  b->ncache = 0;
+  b->next = 0;
+  b->host[0] = b->host[1] = nullptr;
+  b->cap = nullptr;
+  for (int i = 0; i < 2; ++i) {
+    b->used[i] = false;
+    b->done[i] = nullptr;
+    hipError_t e = hipHostMalloc((void**)&b->host[i], sizeof(Batch), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      emx_batch_destroy(b);
+      return hip_fail(e, "batch_create");
+    }
+  }
+  hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    emx_batch_destroy(b);
+    return hip_fail(e, "batch_create");
+  }
+  *out = b;
+  return EMX_OK;
+}
+
+emx_status emx_batch_destroy(emx_batch* b) {
+  if (!b) return fail(EMX_EINVAL, "batch is NULL");
+  for (int i = 0; i < 2; ++i) {
+    if (b->done[i]) {
+      (void)hipEventSynchronize(b->done[i]);
+      (void)hipEventDestroy(b->done[i]);
+    }
+    if (b->host[i]) (void)hipHostFree(b->host[i]);
+  }
+  for (int i = 0; i < b->ncache; ++i) (void)hipGraphExecDestroy(b->execs[i]);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+  return EMX_OK;
+}
+
+emx_status emx_batch_tuning(const emx_batch* b, char* buf, size_t len) {
+  if (!b || !buf) return fail(EMX_EINVAL, "NULL argument");
+  const Tuning& t = b->tune;
+  const int w = snprintf(buf, len,
+                         "{\"grid_move\": %d, \"grid_chunk\": %d, \"grid_tile\": %d, "
+                         "\"grid_setup\": %d, \"grid_march\": %d, \"grid_apply\": %d, "
+                         "\"grid_cells\": %d, \"seg\": %d, \"graph\": %d}",
+                         t.grid_move, t.grid_chunk, t.grid_tile, t.grid_setup, t.grid_march,
+                         t.grid_apply, t.grid_cells, t.seg, t.graph);
+  if (w < 0 || (size_t)w >= len) return fail(EMX_ENOMEM, "buffer too small");
+  return EMX_OK;
+}
+
+size_t emx_batch_scratch_bytes(const emx_batch* b, const emx_batch_item* items, int32_t n) {
+  if (!b || check_items(items, n) != EMX_OK) return 0;
+  return batch_layout(items, n, b->tune.seg, nullptr, nullptr);
+}
+
+emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t n,
+                              void* d_scratch, size_t scratch_bytes, void* stream) {
+  if (!b) return fail(EMX_EINVAL, "batch is NULL");
+  emx_status s = check_items(items, n);
+  if (s != EMX_OK) return s;
+  if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
+  if (((uintptr_t)d_scratch & 255u) != 0)
+    return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
+  const size_t need = batch_layout(items, n, b->tune.seg, nullptr, nullptr);
+  if (scratch_bytes < need)
+    return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
+
+  // ---- validate every frame before any map is touched
+  for (int32_t i = 0; i < n; ++i) {
+    const emx_batch_item& bi = items[i];
+    int64_t ngx, ngy;
+    int sx, sy;
+    if ((bi.stages & EMX_STAGE_MOVE) && !plan_move(bi.map, bi.cx, bi.cy, &ngx, &ngy, &sx, &sy))
+      return fail(EMX_EINVAL, "item %d: map centre out of range", i);
+  }
+
+  // ---- fill the host table (wait until the copy that last read it is done)
+  const int buf = b->next;
+  b->next ^= 1;
+  if (b->used[buf]) {
+    hipError_t e = hipEventSynchronize(b->done[buf]);
+    if (e != hipSuccess) return hip_fail(e, "pipeline_batch");
+  }
+  Batch* tab = b->host[buf];
+  memset(tab, 0, sizeof(Batch));
+  tab->n = n;
+  Batch* d_tab = (Batch*)d_scratch;
+  bool key64 = false;
+  // plan every item on copies of the map geometry: no map changes until the
+  // whole batch has been checked
+  int cur[kMaxItems];
+  int64_t cgx[kMaxItems], cgy[kMaxItems];
+  for (int32_t i = 0; i < n; ++i) {
+    const emx_batch_item& bi = items[i];
+    emx_map tmp = *bi.map;
+    Item& it = tab->items[i];
+    int sx = 0, sy = 0;
+    if (bi.stages & EMX_STAGE_MOVE) {
+      int64_t ngx, ngy;
+      plan_move(bi.map, bi.cx, bi.cy, &ngx, &ngy, &sx, &sy);
+      if (sx != 0 || sy != 0) {
+        tmp.cur = 1 - tmp.cur;
+        tmp.cgx = ngx;
+        tmp.cgy = ngy;
+      }
+    }
+    const bool pts = (bi.stages & (EMX_STAGE_FUSE | EMX_STAGE_CLEAR)) != 0;
+    s = make_item(&tmp, pts ? &bi.frame : nullptr, &it);
+    if (s != EMX_OK) return fail(s, "item %d: %s", i, last_error_text());
+    it.Lsrc = bi.map->sets[bi.map->cur];
+    it.sx = sx;
+    it.sy = sy;
+    it.stages = bi.stages;
+    it.w = bi.d_weights;
+    it.out_cell = bi.d_out_cell;
+    it.out_accept = bi.d_out_accept;
+    it.out_cleared = bi.d_out_cleared;
+    it.index = i;
+    cur[i] = tmp.cur;
+    cgx[i] = tmp.cgx;
+    cgy[i] = tmp.cgy;
+    if ((bi.stages & EMX_STAGE_FUSE) && it.n > 0 && fuse_needs_key64(it.T)) key64 = true;
+  }
+  batch_layout(items, n, b->tune.seg, (char*)d_scratch, tab);
+  tab->key64 = key64 ? 1 : 0;
+  for (int32_t i = 0; i < n; ++i) {
+    Item& it = tab->items[i];
+    it.cq.counter = d_tab->counter;
+    it.cq.seg = b->tune.seg;
+    const uint32_t st = it.stages;
+    const int64_t C = (int64_t)it.c.nx * it.c.ny;
+    const bool moved = (st & EMX_STAGE_MOVE) && (it.sx != 0 || it.sy != 0);
+    const bool fuse = (st & EMX_STAGE_FUSE) && it.n > 0;
+    const bool clear = (st & EMX_STAGE_CLEAR) != 0;
+    tab->off[kBMove][i + 1] = tab->off[kBMove][i] + (moved ? move_units(it.c.nx, it.c.ny) : 0);
+    tab->off[kBChunk][i + 1] = tab->off[kBChunk][i] + (fuse ? it.B : 0);
+    tab->off[kBTile][i + 1] = tab->off[kBTile][i] + (fuse ? it.T : 0);
+    tab->off[kBSetup][i + 1] =
+        tab->off[kBSetup][i] + (clear && it.n > 0 ? clear_setup_units(it.n, it.nprep) : 0);
+    tab->off[kBApply][i + 1] = tab->off[kBApply][i] + (clear ? clear_apply_units(C) : 0);
+    tab->off[kBCells][i + 1] =
+        tab->off[kBCells][i] +
+        ((st & (EMX_STAGE_NORMALS | EMX_STAGE_TRAV)) ? cells_units(it.c.nx, it.c.ny) : 0);
+  }
+
+  // ---- enqueue: a cached graph, or the same sequence directly
+  hipStream_t st = (hipStream_t)stream;
+  const Tuning& t = b->tune;
+  auto enqueue = [&](hipStream_t q) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(d_tab, tab, sizeof(Batch), hipMemcpyHostToDevice, q);
+    if (e == hipSuccess) e = launch_move_batch(d_tab, t.grid_move, q);
+    if (e == hipSuccess) e = launch_fuse_batch(d_tab, key64, t.grid_chunk, t.grid_tile, q);
+    if (e == hipSuccess) e = launch_clear_batch(d_tab, t.grid_setup, t.grid_march, t.grid_apply, q);
+    if (e == hipSuccess) e = launch_cells_batch(d_tab, t.grid_cells, q);
+    return e;
+  };
+  hipError_t e = hipSuccess;
+  if (t.graph) {
+    int slot = -1;
+    for (int k = 0; k < b->ncache; ++k)
+      if (b->keys[k].scratch == d_scratch && b->keys[k].key64 == (int)key64 &&
+          b->keys[k].buf == buf)
+        slot = k;
+    if (slot < 0) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t ex = nullptr;
+      e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t e1 = enqueue(b->cap);
+        e = hipStreamEndCapture(b->cap, &g);
+        if (e1 != hipSuccess) e = e1;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(e, "pipeline_batch: graph capture");
+      if (b->ncache == emx_batch::kCache) {
+        (void)hipGraphExecDestroy(b->execs[0]);
+        for (int k = 1; k < b->ncache; ++k) {
+          b->keys[k - 1] = b->keys[k];
+          b->execs[k - 1] = b->execs[k];
+        }
+        --b->ncache;
+      }
+      slot = b->ncache++;
+      b->keys[slot] = GraphKey{d_scratch, (int)key64, buf};
+      b->execs[slot] = ex;
+    }
+    e = hipGraphLaunch(b->execs[slot], st);
+  } else {
+    e = enqueue(st);
+  }
+  if (e == hipSuccess) e = hipEventRecord(b->done[buf], st);
+  if (e != hipSuccess) return hip_fail(e, "pipeline_batch");
+  b->used[buf] = true;
+  // the moves are enqueued: commit the maps' new geometry
+  for (int32_t i = 0; i < n; ++i) {
+    items[i].map->cur = cur[i];
+    items[i].map->cgx = cgx[i];
+    items[i].map->cgy = cgy[i];
+  }
+  return EMX_OK;
+}
+
+}  // extern "C"

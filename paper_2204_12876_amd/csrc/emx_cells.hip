@@ -3,6 +3,7 @@
 // The stencils (normals, traversability) stage a 34x34 halo tile of heights
 // and validity in LDS.  Each 32x8 workgroup then produces a 32x32 output tile,
 // four rows per thread, so every height is read from HBM about 1.13 times.
+// The batched launch computes normals and traversability from one staged tile.
 #include "emx_kernels.h"
 
 namespace emx {
@@ -37,43 +38,42 @@ __global__ __launch_bounds__(kNTf) void k_fill_prior(FillArgs a) {
 }
 
 // ------------------------------------------------------------------------ move
-struct MoveArgs {
-  Consts c;
-  Layers src;
-  Layers dst;
-  int sx, sy;
-};
+constexpr int kMoveW = 64;  // a move unit is 64 x 4 cells
+constexpr int kMoveH = kNTf / kMoveW;
 
 // dst(ix, iy) <- src(ix + sx, iy + sy), or the prior where that is outside.
-__global__ __launch_bounds__(kNTf) void k_move(MoveArgs a) {
-  const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (ix >= a.c.nx || iy >= a.c.ny) return;
-  const int64_t o = (int64_t)iy * a.c.nx + ix;
-  const int jx = ix + a.sx;
-  const int jy = iy + a.sy;
-  if (jx >= 0 && jx < a.c.nx && jy >= 0 && jy < a.c.ny) {
-    const int64_t s = (int64_t)jy * a.c.nx + jx;
-    a.dst.h[o] = a.src.h[s];
-    a.dst.v[o] = a.src.v[s];
-    a.dst.t[o] = a.src.t[s];
-    a.dst.nx[o] = a.src.nx[s];
-    a.dst.ny[o] = a.src.ny[s];
-    a.dst.nz[o] = a.src.nz[s];
-    a.dst.trav[o] = a.src.trav[s];
-    a.dst.valid[o] = a.src.valid[s];
+__device__ __forceinline__ void move_body(const Item& it, int64_t unit) {
+  const int ux = blocks_of(it.c.nx, 6);
+  const int ix = (int)(unit % ux) * kMoveW + (threadIdx.x & (kMoveW - 1));
+  const int iy = (int)(unit / ux) * kMoveH + (threadIdx.x / kMoveW);
+  if (ix >= it.c.nx || iy >= it.c.ny) return;
+  const Layers& src = it.Lsrc;
+  const Layers& dst = it.L;
+  const int64_t o = (int64_t)iy * it.c.nx + ix;
+  const int jx = ix + it.sx;
+  const int jy = iy + it.sy;
+  if (jx >= 0 && jx < it.c.nx && jy >= 0 && jy < it.c.ny) {
+    const int64_t s = (int64_t)jy * it.c.nx + jx;
+    dst.h[o] = src.h[s];
+    dst.v[o] = src.v[s];
+    dst.t[o] = src.t[s];
+    dst.nx[o] = src.nx[s];
+    dst.ny[o] = src.ny[s];
+    dst.nz[o] = src.nz[s];
+    dst.trav[o] = src.trav[s];
+    dst.valid[o] = src.valid[s];
   } else {
     const float qnan = __builtin_nanf("");
-    a.dst.h[o] = a.c.h_init;
-    a.dst.v[o] = a.c.v_init;
-    a.dst.t[o] = 0;
-    a.dst.nx[o] = qnan;
-    a.dst.ny[o] = qnan;
-    a.dst.nz[o] = qnan;
-    a.dst.trav[o] = qnan;
-    a.dst.valid[o] = 0;
+    dst.h[o] = it.c.h_init;
+    dst.v[o] = it.c.v_init;
+    dst.t[o] = 0;
+    dst.nx[o] = qnan;
+    dst.ny[o] = qnan;
+    dst.nz[o] = qnan;
+    dst.trav[o] = qnan;
+    dst.valid[o] = 0;
   }
-  a.dst.mark[o] = 0;
+  dst.mark[o] = 0;
 }
 
 // ---------------------------------------------------------------- stencil tile
@@ -118,17 +118,49 @@ __device__ __forceinline__ bool window_ok(const HaloTile& s, const Consts& c, in
   return ok;
 }
 
-struct StencilArgs {
-  Consts c;
-  Layers L;
-  const float* w;  // traversability weights (89)
-};
+__device__ __forceinline__ void normal_at(const HaloTile& s, int lx, int ly, float inv6r,
+                                          float& nx, float& ny, float& nz) {
+  const float dxm = s.h[ly - 1][lx + 1] - s.h[ly - 1][lx - 1];
+  const float dx0 = s.h[ly][lx + 1] - s.h[ly][lx - 1];
+  const float dxp = s.h[ly + 1][lx + 1] - s.h[ly + 1][lx - 1];
+  const float dym = s.h[ly + 1][lx - 1] - s.h[ly - 1][lx - 1];
+  const float dy0 = s.h[ly + 1][lx] - s.h[ly - 1][lx];
+  const float dyp = s.h[ly + 1][lx + 1] - s.h[ly - 1][lx + 1];
+  const float gxv = ((dxm + dx0) + dxp) * inv6r;
+  const float gyv = ((dym + dy0) + dyp) * inv6r;
+  const float q = (gxv * gxv + gyv * gyv) + 1.0f;
+  const float inv = 1.0f / sqrtf(q);
+  nx = -gxv * inv;
+  ny = -gyv * inv;
+  nz = inv;
+}
 
-__global__ __launch_bounds__(kNTf) void k_normals(StencilArgs a) {
+__device__ __forceinline__ float trav_at(const HaloTile& s, int lx, int ly, const float* sw) {
+  float win[9];
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) win[dy * 3 + dx] = s.h[ly - 1 + dy][lx - 1 + dx];
+  float T = sw[88];
+#pragma unroll
+  for (int ch = 0; ch < 8; ++ch) {
+    float acc = sw[72 + ch];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc = fmaf(sw[ch * 9 + k], win[k], acc);
+    T = fmaf(sw[80 + ch], fmaxf(acc, 0.0f), T);
+  }
+  return T;
+}
+
+// Normals and/or traversability of one 32x32 output tile.
+__device__ __forceinline__ void cells_body(const Item& it, int64_t unit, bool do_n, bool do_t) {
   __shared__ HaloTile s;
-  const int x0 = blockIdx.x * kSW;
-  const int y0 = blockIdx.y * kSH;
-  load_halo(s, a.c, a.L, x0, y0);
+  __shared__ float sw[89];
+  const int ux = blocks_of(it.c.nx, 5);
+  const int x0 = (int)(unit % ux) * kSW;
+  const int y0 = (int)(unit / ux) * kSH;
+  if (do_t && threadIdx.x < 89) sw[threadIdx.x] = it.w[threadIdx.x];
+  load_halo(s, it.c, it.L, x0, y0);
   __syncthreads();
   const int tx = threadIdx.x & (kSW - 1);
   const int ty0 = threadIdx.x / kSW;
@@ -138,72 +170,54 @@ __global__ __launch_bounds__(kNTf) void k_normals(StencilArgs a) {
     const int ty = ty0 + j * (kNTf / kSW);
     const int gx = x0 + tx;
     const int gy = y0 + ty;
-    if (gx >= a.c.nx || gy >= a.c.ny) continue;
+    if (gx >= it.c.nx || gy >= it.c.ny) continue;
     const int lx = tx + 1;
     const int ly = ty + 1;
-    float nx = qnan, ny = qnan, nz = qnan;
-    if (window_ok(s, a.c, gx, gy, lx, ly)) {
-      const float dxm = s.h[ly - 1][lx + 1] - s.h[ly - 1][lx - 1];
-      const float dx0 = s.h[ly][lx + 1] - s.h[ly][lx - 1];
-      const float dxp = s.h[ly + 1][lx + 1] - s.h[ly + 1][lx - 1];
-      const float dym = s.h[ly + 1][lx - 1] - s.h[ly - 1][lx - 1];
-      const float dy0 = s.h[ly + 1][lx] - s.h[ly - 1][lx];
-      const float dyp = s.h[ly + 1][lx + 1] - s.h[ly - 1][lx + 1];
-      const float gxv = ((dxm + dx0) + dxp) * a.c.inv6r;
-      const float gyv = ((dym + dy0) + dyp) * a.c.inv6r;
-      const float q = (gxv * gxv + gyv * gyv) + 1.0f;
-      const float inv = 1.0f / sqrtf(q);
-      nx = -gxv * inv;
-      ny = -gyv * inv;
-      nz = inv;
+    const bool ok = window_ok(s, it.c, gx, gy, lx, ly);
+    const int64_t o = (int64_t)gy * it.c.nx + gx;
+    if (do_n) {
+      float nx = qnan, ny = qnan, nz = qnan;
+      if (ok) normal_at(s, lx, ly, it.c.inv6r, nx, ny, nz);
+      it.L.nx[o] = nx;
+      it.L.ny[o] = ny;
+      it.L.nz[o] = nz;
     }
-    const int64_t o = (int64_t)gy * a.c.nx + gx;
-    a.L.nx[o] = nx;
-    a.L.ny[o] = ny;
-    a.L.nz[o] = nz;
+    if (do_t) it.L.trav[o] = ok ? trav_at(s, lx, ly, sw) : qnan;
   }
 }
 
-__global__ __launch_bounds__(kNTf) void k_trav(StencilArgs a) {
-  __shared__ HaloTile s;
-  __shared__ float sw[89];
-  const int x0 = blockIdx.x * kSW;
-  const int y0 = blockIdx.y * kSH;
-  if (threadIdx.x < 89) sw[threadIdx.x] = a.w[threadIdx.x];
-  load_halo(s, a.c, a.L, x0, y0);
-  __syncthreads();
-  const int tx = threadIdx.x & (kSW - 1);
-  const int ty0 = threadIdx.x / kSW;
-  const float qnan = __builtin_nanf("");
-#pragma unroll
-  for (int j = 0; j < kSH / (kNTf / kSW); ++j) {
-    const int ty = ty0 + j * (kNTf / kSW);
-    const int gx = x0 + tx;
-    const int gy = y0 + ty;
-    if (gx >= a.c.nx || gy >= a.c.ny) continue;
-    const int lx = tx + 1;
-    const int ly = ty + 1;
-    float T = qnan;
-    if (window_ok(s, a.c, gx, gy, lx, ly)) {
-      float win[9];
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) win[dy * 3 + dx] = s.h[ly - 1 + dy][lx - 1 + dx];
-      T = sw[88];
-#pragma unroll
-      for (int ch = 0; ch < 8; ++ch) {
-        float acc = sw[72 + ch];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) acc = fmaf(sw[ch * 9 + k], win[k], acc);
-        T = fmaf(sw[80 + ch], fmaxf(acc, 0.0f), T);
-      }
-    }
-    a.L.trav[(int64_t)gy * a.c.nx + gx] = T;
+// ---------------------------------------------------------------- launches
+__global__ __launch_bounds__(kNTf) void k_move(Item it) { move_body(it, blockIdx.x); }
+__global__ __launch_bounds__(kNTf) void k_normals(Item it) {
+  cells_body(it, blockIdx.x, true, false);
+}
+__global__ __launch_bounds__(kNTf) void k_trav(Item it) {
+  cells_body(it, blockIdx.x, false, true);
+}
+
+__global__ __launch_bounds__(kNTf) void k_move_b(const Batch* bt) {
+  const int64_t total = bt->off[kBMove][bt->n];
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int i = batch_item(bt, kBMove, w);
+    move_body(bt->items[i], w - bt->off[kBMove][i]);
+  }
+}
+
+__global__ __launch_bounds__(kNTf) void k_cells_b(const Batch* bt) {
+  const int64_t total = bt->off[kBCells][bt->n];
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int i = batch_item(bt, kBCells, w);
+    const Item& it = bt->items[i];
+    cells_body(it, w - bt->off[kBCells][i], (it.stages & kStageNormals) != 0,
+               (it.stages & kStageTrav) != 0);
+    __syncthreads();
   }
 }
 
 }  // namespace
+
+int64_t move_units(int nx, int ny) { return (int64_t)blocks_of(nx, 6) * ((ny + kMoveH - 1) / kMoveH); }
+int64_t cells_units(int nx, int ny) { return (int64_t)blocks_of(nx, 5) * blocks_of(ny, 5); }
 
 hipError_t launch_fill_prior(const Consts& c, const Layers& L, uint32_t* ctl, int nctl,
                              hipStream_t stream) {
@@ -213,41 +227,37 @@ hipError_t launch_fill_prior(const Consts& c, const Layers& L, uint32_t* ctl, in
   a.cells = (int64_t)c.nx * c.ny;
   a.ctl = ctl;
   a.nctl = ctl ? nctl : 0;
-  hipLaunchKernelGGL(k_fill_prior, dim3((unsigned)((a.cells + kNTf - 1) / kNTf)), dim3(kNTf), 0,
-                     stream, a);
+  const int64_t n = a.cells > a.nctl ? a.cells : a.nctl;
+  hipLaunchKernelGGL(k_fill_prior, dim3((unsigned)((n + kNTf - 1) / kNTf)), dim3(kNTf), 0, stream,
+                     a);
   return hipGetLastError();
 }
 
-hipError_t launch_move(const Consts& c, const Layers& src, const Layers& dst, int sx, int sy,
-                       hipStream_t stream) {
-  MoveArgs a;
-  a.c = c;
-  a.src = src;
-  a.dst = dst;
-  a.sx = sx;
-  a.sy = sy;
-  hipLaunchKernelGGL(k_move, dim3((c.nx + 63) / 64, (c.ny + 3) / 4), dim3(kNTf), 0, stream, a);
+hipError_t launch_move(const Item& it, hipStream_t stream) {
+  hipLaunchKernelGGL(k_move, dim3((unsigned)move_units(it.c.nx, it.c.ny)), dim3(kNTf), 0, stream,
+                     it);
   return hipGetLastError();
 }
 
-hipError_t launch_normals(const Consts& c, const Layers& L, hipStream_t stream) {
-  StencilArgs a;
-  a.c = c;
-  a.L = L;
-  a.w = nullptr;
-  hipLaunchKernelGGL(k_normals, dim3((c.nx + kSW - 1) / kSW, (c.ny + kSH - 1) / kSH), dim3(kNTf),
-                     0, stream, a);
+hipError_t launch_normals(const Item& it, hipStream_t stream) {
+  hipLaunchKernelGGL(k_normals, dim3((unsigned)cells_units(it.c.nx, it.c.ny)), dim3(kNTf), 0,
+                     stream, it);
   return hipGetLastError();
 }
 
-hipError_t launch_trav(const Consts& c, const Layers& L, const float* weights,
-                       hipStream_t stream) {
-  StencilArgs a;
-  a.c = c;
-  a.L = L;
-  a.w = weights;
-  hipLaunchKernelGGL(k_trav, dim3((c.nx + kSW - 1) / kSW, (c.ny + kSH - 1) / kSH), dim3(kNTf), 0,
-                     stream, a);
+hipError_t launch_trav(const Item& it, hipStream_t stream) {
+  hipLaunchKernelGGL(k_trav, dim3((unsigned)cells_units(it.c.nx, it.c.ny)), dim3(kNTf), 0, stream,
+                     it);
+  return hipGetLastError();
+}
+
+hipError_t launch_move_batch(const Batch* d_batch, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_move_b, dim3(grid), dim3(kNTf), 0, stream, d_batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_cells_batch(const Batch* d_batch, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_cells_b, dim3(grid), dim3(kNTf), 0, stream, d_batch);
   return hipGetLastError();
 }
 

@@ -4,6 +4,12 @@
 // rounded float32 division/sqrt.  Kernels that take decisions (binning, gate,
 // ray samples, clearing predicate) rely on that to reproduce the operation
 // order the ABI documents exactly.
+//
+// Every kernel body works on one `Item`: one map with one frame.  It is called
+// either from a plain launch (the Item passed by value, one workgroup per unit
+// of work) or from a batched persistent launch that looks its units up in a
+// device-resident `Batch` table.  The arithmetic is the same code either way,
+// so a map's results are identical alone and in a batch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,11 +20,16 @@ namespace emx {
 // Points per fusion chunk.  This fixes the float32 summation order of the fused
 // sums, so it is a constant of the library, not a tunable.
 constexpr int kChunk = 2048;
-constexpr int kChunkLog = 11;
 // Map tiles of 32x32 cells own the per-cell merge.
 constexpr int kTileLog = 5;
 constexpr int kTile = 1 << kTileLog;
 constexpr int kTileCells = kTile * kTile;
+
+// Clearing queue: kSubQ sub-queues, each with its own counter kCtrStride words
+// apart.
+constexpr int kSubQ = 64;
+constexpr int kCtrStride = 32;
+constexpr int kCtrWords = kSubQ * kCtrStride;
 
 // One buffer set of map layers, row-major [ny][nx].
 struct Layers {
@@ -31,7 +42,7 @@ struct Layers {
   float* trav;
   uint8_t* valid;
   uint8_t* mark;  // clearing marks; all zero between calls
-  float* cmax;    // per 8x8 block: max height over cells a ray may clear (transient)
+  float* cmax;    // per block: max height over cells a ray may clear (transient)
 };
 
 // Clearing prunes samples by square blocks of 2^b cells, b >= 3: the
@@ -64,6 +75,72 @@ struct Consts {
 struct Pose32 {
   float R[9];
   float t[3];
+};
+
+struct FuseScratch {
+  uint16_t* rec_local;  // [B * kChunk] cell within its tile of each per-chunk partial
+  float* rec_w;         // [B * kChunk] chunk partial of sum 1/sp2
+  float* rec_wz;        // [B * kChunk] chunk partial of sum zm/sp2
+  uint32_t* dir;        // [B * T]  (start << 16 | count) of a tile's partials in a chunk
+};
+
+// Where a clearing setup queues its ray segments.
+struct ClearQueue {
+  float4* ray;        // (dx, dy, dz, K) per ray, indexed ray_base + i
+  int32_t* ray_end;   // end point's cell or -1
+  int32_t* ray_item;  // item of the ray (batched launches), or nullptr
+  uint2* queue;       // kSubQ sub-queues of qcap (ray, k_start << 8 | count) entries
+  uint32_t* counter;  // kSubQ counters, kCtrStride apart; zero on entry
+  int64_t qcap;       // entries per sub-queue
+  int seg;            // samples per queued segment (1..255)
+};
+
+// Queue capacity: on average kQueueSamplesPerRay samples per point fit.
+constexpr int kQueueSamplesPerRay = 128;
+
+// Stages of one frame, in pipeline order.
+constexpr uint32_t kStageMove = 1u;
+constexpr uint32_t kStageFuse = 2u;
+constexpr uint32_t kStageClear = 4u;
+constexpr uint32_t kStageNormals = 8u;
+constexpr uint32_t kStageTrav = 16u;
+
+// One map with one frame: everything a kernel body reads.
+struct Item {
+  Consts c;
+  Pose32 P;
+  Layers L;     // current buffer set (after any move)
+  Layers Lsrc;  // move source set
+  const float* x;
+  const float* y;
+  const float* z;
+  int64_t n;
+  int32_t t_now;
+  int sx, sy;   // move shift in cells
+  uint32_t stages;
+  const float* w;  // traversability weights (89)
+  int32_t* out_cell;
+  uint8_t* out_accept;
+  uint8_t* out_cleared;
+  FuseScratch fs;
+  ClearQueue cq;
+  int64_t ray_base;  // this item's first ray in cq
+  int tiles_x, T, B;
+  int bl, bx, by, nb, nprep;
+  int32_t index;     // position in its batch
+};
+
+// Batched launches: a device-resident table of items and, per stage, the
+// prefix of work units over the items.
+constexpr int kMaxItems = 64;
+enum BatchStage { kBMove = 0, kBChunk, kBTile, kBSetup, kBApply, kBCells, kBNum };
+
+struct Batch {
+  int n;
+  int key64;  // pass 1 sorts 64-bit keys for this batch
+  int64_t off[kBNum][kMaxItems + 1];
+  uint32_t counter[kCtrWords];  // clearing sub-queue counters (uploaded as zero)
+  Item items[kMaxItems];
 };
 
 struct PointEval {
@@ -120,6 +197,18 @@ __device__ __forceinline__ int block_exclusive_sum(int v, int& total, int* sm) {
   __syncthreads();
   total = tot;
   return pre + x - v;
+}
+
+// ------------------------------------------------------------- batched units
+// Item holding global unit w of `stage`: the last item whose prefix is <= w.
+__device__ __forceinline__ int batch_item(const Batch* bt, int stage, int64_t w) {
+  int lo = 0, hi = bt->n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bt->off[stage][mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 }  // namespace emx

@@ -1,7 +1,7 @@
 // Height fusion (Sec. II-C, Eq. 1 and Eq. 2) as a deterministic two-pass
 // sort-and-reduce, with no float atomics.
 //
-// Pass 1, k_fuse_chunk: one workgroup per chunk of kChunk consecutive points.
+// Pass 1, chunk body: one workgroup per chunk of kChunk consecutive points.
 //   - Takes the per-point decisions: transform, range, bin, and the Mahalanobis
 //     gate against the frame-start prior.
 //   - Sorts the accepted points in LDS by (tile, cell in tile, point index).
@@ -9,17 +9,16 @@
 //     a pairwise tree aligned to the run start.
 //   - Writes the partials, grouped by tile, and a dense tile directory row for
 //     the chunk.
-// Pass 2, k_fuse_tile: one workgroup per 32x32-cell map tile.
+// Pass 2, tile body: one workgroup per 32x32-cell map tile.
 //   - Stages the tile's partials from every chunk that touched it in LDS.
-//   - Adds them chunk by chunk.  A chunk holds at most one partial per cell,
-//     so each chunk's partials go to the cells in parallel, and every cell
-//     sees its partials in chunk order.
+//   - Adds them chunk by chunk.  A chunk holds at most one partial per cell;
+//     each wave owns a quarter of the cells and walks the chunks in order.
 //   - Applies the information-form update once per touched cell.
 //
 // The float32 sums therefore run in an order fixed by the frame alone: a
 // pairwise tree over a cell's points in point order within each chunk, then
-// chunk partials left to right in chunk order.  Results are bitwise identical from run to run, whatever the tile
-// size, grid shape or batching of pass 2.
+// chunk partials left to right in chunk order.  Results are bitwise identical
+// from run to run, whatever the tile size, grid shape or batching.
 #include "emx_kernels.h"
 
 namespace emx {
@@ -79,39 +78,24 @@ __device__ __forceinline__ void bitonic_sort_regs(KeyT& a, KeyT& b, KeyT* s) {
   }
 }
 
-struct ChunkArgs {
-  const float* x;
-  const float* y;
-  const float* z;
-  int64_t n;
-  Pose32 P;
-  Consts c;
-  const float* h;
-  const float* v;
-  int32_t* out_cell;
-  uint8_t* out_accept;
-  FuseScratch s;
-  int tiles_x;
-  int T;
-};
-
+// ------------------------------------------------------------------ pass 1
 template <typename KeyT>
-__global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
+__device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
   constexpr KeyT kNoKey = (KeyT)~(KeyT)0;
   __shared__ KeyT s_key[kChunk];
   __shared__ float s_w[kChunk];
   __shared__ float s_wz[kChunk];
-  __shared__ uint32_t s_seg[kChunk];   // (tile << 2*kTileLog | local) of record r
+  __shared__ uint32_t s_seg[kChunk];   // (tile << kSegBits | local) of record r
   __shared__ float s_vw[kChunk];       // per-key values in sorted order (tree sums)
   __shared__ float s_vwz[kChunk];
   __shared__ int16_t s_head[kChunk];   // position of each key's run head
   __shared__ int s_isum[kNT1 / 64];
 
   const int tid = threadIdx.x;
-  const int64_t chunk = blockIdx.x;
   const int64_t base = chunk * kChunk;
-  uint32_t* drow = a.s.dir + chunk * (int64_t)a.T;
-  for (int t = tid; t < a.T; t += kNT1) drow[t] = 0u;
+  const int T = it.T;
+  uint32_t* drow = it.fs.dir + chunk * (int64_t)T;
+  for (int t = tid; t < T; t += kNT1) drow[t] = 0u;
 
   // ---- per-point decisions; thread t takes points t and t + kNT1
   KeyT key[2];
@@ -121,25 +105,25 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
     const int p = j * kNT1 + tid;
     const int64_t i = base + p;
     key[j] = kNoKey;
-    if (i < a.n) {
-      const PointEval e = eval_point(a.P, a.c, a.x[i], a.y[i], a.z[i]);
+    if (i < it.n) {
+      const PointEval e = eval_point(it.P, it.c, it.x[i], it.y[i], it.z[i]);
       int cell = -1;
       bool acc = false;
       int ix = 0, iy = 0;
-      if (e.valid && bin_xy(e.xm, e.ym, a.c, ix, iy)) {
-        cell = iy * a.c.nx + ix;
-        const float h0 = a.h[cell];
-        const float v0 = a.v[cell];
+      if (e.valid && bin_xy(e.xm, e.ym, it.c, ix, iy)) {
+        cell = iy * it.c.nx + ix;
+        const float h0 = it.L.h[cell];
+        const float v0 = it.L.v[cell];
         const float d = e.zm - h0;
-        acc = (d * d) <= (a.c.k2 * (v0 + e.sp2));
+        acc = (d * d) <= (it.c.k2 * (v0 + e.sp2));
       }
-      if (a.out_cell) a.out_cell[i] = cell;
-      if (a.out_accept) a.out_accept[i] = acc ? 1 : 0;
+      if (it.out_cell) it.out_cell[i] = cell;
+      if (it.out_accept) it.out_accept[i] = acc ? 1 : 0;
       if (acc) {
         const float w = 1.0f / e.sp2;
         s_w[p] = w;
         s_wz[p] = w * e.zm;
-        const uint32_t tile = (uint32_t)((iy >> kTileLog) * a.tiles_x + (ix >> kTileLog));
+        const uint32_t tile = (uint32_t)((iy >> kTileLog) * it.tiles_x + (ix >> kTileLog));
         const uint32_t local = (uint32_t)(((iy & (kTile - 1)) << kTileLog) | (ix & (kTile - 1)));
         const KeyT seg = ((KeyT)tile << kSegBits) | (KeyT)local;
         key[j] = (seg << kPBits) | (KeyT)p;
@@ -152,7 +136,7 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
   if (nacc == 0) return;  // uniform: the directory row stays zero
 
   // ---- sort by (tile, local, point); invalid keys sort last
-  bitonic_sort_regs(key[0], key[1], s_key);
+  bitonic_sort_regs<KeyT>(key[0], key[1], s_key);
   s_key[2 * tid] = key[0];
   s_key[2 * tid + 1] = key[1];
   __syncthreads();
@@ -173,8 +157,8 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
   }
   // run head of every key: inclusive max-scan of head positions
   {
-    int m0 = hpos[0];
-    int m1 = max(hpos[0], hpos[1]);
+    const int m0 = hpos[0];
+    const int m1 = max(hpos[0], hpos[1]);
     const int lane = tid & 63;
     const int wid = tid >> 6;
     int x = m1;
@@ -250,25 +234,25 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(ChunkArgs a) {
     const int q = hpos[j];
     const uint32_t sk = (uint32_t)(s_key[q] >> kPBits);
     const int64_t o = base + r;
-    a.s.rec_local[o] = (uint16_t)(sk & (kTileCells - 1));
-    a.s.rec_w[o] = s_vw[q];
-    a.s.rec_wz[o] = s_vwz[q];
+    it.fs.rec_local[o] = (uint16_t)(sk & (kTileCells - 1));
+    it.fs.rec_w[o] = s_vw[q];
+    it.fs.rec_wz[o] = s_vwz[q];
     s_seg[r] = sk;
     ++r;
   }
   __syncthreads();
 
   // ---- directory: first record and record count of each touched tile
-  for (int r = tid; r < nrec; r += kNT1) {
-    const uint32_t tile = s_seg[r] >> (2 * kTileLog);
-    if (r > 0 && (s_seg[r - 1] >> (2 * kTileLog)) == tile) continue;
-    int lo = r, hi = nrec;  // first record of a later tile
+  for (int r2 = tid; r2 < nrec; r2 += kNT1) {
+    const uint32_t tile = s_seg[r2] >> kSegBits;
+    if (r2 > 0 && (s_seg[r2 - 1] >> kSegBits) == tile) continue;
+    int lo = r2, hi = nrec;  // first record of a later tile
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if ((s_seg[mid] >> (2 * kTileLog)) == tile) lo = mid + 1;
+      if ((s_seg[mid] >> kSegBits) == tile) lo = mid + 1;
       else hi = mid;
     }
-    drow[tile] = ((uint32_t)r << 16) | (uint32_t)(lo - r);
+    drow[tile] = ((uint32_t)r2 << 16) | (uint32_t)(lo - r2);
   }
 }
 
@@ -277,17 +261,7 @@ constexpr int kNT2 = 256;
 constexpr int kCap = 4096;     // partials held in LDS per round
 constexpr int kWin = kNT2;     // directory entries read per window
 
-struct TileArgs {
-  FuseScratch s;
-  int B;
-  int T;
-  int tiles_x;
-  Consts c;
-  Layers L;
-  int32_t t_now;
-};
-
-__global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
+__device__ __forceinline__ void tile_body(const Item& it, int t) {
   __shared__ float acc_w[kTileCells];
   __shared__ float acc_wz[kTileCells];
   __shared__ uint8_t hit[kTileCells];
@@ -302,17 +276,18 @@ __global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
   __shared__ int s_g1;
 
   const int tid = threadIdx.x;
-  const int t = blockIdx.x;
+  const int B = it.B;
+  const int T = it.T;
   for (int l = tid; l < kTileCells; l += kNT2) {
     acc_w[l] = 0.0f;
     acc_wz[l] = 0.0f;
     hit[l] = 0;
   }
 
-  for (int k0 = 0; k0 < a.B; k0 += kWin) {
+  for (int k0 = 0; k0 < B; k0 += kWin) {
     // compact the chunks of this window that touched the tile, in chunk order
     const int kk = k0 + tid;
-    const uint32_t d = (kk < a.B) ? a.s.dir[(int64_t)kk * a.T + t] : 0u;
+    const uint32_t d = (kk < B) ? it.fs.dir[(int64_t)kk * T + t] : 0u;
     int L = 0;
     const int pos = block_exclusive_sum<kNT2>(d != 0u ? 1 : 0, L, s_isum);
     if (d != 0u) {
@@ -353,9 +328,9 @@ __global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
           else hi = mid - 1;
         }
         const int64_t idx = (int64_t)e_chunk[lo] * kChunk + e_start[lo] + (gp - e_pre[lo]);
-        u_l[p] = a.s.rec_local[idx];
-        u_w[p] = a.s.rec_w[idx];
-        u_wz[p] = a.s.rec_wz[idx];
+        u_l[p] = it.fs.rec_local[idx];
+        u_w[p] = it.fs.rec_w[idx];
+        u_wz[p] = it.fs.rec_wz[idx];
       }
       __syncthreads();
       // chunk by chunk.  A chunk holds at most one partial per cell, and wave w
@@ -384,22 +359,49 @@ __global__ __launch_bounds__(kNT2) void k_fuse_tile(TileArgs a) {
   __syncthreads();
 
   // ---- information-form update of every touched cell
-  const int tx = t % a.tiles_x;
-  const int ty = t / a.tiles_x;
+  const int tx = t % it.tiles_x;
+  const int ty = t / it.tiles_x;
   for (int l = tid; l < kTileCells; l += kNT2) {
     if (!hit[l]) continue;
     const int ix = (tx << kTileLog) + (l & (kTile - 1));
     const int iy = (ty << kTileLog) + (l >> kTileLog);
-    const int64_t cell = (int64_t)iy * a.c.nx + ix;
-    const float h0 = a.L.h[cell];
-    const float v0 = a.L.v[cell];
+    const int64_t cell = (int64_t)iy * it.c.nx + ix;
+    const float h0 = it.L.h[cell];
+    const float v0 = it.L.v[cell];
     const float W = (1.0f / v0) + acc_w[l];
     const float v1 = 1.0f / W;
     const float h1 = ((h0 / v0) + acc_wz[l]) * v1;
-    a.L.h[cell] = h1;
-    a.L.v[cell] = v1;
-    a.L.t[cell] = a.t_now;
-    a.L.valid[cell] = 1;
+    it.L.h[cell] = h1;
+    it.L.v[cell] = v1;
+    it.L.t[cell] = it.t_now;
+    it.L.valid[cell] = 1;
+  }
+}
+
+// ---------------------------------------------------------------- launches
+template <typename KeyT>
+__global__ __launch_bounds__(kNT1) void k_fuse_chunk(Item it) {
+  chunk_body<KeyT>(it, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kNT2) void k_fuse_tile(Item it) { tile_body(it, blockIdx.x); }
+
+template <typename KeyT>
+__global__ __launch_bounds__(kNT1) void k_fuse_chunk_b(const Batch* bt) {
+  const int64_t total = bt->off[kBChunk][bt->n];
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int i = batch_item(bt, kBChunk, w);
+    chunk_body<KeyT>(bt->items[i], w - bt->off[kBChunk][i]);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kNT2) void k_fuse_tile_b(const Batch* bt) {
+  const int64_t total = bt->off[kBTile][bt->n];
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int i = batch_item(bt, kBTile, w);
+    tile_body(bt->items[i], (int)(w - bt->off[kBTile][i]));
+    __syncthreads();
   }
 }
 
@@ -409,6 +411,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int tiles_x_of(int nx) { return (nx + kTile - 1) >> kTileLog; }
 int tiles_y_of(int ny) { return (ny + kTile - 1) >> kTileLog; }
+bool fuse_needs_key64(int T) { return (int64_t)T * kTileCells > kMaxCells32; }
 
 size_t fuse_scratch_layout(int64_t max_points, int T, char* base, FuseScratch* out) {
   const int64_t B = (max_points + kChunk - 1) / kChunk;
@@ -431,43 +434,29 @@ size_t fuse_scratch_layout(int64_t max_points, int T, char* base, FuseScratch* o
   return off;
 }
 
-hipError_t launch_fuse(const float* x, const float* y, const float* z, int64_t n,
-                       const Pose32& P, const Consts& c, const Layers& L, int32_t t_now,
-                       int32_t* out_cell, uint8_t* out_accept, const FuseScratch& s,
-                       hipStream_t stream) {
-  if (n <= 0) return hipSuccess;
-  const int tx = tiles_x_of(c.nx);
-  const int T = tx * tiles_y_of(c.ny);
-  const int B = (int)((n + kChunk - 1) / kChunk);
-  ChunkArgs a1;
-  a1.x = x;
-  a1.y = y;
-  a1.z = z;
-  a1.n = n;
-  a1.P = P;
-  a1.c = c;
-  a1.h = L.h;
-  a1.v = L.v;
-  a1.out_cell = out_cell;
-  a1.out_accept = out_accept;
-  a1.s = s;
-  a1.tiles_x = tx;
-  a1.T = T;
-  if ((int64_t)T * kTileCells <= kMaxCells32)
-    hipLaunchKernelGGL(k_fuse_chunk<uint32_t>, dim3(B), dim3(kNT1), 0, stream, a1);
+hipError_t launch_fuse(const Item& it, hipStream_t stream) {
+  if (it.n <= 0) return hipSuccess;
+  if (fuse_needs_key64(it.T))
+    hipLaunchKernelGGL(k_fuse_chunk<uint64_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
   else
-    hipLaunchKernelGGL(k_fuse_chunk<uint64_t>, dim3(B), dim3(kNT1), 0, stream, a1);
+    hipLaunchKernelGGL(k_fuse_chunk<uint32_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  TileArgs a2;
-  a2.s = s;
-  a2.B = B;
-  a2.T = T;
-  a2.tiles_x = tx;
-  a2.c = c;
-  a2.L = L;
-  a2.t_now = t_now;
-  hipLaunchKernelGGL(k_fuse_tile, dim3(T), dim3(kNT2), 0, stream, a2);
+  hipLaunchKernelGGL(k_fuse_tile, dim3(it.T), dim3(kNT2), 0, stream, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_fuse_batch(const Batch* d_batch, bool key64, int grid_chunk, int grid_tile,
+                             hipStream_t stream) {
+  if (key64)
+    hipLaunchKernelGGL(k_fuse_chunk_b<uint64_t>, dim3(grid_chunk), dim3(kNT1), 0, stream,
+                       d_batch);
+  else
+    hipLaunchKernelGGL(k_fuse_chunk_b<uint32_t>, dim3(grid_chunk), dim3(kNT1), 0, stream,
+                       d_batch);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_fuse_tile_b, dim3(grid_tile), dim3(kNT2), 0, stream, d_batch);
   return hipGetLastError();
 }
 

@@ -1,0 +1,58 @@
+// Host-side internals shared by the plain and batched C ABI entry points.
+#pragma once
+
+#include <stdint.h>
+
+#include "emx.h"
+#include "emx_kernels.h"
+
+namespace emx {
+
+// Per-map control words after the two buffer sets: the clearing sub-queue
+// counters of the plain calls.
+constexpr int kCtlWords = kCtrWords;
+
+// Default clearing segment length (samples per queued segment).
+constexpr int kDefaultSeg = 32;
+
+emx_status fail(emx_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+emx_status hip_fail(hipError_t e, const char* what);
+const char* last_error_text();
+
+emx_status check_params(const emx_params* p);
+Consts make_consts(const emx_params& p);
+size_t set_layout(const emx_params& p, char* base, Layers* L);
+int tiles_of(const emx_params& p);
+int persistent_grid(int per_cu);
+bool center_cell(double c, double r, int64_t* out);
+
+}  // namespace emx
+
+struct emx_map {
+  emx_params p;
+  emx::Consts c;
+  int64_t cgx, cgy;
+  int64_t t0;
+  char* state;
+  size_t set_bytes;
+  int cur;
+  emx::Layers sets[2];
+  uint32_t* ctl;
+  int march_grid;
+};
+
+namespace emx {
+
+emx_status check_map(const emx_map* m);
+emx_status check_frame(const emx_frame* f);
+
+// Item for map m and frame f (f may be NULL for per-cell calls), on the map's
+// current buffer set.  Validates the pose and time; fills geometry, not scratch.
+emx_status make_item(const emx_map* m, const emx_frame* f, Item* it);
+
+// Plan the move of map m to centre (cx, cy): shift in cells, clamped; returns
+// false if the centre is out of range.
+bool plan_move(const emx_map* m, double cx, double cy, int64_t* ngx, int64_t* ngy, int* sx,
+               int* sy);
+
+}  // namespace emx
