@@ -1,21 +1,31 @@
 """Benchmark of the elevation-map fusion hot path on one MI355X.
 
-Workload: one robot.
+Headline workload: one robot.
   * A 400x400 map at 0.04 m (16 x 16 m).
   * 300k-point frames: a 64-beam dome LiDAR plus four depth frustums.
   * The frames follow a seeded smooth trajectory over a synthetic terrain.
 One step is one frame through the whole per-frame path, the ABI calls in
 order: move_map, fuse_points, clear_visibility, compute_normals,
-traversability.
-Every frame is generated on the device before timing starts.  The plain loop
-waits for each frame before submitting the next, so the recorded per-frame
-latency is submission to completion.
+traversability.  Every frame is generated on the device before timing starts.
+  * value: the timed frames submitted back to back (inputs resident in HBM),
+    points per second of wall time between two device synchronisations.
+  * latency_ms: the same frames with the host waiting for each one
+    (submission to completion).
+  * roofline: the dominant kernel of the plain path, its per-launch duration
+    taken with events on its stream around each launch.
 
-Prints one JSON line.
+Also reported, each with its plain per-frame comparison:
+  * batched: 16 maps of uneven sizes, one frame each, in one batched launch
+    (emx_pipeline_batch) against 16 per-frame plain pipelines;
+  * server: 64 robots sending frames by Poisson arrival at 20 Hz each into the
+    continuous-batching server, against the per-frame plain loop on the same
+    arrival trace; and both with every frame queued at once (saturated).
+Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -30,6 +40,12 @@ sys.path.insert(0, ROOT)
 METRIC = "points fused/sec and p99 update latency: batched server vs per-frame plain"
 HBM_PEAK_GBS = 8000.0
 STAGES = ("move_map", "fuse_points", "clear_visibility", "compute_normals", "traversability")
+TUNING_FILE = os.path.join(ROOT, "paper_2204_12876_amd", "tuning_mi355x.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_400x400_300k.txt")
+
+
+def say(*a):
+    print("#", *a, file=sys.stderr, flush=True)
 
 
 def parse():
@@ -40,6 +56,17 @@ def parse():
     ap.add_argument("--points", type=int, default=300000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=12)
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-server", action="store_true")
+    ap.add_argument("--batched-reps", type=int, default=20)
+    ap.add_argument("--server-seconds", type=float, default=1.0)
+    ap.add_argument("--server-robots", type=int, default=64)
+    ap.add_argument("--tuning", default=None, help="batch tuning JSON (default: the tuned file)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy 256 MiB device to device once (a known-size kernel that "
+                         "calibrates hardware byte counters)")
+    ap.add_argument("--autotune", default=None, metavar="OUT",
+                    help="tune the batched executor on the 16-map workload, write OUT, exit")
     return ap.parse_args()
 
 
@@ -53,62 +80,105 @@ def cpu_model() -> str:
     return platform.processor()
 
 
-def algorithmic_bytes(cell: np.ndarray, acc: np.ndarray, n: int, C: int) -> dict:
-    """Bytes the method must move per call, by stage.
-    fuse: points (12 B) + prior h, v of each distinct in-map cell hit (8 B) +
-    h, v, t_upd, valid written for each updated cell (13 B)."""
-    touched = np.unique(cell[cell >= 0]).size
-    updated = np.unique(cell[acc.astype(bool)]).size
-    return dict(
-        fuse_points=12 * n + 8 * touched + 13 * updated,
-        clear_visibility=12 * n + 25 * C + 1 * C,
-        compute_normals=5 * C + 12 * C,
-        traversability=5 * C + 4 * C,
-        move_map=2 * 29 * C,
-        touched=touched, updated=updated)
+def frame_stats(cell: np.ndarray, acc: np.ndarray) -> dict:
+    return dict(touched=np.unique(cell[cell >= 0]).size,
+                updated=np.unique(cell[acc.astype(bool)]).size)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every map and frame "
-              "of this workload fits one MI355X.", file=sys.stderr)
-        sys.exit(2)
+def kernel_alg_bytes(name: str, n: int, C: int, touched: float, updated: float) -> float:
+    """Bytes each kernel must move at the least, per launch.
+      fusion pass 1: the points (12 B) and the prior h, v of each distinct
+        in-map cell they hit (8 B);
+      fusion pass 2: prior h, v read and h, v, t_upd, valid written for each
+        updated cell (8 + 13 B);
+      clearing: setup reads the points and h, t_upd, valid per cell for the
+        block maxima (9 B); the march reads each cell's h, v, t_upd, valid and
+        normal once (25 B); apply reads the marks and writes the output mask;
+      normals: h, valid in (5 B), three components out (12 B);
+      traversability: h, valid in, one float out (9 B);
+      move: every layer read and written once (2 x 29 B)."""
+    return {
+        "k_fuse_chunk": 12 * n + 8 * touched,
+        "k_fuse_tile": 21 * updated,
+        "k_clear_setup": 12 * n + 9 * C,
+        "k_clear_march": 25 * C,
+        "k_clear_apply": 2 * C,
+        "k_normals": 17 * C,
+        "k_trav": 9 * C,
+        "k_move": 58 * C,
+    }.get(name, 0.0)
+
+
+def csrc_hash() -> str:
+    d = os.path.join(ROOT, "paper_2204_12876_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary,
+    or None if it is absent or was taken from different kernel sources."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("csrc_sha256_16") != csrc_hash():
+            return None
+        f = float(kv[f"{kernel}.fetch_kib"]) * float(kv["fetch_factor"])
+        w = float(kv[f"{kernel}.write_kib"]) * float(kv["write_factor"])
+        return 1024.0 * (f + w)
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def load_tuning(args):
+    if args.tuning:
+        return args.tuning
+    if os.path.exists(TUNING_FILE):
+        with open(TUNING_FILE) as fh:
+            return json.dumps(json.load(fh)["tuning"])
+    return None
+
+
+# ------------------------------------------------------------- plain, one robot
+def plain_single_robot(args, dev):
     import torch
 
     import synth
-    from paper_2204_12876_amd import ElevationMap, aligned_empty
+    from paper_2204_12876_amd import ElevationMap, _emx
 
-    dev = torch.device("cuda:0")
     K, W = args.steps, args.warmup
     t_gen = time.perf_counter()
     d = synth.cfg1(n_frames=W + K, device=dev, n_points=args.points)
     torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t_gen
-    print(f"# generated {W + K} frames of {args.points} points in {t_gen:.1f} s", file=sys.stderr,
-          flush=True)
+    say(f"generated {W + K} frames of {args.points} points in {time.perf_counter() - t_gen:.1f} s")
     frames = [(f.x.contiguous(), f.y.contiguous(), f.z.contiguous(), f.pose, f.t_ms)
               for f in d["frames"]]
     centers = d["centers"]
     params = d["params"]
     C = params["nx"] * params["ny"]
     w = torch.from_numpy(synth.trav_weights()).to(dev)
-    m = ElevationMap(params, centers[0][0], centers[0][1], 0, device=dev)
-    scratch = m.scratch(args.points)
     stream = torch.cuda.current_stream(dev)
+    probe = ElevationMap(params, device=dev)
+    scratch = probe.scratch(args.points)
+    probe.close()
 
-    def step(k, ev=None):
+    def run(m, k, ev=None, cell=None, acc=None):
         x, y, z, pose, t = frames[k]
-        cx, cy = centers[k]
         if ev is not None:
             ev[0].record(stream)
-        m.move_map(cx, cy)
+        m.move_map(*centers[k])
         if ev is not None:
             ev[1].record(stream)
-        m.fuse_points(x, y, z, pose, t, scratch=scratch)
+        m.fuse_points(x, y, z, pose, t, scratch=scratch, out_cell=cell, out_accept=acc)
         if ev is not None:
             ev[2].record(stream)
-        m.clear_visibility(x, y, z, pose, t)
+        m.clear_visibility(x, y, z, pose, t, scratch=scratch)
         if ev is not None:
             ev[3].record(stream)
         m.compute_normals()
@@ -118,139 +188,396 @@ def main():
         if ev is not None:
             ev[5].record(stream)
 
-    for k in range(W):
-        step(k)
-    torch.cuda.synchronize()
+    def fresh():
+        m = ElevationMap(params, centers[0][0], centers[0][1], 0, device=dev)
+        for k in range(W):
+            run(m, k)
+        torch.cuda.synchronize()
+        return m
 
-    # ---- timed: plain per-frame loop, host waits for every frame
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
-    lat = np.zeros(K)
+    # ---- timed: frames back to back, inputs resident; wall clock between syncs
+    m = fresh()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for j in range(K):
-        s = time.perf_counter()
-        step(W + j, evs[j])
-        stream.synchronize()
-        lat[j] = time.perf_counter() - s
+        run(m, W + j)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    m.close()
+    n_pts = sum(frames[W + j][0].numel() for j in range(K))
+    say(f"plain back to back: {wall / K * 1e3:.3f} ms/frame")
+
+    # ---- latency: the host waits for every frame; events per stage
+    m = fresh()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
+    lat = np.zeros(K)
+    for j in range(K):
+        s = time.perf_counter()
+        run(m, W + j, evs[j])
+        stream.synchronize()
+        lat[j] = time.perf_counter() - s
     stage_ms = {name: float(np.mean([evs[j][i].elapsed_time(evs[j][i + 1]) for j in range(K)]))
                 for i, name in enumerate(STAGES)}
-    step_ms = float(np.mean([evs[j][0].elapsed_time(evs[j][5]) for j in range(K)]))
-    n_pts = sum(frames[W + j][0].numel() for j in range(K))
+    m.close()
 
-    # ---- the same frames submitted back to back (no host wait): device rate
-    m2 = ElevationMap(params, centers[0][0], centers[0][1], 0, device=dev)
-    for k in range(W):
-        x, y, z, pose, t = frames[k]
-        m2.move_map(*centers[k])
-        m2.fuse_points(x, y, z, pose, t, scratch=scratch)
-        m2.clear_visibility(x, y, z, pose, t)
-        m2.compute_normals()
-        m2.traversability(w)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for j in range(K):
-        x, y, z, pose, t = frames[W + j]
-        m2.move_map(*centers[W + j])
-        m2.fuse_points(x, y, z, pose, t, scratch=scratch)
-        m2.clear_visibility(x, y, z, pose, t)
-        m2.compute_normals()
-        m2.traversability(w)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    async_ms = e0.elapsed_time(e1) / K
-    m2.close()
-
-    # ---- algorithmic bytes: replay the run untimed with per-point outputs
-    m3 = ElevationMap(params, centers[0][0], centers[0][1], 0, device=dev)
+    # ---- per-kernel durations (events around each launch) and frame statistics
+    m = fresh()
     cell = torch.empty(args.points, dtype=torch.int32, device=dev)
     acc = torch.empty(args.points, dtype=torch.uint8, device=dev)
-    ab = {s: [] for s in STAGES}
-    ab["touched"], ab["updated"] = [], []
-    for k in range(W + K):
-        x, y, z, pose, t = frames[k]
-        m3.move_map(*centers[k])
-        m3.fuse_points(x, y, z, pose, t, out_cell=cell, out_accept=acc, scratch=scratch)
-        m3.clear_visibility(x, y, z, pose, t)
-        m3.compute_normals()
-        m3.traversability(w)
-        if k >= W:
-            n = x.numel()
-            b = algorithmic_bytes(cell[:n].cpu().numpy(), acc[:n].cpu().numpy(), n, C)
-            for s in b:
-                ab[s].append(b[s])
-    m3.close()
-    alg = {s: float(np.mean(ab[s])) for s in ab}
-    dominant = max(STAGES, key=lambda s: stage_ms[s])
-    dom_gbs = alg[dominant] / (stage_ms[dominant] * 1e-3) / 1e9
+    stats = []
+    _emx.timing_begin()
+    for j in range(K):
+        run(m, W + j, cell=cell, acc=acc)
+        n = frames[W + j][0].numel()
+        stats.append(frame_stats(cell[:n].cpu().numpy(), acc[:n].cpu().numpy()))
+    kt = _emx.timing_end()
+    m.close()
+    touched = float(np.mean([s["touched"] for s in stats]))
+    updated = float(np.mean([s["updated"] for s in stats]))
+    n_mean = n_pts / K
+    kernels = {}
+    for name, (cnt, tot_ms) in kt.items():
+        avg_us = tot_ms / cnt * 1e3
+        ab = kernel_alg_bytes(name, n_mean, C, touched, updated)
+        kernels[name] = {"launches": cnt, "avg_us": avg_us, "alg_bytes": ab,
+                         "alg_GBps": ab / (avg_us * 1e-6) / 1e9 if avg_us > 0 else None}
+    dom = max((k for k in kernels if k != "k_fill_prior"),
+              key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+    dk = kernels[dom]
+    traffic = measured_traffic(dom)
 
-    value = n_pts / wall
+    out = {
+        "value": n_pts / wall,
+        "ms_per_step": wall / K * 1e3,
+        "config": {"workload": "plain single robot: 400x400 map at 0.04 m, 300k-point frames "
+                               "(dome LiDAR + 4 depth frustums), full pipeline per frame",
+                   "map_cells": C, "points_per_frame": args.points, "frames": K,
+                   "mode": "per-frame plain calls, frames submitted back to back"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p99": float(np.percentile(lat, 99) * 1e3),
+                       "max": float(lat.max() * 1e3),
+                       "note": "host waits for each frame before the next"},
+        "maps_per_s": K / wall,
+        "stage_ms": stage_ms,
+        "kernels": kernels,
+        "cells_touched": touched, "cells_updated": updated,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dk["alg_GBps"] / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_us": dk["avg_us"]},
+    }
+    return out, dict(frames=frames, centers=centers, params=params)
+
+
+# ------------------------------------------------------------ batched, 16 maps
+def batched_maps(args, dev, tuning):
+    import torch
+
+    import synth
+    from paper_2204_12876_amd import BatchEntry, ElevationMap, PipelineBatch
+
+    t_gen = time.perf_counter()
+    d = synth.cfg2(device=dev)
+    torch.cuda.synchronize()
+    items = d["items"]
+    pts = sum(it["frames"][0].n for it in items)
+    say(f"generated 16 maps / {pts} points in {time.perf_counter() - t_gen:.1f} s")
+    w = torch.from_numpy(synth.trav_weights()).to(dev)
+    fr = [(it["frames"][0].x.contiguous(), it["frames"][0].y.contiguous(),
+           it["frames"][0].z.contiguous(), it["frames"][0].pose) for it in items]
+    R = args.batched_reps
+    stream = torch.cuda.current_stream(dev)
+
+    def maps():
+        return [ElevationMap(it["params"], 0.0, 0.0, 0, device=dev) for it in items]
+
+    # batched
+    mb = maps()
+    pb = PipelineBatch(tuning, device=dev)
+
+    def batch(rep):
+        pb.run([BatchEntry(m, x, y, z, pose, 100 * rep, center=(0.0, 0.0), weights=w)
+                for m, (x, y, z, pose) in zip(mb, fr)])
+
+    for rep in range(3):
+        batch(rep)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for rep in range(3, 3 + R):
+        batch(rep)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / R
+    lat_b = []
+    for rep in range(3 + R, 3 + 2 * R):
+        s = time.perf_counter()
+        batch(rep)
+        stream.synchronize()
+        lat_b.append(time.perf_counter() - s)
+
+    # 16 per-frame plain pipelines
+    mp = maps()
+    scratch = max((m.scratch(f[0].numel()) for m, f in zip(mp, fr)), key=lambda t: t.numel())
+
+    def plain(rep):
+        for m, (x, y, z, pose) in zip(mp, fr):
+            m.move_map(0.0, 0.0)
+            m.fuse_points(x, y, z, pose, 100 * rep, scratch=scratch)
+            m.clear_visibility(x, y, z, pose, 100 * rep, scratch=scratch)
+            m.compute_normals()
+            m.traversability(w)
+
+    for rep in range(3):
+        plain(rep)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for rep in range(3, 3 + R):
+        plain(rep)
+    torch.cuda.synchronize()
+    t_p = (time.perf_counter() - t0) / R
+    lat_p = []
+    for rep in range(3 + R, 3 + 2 * R):
+        s = time.perf_counter()
+        plain(rep)
+        stream.synchronize()
+        lat_p.append(time.perf_counter() - s)
+    # identical results, as the batched path promises
+    same = all(torch.equal(a.export_state(), b.export_state()) for a, b in zip(mb, mp))
+    for m in mb + mp:
+        m.close()
+    pb.close()
+    say(f"batched {t_b * 1e3:.3f} ms vs plain {t_p * 1e3:.3f} ms per 16 maps")
+    return {
+        "workload": "16 maps, sides U{200..1000} at 0.02-0.1 m, one frame each of "
+                    "logU[20k, 1M] points, full pipeline",
+        "points_per_batch": int(pts),
+        "batched": {"ms": t_b * 1e3, "points_per_s": pts / t_b, "maps_per_s": 16 / t_b,
+                    "p50_ms": float(np.percentile(lat_b, 50) * 1e3),
+                    "p99_ms": float(np.percentile(lat_b, 99) * 1e3)},
+        "plain": {"ms": t_p * 1e3, "points_per_s": pts / t_p, "maps_per_s": 16 / t_p,
+                  "p50_ms": float(np.percentile(lat_p, 50) * 1e3),
+                  "p99_ms": float(np.percentile(lat_p, 99) * 1e3)},
+        "speedup": t_p / t_b,
+        "results_identical": bool(same),
+        "tuning": pb_tuning_text(tuning),
+    }
+
+
+def pb_tuning_text(tuning):
+    return json.loads(tuning) if tuning else "library defaults"
+
+
+# -------------------------------------------------------------- server, 64 robots
+def serving(args, dev, tuning):
+    import torch
+
+    import synth
+    from paper_2204_12876_amd import ElevationMap
+    from paper_2204_12876_amd.server import (GpuExecutor, Request, Server, latency_summary,
+                                             run_plain_trace, run_trace)
+
+    t_gen = time.perf_counter()
+    d = synth.cfg3(device=dev, n_robots=args.server_robots, n_frames=1)
+    torch.cuda.synchronize()
+    items = d["items"]
+    say(f"generated {len(items)} robot frames in {time.perf_counter() - t_gen:.1f} s")
+    w = torch.from_numpy(synth.trav_weights()).to(dev)
+    host = []
+    for it in items:
+        f = it["frames"][0]
+        xyz = torch.empty((3, f.n), dtype=torch.float32, pin_memory=True)
+        xyz[0].copy_(f.x)
+        xyz[1].copy_(f.y)
+        xyz[2].copy_(f.z)
+        host.append((xyz, f.pose, it["centers"][0]))
+    largest = max((it["params"] for it in items), key=lambda p: p["nx"] * p["ny"])
+    rng = np.random.default_rng(12876 + 3)
+
+    def trace(seconds, saturated_frames=0):
+        reqs, seq = [], 0
+        for k, it in enumerate(items):
+            xyz, pose, c = host[k]
+            if saturated_frames:
+                times = np.zeros(saturated_frames)
+            else:
+                gaps = rng.exponential(1.0 / it["rate_hz"], int(seconds * it["rate_hz"] * 3) + 8)
+                times = np.cumsum(gaps)
+                times = times[times < seconds]
+            for j, t in enumerate(times):
+                # the robot re-observes from its pose; the centre alternates by one cell
+                cx = c[0] + (it["params"]["resolution"] if j % 2 else 0.0)
+                reqs.append(Request(robot=k, xyz=xyz, pose=pose, t_ms=100 * (j + 1),
+                                    center=(cx, c[1]), arrival=float(t), seq=seq))
+                seq += 1
+        return reqs
+
+    budget = 32 << 30
+
+    def run_server(reqs):
+        ex = GpuExecutor(largest, lanes=2, max_items=64, max_batch_points=8_000_000,
+                         pool_points=24_000_000, weights=w, tuning=tuning, device=dev)
+        srv = Server(ex, budget)
+        for k, it in enumerate(items):
+            srv.add_map(k, it["params"], *host[k][2])
+        for _ in range(3):                  # both host tables of each lane captured
+            run_trace(srv, trace(0, saturated_frames=2))
+        srv.completed.clear()
+        srv.batch_sizes.clear()
+        run_trace(srv, reqs, timeout_s=120)
+        s = latency_summary(reqs)
+        s["mean_batch_items"] = float(np.mean(srv.batch_sizes))
+        s["batches"] = len(srv.batch_sizes)
+        s["hbm_budget_bytes"] = budget
+        s["hbm_reserved_bytes"] = srv.budget.used
+        return s
+
+    def run_plain(reqs):
+        maps = {k: ElevationMap(it["params"], *host[k][2], 0, device=dev)
+                for k, it in enumerate(items)}
+        mx = max(h[0].shape[1] for h in host)
+        run_plain_trace(maps, trace(0, saturated_frames=1), w, device=dev, max_points=mx)
+        run_plain_trace(maps, reqs, w, device=dev, max_points=mx)
+        for m in maps.values():
+            m.close()
+        return latency_summary(reqs)
+
+    poisson = trace(args.server_seconds)
+    offered = sum(r.n for r in poisson) / args.server_seconds
+    say(f"server trace: {len(poisson)} frames, offered {offered / 1e6:.0f} M points/s")
+    srv_p = run_server(poisson)
+    say(f"server p50 {srv_p['p50_ms']:.3f} p99 {srv_p['p99_ms']:.3f} ms")
+    pln_p = run_plain(_fresh(poisson))
+    say(f"plain  p50 {pln_p['p50_ms']:.3f} p99 {pln_p['p99_ms']:.3f} ms")
+    sat = trace(0, saturated_frames=6)
+    srv_s = run_server(sat)
+    pln_s = run_plain(_fresh(sat))
+    say(f"saturated: server {srv_s['points_per_s'] / 1e9:.2f} vs plain "
+        f"{pln_s['points_per_s'] / 1e9:.2f} G points/s")
+    return {
+        "workload": f"{len(items)} robots, maps U{{256..800}}^2 at 0.04 m, frames "
+                    "logU[50k, 500k] points, Poisson arrivals at 20 Hz each, full pipeline, "
+                    "frames copied from pinned host memory, 32 GiB device budget",
+        "offered_points_per_s": offered,
+        "poisson": {"server": srv_p, "plain": pln_p},
+        "saturated": {"frames_per_robot": 6, "server": srv_s, "plain": pln_s},
+    }
+
+
+def autotune_batched(dev, out_path):
+    """Tune the batched executor on the 16-map workload; write the result."""
+    import torch
+
+    import synth
+    from paper_2204_12876_amd import BatchEntry, ElevationMap
+    from paper_2204_12876_amd.autotune import autotune, default_tuning, time_tuning
+    d = synth.cfg2(device=dev)
+    w = torch.from_numpy(synth.trav_weights()).to(dev)
+    maps, frames = [], []
+    for it in d["items"]:
+        f = it["frames"][0]
+        maps.append(ElevationMap(it["params"], 0.0, 0.0, 0, device=dev))
+        frames.append((f.x.contiguous(), f.y.contiguous(), f.z.contiguous(), f.pose))
+
+    def run_batch(pb, rep):
+        pb.run([BatchEntry(m, x, y, z, pose, 100 * rep, center=(0.0, 0.0), weights=w)
+                for m, (x, y, z, pose) in zip(maps, frames)])
+
+    start = default_tuning()
+    best, _, hist = autotune(run_batch, start, device=dev, log=say)
+    t_def = time_tuning(run_batch, start, device=dev)
+    t_best = time_tuning(run_batch, best, device=dev)
+    out = {"tuning": best,
+           "workload": "16 maps, sides U{200..1000} at 0.02-0.1 m, one frame each of "
+                       "logU[20k, 1M] points, full pipeline",
+           "points_per_batch": int(sum(f[0].numel() for f in frames)),
+           "ms_best": t_best * 1e3, "ms_default": t_def * 1e3,
+           "device": torch.cuda.get_device_name(dev), "candidates_timed": len(hist)}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out), flush=True)
+
+
+def _fresh(reqs):
+    """Copies of requests with their timing fields reset."""
+    from paper_2204_12876_amd.server import Request
+    return [Request(robot=r.robot, xyz=r.xyz, pose=r.pose, t_ms=r.t_ms, center=r.center,
+                    arrival=r.arrival, seq=r.seq) for r in reqs]
+
+
+# ------------------------------------------------------------------- CPU oracle
+def cpu_baseline(args, ctx):
+    import oracle as O
+    import synth
+    params, frames, centers = ctx["params"], ctx["frames"], ctx["centers"]
+    p = O.Params.from_dict(params)
+    nfr = max(1, args.cpu_frames)
+    st = O.init_map(p, centers[0][0], centers[0][1], 0)
+    wts = synth.trav_weights()
+    t_cpu, pts = 0.0, 0
+    host = [(frames[k][0].cpu().numpy(), frames[k][1].cpu().numpy(),
+             frames[k][2].cpu().numpy()) for k in range(nfr)]
+    for k in range(nfr):
+        xs, ys, zs = host[k]
+        pose, t = frames[k][3], frames[k][4]
+        s = time.perf_counter()
+        st = O.move_map(p, st, *centers[k])
+        r = O.fuse(p, st, xs, ys, zs, pose, t)
+        st = r.state
+        mk = O.clear_visibility(p, st, xs, ys, zs, pose, t)
+        st = O.apply_clear(p, st, mk)
+        st.nrm[:] = O.compute_normals(p, st.h, st.valid).astype(np.float32)
+        T, _ = O.traversability(st.h, st.valid, wts)
+        st.trav[:] = T.astype(np.float32)
+        t_cpu += time.perf_counter() - s
+        pts += xs.size
+    return {"value": pts / t_cpu, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {nfr} frames of the same workload, full pipeline, "
+                      f"{t_cpu:.1f} s on one thread; {cpu_model()}, "
+                      f"{os.cpu_count()} host threads visible"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every map and frame "
+              "of this workload fits one MI355X.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    dev = torch.device("cuda:0")
+    if args.autotune:
+        autotune_batched(dev, args.autotune)
+        return
+    tuning = load_tuning(args)
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        say("calibration copy: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
+    plain, ctx = plain_single_robot(args, dev)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": plain.pop("value"),
         "unit": "points/s",
         "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": wall / K * 1e3,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": plain.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "plain single robot: 400x400 map at 0.04 m, 300k-point frames "
-                               "(dome LiDAR + 4 depth frustums), full pipeline per frame",
-                   "map_cells": C, "points_per_frame": args.points, "frames": K,
-                   "mode": "per-frame plain (host waits each frame)"},
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3),
-                       "max": float(lat.max() * 1e3)},
-        "device_ms_per_step": step_ms,
-        "async_ms_per_step": async_ms,
-        "async_points_per_s": args.points / (async_ms * 1e-3),
-        "maps_per_s": 1e3 / (wall / K * 1e3),
-        "stage_ms": stage_ms,
-        "stage_alg_bytes": {s: alg[s] for s in STAGES},
-        "stage_alg_GBps": {s: alg[s] / (stage_ms[s] * 1e-3) / 1e9 for s in STAGES},
-        "cells_touched": alg["touched"], "cells_updated": alg["updated"],
-        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dom_gbs,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
-                     "traffic": None},
     }
-
-    # ---- CPU oracle on a bounded sample of the same workload
+    out.update(plain)
+    if not args.skip_batched:
+        out["batched"] = batched_maps(args, dev, tuning)
+    if not args.skip_server:
+        out["server"] = serving(args, dev, tuning)
     if not args.no_cpu_baseline:
-        import oracle as O
-        p = O.Params.from_dict(params)
-        nfr = max(1, args.cpu_frames)
-        st = O.init_map(p, centers[0][0], centers[0][1], 0)
-        wts = synth.trav_weights()
-        t_cpu = 0.0
-        pts = 0
-        host = [(frames[k][0].cpu().numpy(), frames[k][1].cpu().numpy(),
-                 frames[k][2].cpu().numpy()) for k in range(nfr)]
-        for k in range(nfr):
-            xs, ys, zs = host[k]
-            pose, t = frames[k][3], frames[k][4]
-            s = time.perf_counter()
-            st = O.move_map(p, st, *centers[k])
-            r = O.fuse(p, st, xs, ys, zs, pose, t)
-            st = r.state
-            mk = O.clear_visibility(p, st, xs, ys, zs, pose, t)
-            st = O.apply_clear(p, st, mk)
-            nrm = O.compute_normals(p, st.h, st.valid)
-            st.nrm[:] = nrm.astype(np.float32)
-            T, _ = O.traversability(st.h, st.valid, wts)
-            st.trav[:] = T.astype(np.float32)
-            t_cpu += time.perf_counter() - s
-            pts += xs.size
-        out["cpu_baseline"] = {"value": pts / t_cpu, "unit": "points/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"first {nfr} frames of the same workload, full "
-                                         f"pipeline, {t_cpu:.1f} s; {cpu_model()}, "
-                                         f"{os.cpu_count()} host threads visible"}
+        out["cpu_baseline"] = cpu_baseline(args, ctx)
     print(json.dumps(out), flush=True)
 
 

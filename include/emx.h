@@ -275,6 +275,14 @@ emx_status emx_batch_tuning(const emx_batch* batch, char* buf, size_t len);
 size_t emx_batch_scratch_bytes(const emx_batch* batch, const emx_batch_item* items,
                                int32_t n);
 
+/* An upper bound of emx_batch_scratch_bytes() over every batch of at most
+ * max_items items (1..EMX_BATCH_MAX_ITEMS) whose maps have no more fusion
+ * tiles than a map of `largest` and whose frames hold at most max_points
+ * points together.  For callers that size one scratch buffer up front, as a
+ * server under a fixed memory budget does.  0 if an argument is invalid. */
+size_t emx_batch_scratch_bound(const emx_batch* batch, const emx_params* largest,
+                               int32_t max_items, int64_t max_points);
+
 /* Run the batch on `stream`.
  *   d_scratch: >= emx_batch_scratch_bytes(), 256-aligned.  Its first bytes
  *              hold the batch's device table.  A graph is cached per scratch
@@ -286,6 +294,17 @@ size_t emx_batch_scratch_bytes(const emx_batch* batch, const emx_batch_item* ite
  *   pinned table. */
 emx_status emx_pipeline_batch(emx_batch* batch, const emx_batch_item* items, int32_t n,
                               void* d_scratch, size_t scratch_bytes, void* stream);
+
+/* ---------------------------------------------------------------- timing
+ * Per-kernel timing of the plain calls, for profiling.  Between begin and
+ * end, each kernel launched by a plain call is bracketed by two timing
+ * events on its own stream; batched calls are not timed.  end waits for the
+ * recorded events and writes a JSON object to buf (len bytes):
+ *   {"<kernel>": [launches, total_ms], ...}
+ * in order of first launch.  Meant for one host thread; the events add a
+ * little time between kernels, not inside them. */
+emx_status emx_timing_begin(void);
+emx_status emx_timing_end(char* buf, size_t len);
 
 #ifdef __cplusplus
 }

@@ -223,19 +223,30 @@ class PipelineBatch:
         except Exception:
             pass
 
-    def run(self, entries):
-        arr = _emx.make_batch_items([e.item() for e in entries])
-        n = len(entries)
+    def reserve(self, nbytes: int):
+        """Allocate the scratch buffer now (graphs are cached per address)."""
+        if self._scratch is None or self._scratch_bytes < nbytes:
+            self._scratch = aligned_empty(nbytes, self.device)
+            self._scratch_bytes = int(nbytes)
+
+    def scratch_bound(self, largest_params: dict, max_items: int, max_points: int) -> int:
+        return _emx.batch_scratch_bound(self.handle, make_params(largest_params), max_items,
+                                        max_points)
+
+    def run_items(self, arr, n: int, stream: int):
+        """Run a ctypes array of emx_batch_item on ``stream``."""
         need = _emx.batch_scratch_bytes(self.handle, arr, n)
         if need == 0:
             raise EmxError(_emx.EMX_EINVAL, _emx.last_error())
         if self._scratch is None or self._scratch_bytes < need:
             # keep one buffer, generously sized: graphs are cached per scratch address
-            size = max(need, 2 * self._scratch_bytes)
-            self._scratch = aligned_empty(size, self.device)
-            self._scratch_bytes = size
+            self.reserve(max(need, 2 * self._scratch_bytes))
         _emx.pipeline_batch(self.handle, arr, n, self._scratch.data_ptr(), self._scratch_bytes,
-                            _stream(self.device))
+                            stream)
+
+    def run(self, entries):
+        arr = _emx.make_batch_items([e.item() for e in entries])
+        self.run_items(arr, len(entries), _stream(self.device))
 
 
 def pack_state(h, v, t_upd, valid, nrm, trav) -> np.ndarray:

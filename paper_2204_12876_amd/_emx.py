@@ -82,6 +82,9 @@ _SIGS = {
     "emx_batch_destroy": (c_int32, [c_void_p]),
     "emx_batch_tuning": (c_int32, [c_void_p, c_char_p, c_size_t]),
     "emx_batch_scratch_bytes": (c_size_t, [c_void_p, POINTER(BatchItem), c_int32]),
+    "emx_batch_scratch_bound": (c_size_t, [c_void_p, POINTER(Params), c_int32, c_int64]),
+    "emx_timing_begin": (c_int32, []),
+    "emx_timing_end": (c_int32, [c_char_p, c_size_t]),
     "emx_pipeline_batch": (c_int32, [c_void_p, POINTER(BatchItem), c_int32, c_void_p, c_size_t,
                                      c_void_p]),
 }
@@ -247,6 +250,23 @@ def make_batch_items(items) -> "ctypes.Array":
 
 def batch_scratch_bytes(h: int, arr, n: int) -> int:
     return lib().emx_batch_scratch_bytes(c_void_p(h), arr, n)
+
+
+def batch_scratch_bound(h: int, largest: Params, max_items: int, max_points: int) -> int:
+    return lib().emx_batch_scratch_bound(c_void_p(h), byref(largest), int(max_items),
+                                         int(max_points))
+
+
+def timing_begin():
+    check(lib().emx_timing_begin())
+
+
+def timing_end() -> dict:
+    """{kernel: (launches, total_ms)} since timing_begin (waits for the events)."""
+    import json
+    buf = create_string_buffer(1 << 14)
+    check(lib().emx_timing_end(buf, 1 << 14))
+    return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
 
 
 def pipeline_batch(h: int, arr, n: int, d_scratch: int, nbytes: int, stream: int):

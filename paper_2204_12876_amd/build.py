@@ -11,7 +11,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libemx.so")
 
-SOURCES = ["emx_api.hip", "emx_batch.hip", "emx_fuse.hip", "emx_clear.hip", "emx_cells.hip"]
+SOURCES = ["emx_api.hip", "emx_batch.hip", "emx_timing.hip", "emx_fuse.hip", "emx_clear.hip",
+           "emx_cells.hip"]
 
 # Decisions (binning, gate, ray samples) must follow the documented float32
 # operation order: no contraction into FMA, correctly rounded division/sqrt,

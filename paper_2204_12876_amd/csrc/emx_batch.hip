@@ -218,6 +218,20 @@ size_t emx_batch_scratch_bytes(const emx_batch* b, const emx_batch_item* items, 
   return batch_layout(items, n, b->tune.seg, nullptr, nullptr);
 }
 
+size_t emx_batch_scratch_bound(const emx_batch* b, const emx_params* largest, int32_t max_items,
+                               int64_t max_points) {
+  if (!b || check_params(largest) != EMX_OK) return 0;
+  if (max_items < 1 || max_items > kMaxItems || max_points < 0 || max_points > 2147483647LL)
+    return 0;
+  // Every item's chunk count is at most n_i / kChunk + 1 and its fusion
+  // arrays are each padded by under 256 bytes, plus the item's own padding.
+  const int64_t recs = max_points + (int64_t)max_items * kChunk;
+  const size_t fuse = fuse_scratch_layout(recs, tiles_of(*largest), nullptr, nullptr) +
+                      (size_t)max_items * 5 * 256;
+  return align256(sizeof(Batch)) + fuse +
+         clear_scratch_layout(max_points, b->tune.seg, nullptr, nullptr);
+}
+
 emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t n,
                               void* d_scratch, size_t scratch_bytes, void* stream) {
   if (!b) return fail(EMX_EINVAL, "batch is NULL");

@@ -228,24 +228,28 @@ hipError_t launch_fill_prior(const Consts& c, const Layers& L, uint32_t* ctl, in
   a.ctl = ctl;
   a.nctl = ctl ? nctl : 0;
   const int64_t n = a.cells > a.nctl ? a.cells : a.nctl;
+  TimedLaunch tl("k_fill_prior", stream);
   hipLaunchKernelGGL(k_fill_prior, dim3((unsigned)((n + kNTf - 1) / kNTf)), dim3(kNTf), 0, stream,
                      a);
   return hipGetLastError();
 }
 
 hipError_t launch_move(const Item& it, hipStream_t stream) {
+  TimedLaunch tl("k_move", stream);
   hipLaunchKernelGGL(k_move, dim3((unsigned)move_units(it.c.nx, it.c.ny)), dim3(kNTf), 0, stream,
                      it);
   return hipGetLastError();
 }
 
 hipError_t launch_normals(const Item& it, hipStream_t stream) {
+  TimedLaunch tl("k_normals", stream);
   hipLaunchKernelGGL(k_normals, dim3((unsigned)cells_units(it.c.nx, it.c.ny)), dim3(kNTf), 0,
                      stream, it);
   return hipGetLastError();
 }
 
 hipError_t launch_trav(const Item& it, hipStream_t stream) {
+  TimedLaunch tl("k_trav", stream);
   hipLaunchKernelGGL(k_trav, dim3((unsigned)cells_units(it.c.nx, it.c.ny)), dim3(kNTf), 0, stream,
                      it);
   return hipGetLastError();

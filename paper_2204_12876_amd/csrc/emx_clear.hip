@@ -61,6 +61,39 @@ __device__ __forceinline__ float f_of(const Ray& r, int k, float inv_r) {
   return kIsX ? (r.ox + t * r.dx) * inv_r : (r.oy + t * r.dy) * inv_r;
 }
 
+// Smallest k in [lo, hi] with p(k), for p false then true over [lo, hi];
+// hi + 1 if p holds nowhere.  g is a guess of the answer: p is evaluated at g
+// and its neighbour, and a binary search over the rest of the range runs only
+// if the guess is off by more than one.  The answer never depends on g.
+template <class Pred>
+__device__ __forceinline__ int first_true(int lo, int hi, int g, Pred p) {
+  g = min(max(g, lo), hi);
+  int a, b;  // answer in [a, b]; b == hi + 1 stands for "nowhere"
+  if (p(g)) {
+    if (g == lo || !p(g - 1)) return g;
+    a = lo;
+    b = g - 1;
+  } else {
+    if (g == hi) return hi + 1;
+    if (p(g + 1)) return g + 1;
+    a = g + 2;
+    b = hi + 1;
+  }
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (p(m)) b = m;
+    else a = m + 1;
+  }
+  return a;
+}
+
+// Guess of the first k at which o + (k/K) d crosses the line value w,
+// rounded up; any int if the crossing is undefined.
+__device__ __forceinline__ int crossing_guess(float o, float d, float w, int K) {
+  const double k = ((double)w - (double)o) * (double)K / (double)d;
+  return (k > -1.0 && k < 2.0e9) ? (int)ceil(k) : 1;
+}
+
 // Range [lo, hi] of k in [1, K-1] where 0 <= f(k) < lim, for f monotone in k
 // (non-decreasing if inc).  Empty range: lo > hi.
 template <bool kIsX>
@@ -73,26 +106,22 @@ __device__ __forceinline__ void axis_range(const Ray& r, int K, float inv_r, flo
   lo = 1;
   hi = K - 1;
   if (in(lo) && in(hi)) return;
-  // "v >= 0" and "v < lim" are each monotone in k: find where each holds.
-  // P(k) = (inc ? f >= 0 : f < lim) turns true once; Q(k) = (inc ? f < lim :
-  // f >= 0) turns false once.
-  int a = 1, b = K;  // first k with P(k), K if none
-  while (a < b) {
-    const int m = (a + b) >> 1;
-    const float v = f_of<kIsX>(r, m, inv_r);
-    if (inc ? (v >= 0.0f) : (v < lim)) b = m;
-    else a = m + 1;
-  }
-  lo = a;
-  a = 0;
-  b = K - 1;  // last k with Q(k), 0 if none
-  while (a < b) {
-    const int m = (a + b + 1) >> 1;
-    const float v = f_of<kIsX>(r, m, inv_r);
-    if (inc ? (v < lim) : (v >= 0.0f)) a = m;
-    else b = m - 1;
-  }
-  hi = a;
+  // "v >= 0" and "v < lim" are each monotone in k.  P(k) = (inc ? f >= 0 :
+  // f < lim) turns true once; Q(k) = (inc ? f < lim : f >= 0) turns false
+  // once.  The guesses come from the real line o + (k/K) d in metres.
+  const float o = kIsX ? r.ox : r.oy;
+  const float d = kIsX ? r.dx : r.dy;
+  const float wlim = lim / inv_r;
+  auto P = [&](int k) {
+    const float v = f_of<kIsX>(r, k, inv_r);
+    return inc ? (v >= 0.0f) : (v < lim);
+  };
+  auto notQ = [&](int k) {
+    const float v = f_of<kIsX>(r, k, inv_r);
+    return inc ? !(v < lim) : !(v >= 0.0f);
+  };
+  lo = first_true(1, K - 1, crossing_guess(o, d, inc ? 0.0f : wlim, K), P);
+  hi = first_true(1, K - 1, crossing_guess(o, d, inc ? wlim : 0.0f, K), notQ) - 1;
 }
 
 // A cell can be removed only if it is valid, older than the minimum age and
@@ -399,15 +428,22 @@ hipError_t launch_clear(const Item& it, int march_grid, hipStream_t stream) {
   const int64_t cells = (int64_t)it.c.nx * it.c.ny;
   if (it.n > 0) {
     const unsigned nray = (unsigned)((it.n + kNTc - 1) / kNTc);
-    hipLaunchKernelGGL(k_clear_setup, dim3((unsigned)it.nprep + nray), dim3(kNTc), 0, stream,
-                       it);
+    {
+      TimedLaunch tl("k_clear_setup", stream);
+      hipLaunchKernelGGL(k_clear_setup, dim3((unsigned)it.nprep + nray), dim3(kNTc), 0, stream,
+                         it);
+    }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_clear_march, dim3((unsigned)march_grid), dim3(kNTc),
-                       (size_t)it.nb * sizeof(float), stream, it);
+    {
+      TimedLaunch tl("k_clear_march", stream);
+      hipLaunchKernelGGL(k_clear_march, dim3((unsigned)march_grid), dim3(kNTc),
+                         (size_t)it.nb * sizeof(float), stream, it);
+    }
     err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
+  TimedLaunch tl("k_clear_apply", stream);
   hipLaunchKernelGGL(k_clear_apply, dim3((unsigned)((cells + kNTc - 1) / kNTc)), dim3(kNTc), 0,
                      stream, it);
   return hipGetLastError();

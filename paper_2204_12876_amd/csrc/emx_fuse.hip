@@ -9,11 +9,14 @@
 //     a pairwise tree aligned to the run start.
 //   - Writes the partials, grouped by tile, and a dense tile directory row for
 //     the chunk.
-// Pass 2, tile body: one workgroup per 32x32-cell map tile.
-//   - Stages the tile's partials from every chunk that touched it in LDS.
-//   - Adds them chunk by chunk.  A chunk holds at most one partial per cell;
-//     each wave owns a quarter of the cells and walks the chunks in order.
-//   - Applies the information-form update once per touched cell.
+// Pass 2, tile body: one workgroup per 32x32-cell map tile, one thread per cell.
+//   - Loads the tile's partials from every chunk that touched it, a group of
+//     chunks at a time, all loads of a thread issued together.
+//   - Places each partial in its cell's list in chunk order: a chunk holds at
+//     most one partial per cell, so a partial's rank is the number of earlier
+//     chunks holding its cell, read off a per-cell chunk bitmask in LDS.
+//   - Each thread adds its cell's list in chunk order and applies the
+//     information-form update once.
 //
 // The float32 sums therefore run in an order fixed by the frame alone: a
 // pairwise tree over a cell's points in point order within each chunk, then
@@ -31,25 +34,71 @@ constexpr int kSegBits = 2 * kTileLog;    // local cell within the tile
 // 32-bit keys hold (tile, local, point) while tile * kTileCells < 2^21.
 constexpr int64_t kMaxCells32 = (int64_t)1 << (32 - kPBits);
 
+// Value of v held by lane (lane ^ X) of the wave.  Lane distances below 16
+// stay within a DPP row and use row moves (quad permutes for 1 and 2; for 4
+// and 8, two masked row shifts, one per half of each group of 2X lanes);
+// larger distances use a lane permute through the LDS crossbar.
+template <int X>
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v) {
+  if constexpr (X == 1) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+  } else if constexpr (X == 2) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+  } else if constexpr (X == 4) {
+    const int t = __builtin_amdgcn_update_dpp((int)v, (int)v, 0x104, 0xF, 0x5, false);  // row_shl:4
+    return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x114, 0xF, 0xA, false);    // row_shr:4
+  } else if constexpr (X == 8) {
+    const int t = __builtin_amdgcn_update_dpp((int)v, (int)v, 0x108, 0xF, 0x3, false);  // row_shl:8
+    return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x118, 0xF, 0xC, false);    // row_shr:8
+  } else {
+    return (uint32_t)__shfl_xor((int)v, X, 64);
+  }
+}
+
+template <int X>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+  return lane_xor32<X>(v);
+}
+
+template <int X>
+__device__ __forceinline__ uint64_t lane_xor(uint64_t v) {
+  const uint32_t lo = lane_xor32<X>((uint32_t)v);
+  const uint32_t hi = lane_xor32<X>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Ascending bitonic sort of the block's 2 * kNT1 keys.  Thread t holds the
-// keys of sorted positions 2t and 2t+1 in (a, b).
-//   - Compare-exchanges across waves (stride >= 128) go through LDS.
-//   - Strides 2..64 pair lanes of one wave: they use lane shuffles.
-//   - Stride 1 stays within the thread.
-template <typename KeyT>
-__device__ __forceinline__ void bitonic_sort_regs(KeyT& a, KeyT& b, KeyT* s) {
-  const int tid = threadIdx.x;
-  const int i0 = 2 * tid;
-  for (int size = 2; size <= 2 * kNT1; size <<= 1) {
-    int stride = size >> 1;
-    if (stride >= 128) {
+// keys of sorted positions 2t and 2t+1 in (a, b).  The network is unrolled at
+// compile time over merge sizes Z and key strides S:
+//   - strides >= 128 cross waves and go through LDS with block barriers;
+//   - strides 2..64 pair lane t with lane t ^ (S / 2) of the same wave;
+//   - stride 1 stays within the thread.
+template <typename KeyT, int Z, int S>
+__device__ __forceinline__ void lane_steps(KeyT& a, KeyT& b, int i0) {
+  if constexpr (S >= 2) {
+    const KeyT pa = lane_xor<S / 2>(a);
+    const KeyT pb = lane_xor<S / 2>(b);
+    const bool up = (i0 & Z) == 0;
+    const bool keep_min = ((i0 & S) == 0) == up;
+    a = keep_min ? (a < pa ? a : pa) : (a < pa ? pa : a);
+    b = keep_min ? (b < pb ? b : pb) : (b < pb ? pb : b);
+    lane_steps<KeyT, Z, S / 2>(a, b, i0);
+  }
+}
+
+template <typename KeyT, int Z>
+__device__ __forceinline__ void bitonic_from(KeyT& a, KeyT& b, KeyT* s) {
+  if constexpr (Z <= 2 * kNT1) {
+    const int tid = threadIdx.x;
+    const int i0 = 2 * tid;
+    if constexpr (Z / 2 >= 128) {
       s[i0] = a;
       s[i0 + 1] = b;
       __syncthreads();
-      for (; stride >= 128; stride >>= 1) {
+      for (int stride = Z / 2; stride >= 128; stride >>= 1) {
         const int lo = 2 * tid - (tid & (stride - 1));
         const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
+        const bool up = (lo & Z) == 0;
         const KeyT x = s[lo];
         const KeyT y = s[hi];
         if ((x > y) == up) {
@@ -62,20 +111,20 @@ __device__ __forceinline__ void bitonic_sort_regs(KeyT& a, KeyT& b, KeyT* s) {
       b = s[i0 + 1];
       __syncthreads();
     }
-    const bool up = (i0 & size) == 0;
-    for (; stride >= 2; stride >>= 1) {
-      const KeyT pa = __shfl_xor(a, stride >> 1, 64);
-      const KeyT pb = __shfl_xor(b, stride >> 1, 64);
-      const bool keep_min = (((i0 & stride) == 0) == up);
-      a = keep_min ? (a < pa ? a : pa) : (a < pa ? pa : a);
-      b = keep_min ? (b < pb ? b : pb) : (b < pb ? pb : b);
-    }
+    lane_steps<KeyT, Z, (Z / 2 < 64 ? Z / 2 : 64)>(a, b, i0);
+    const bool up = (i0 & Z) == 0;
     if ((a > b) == up) {
       const KeyT t = a;
       a = b;
       b = t;
     }
+    bitonic_from<KeyT, 2 * Z>(a, b, s);
   }
+}
+
+template <typename KeyT>
+__device__ __forceinline__ void bitonic_sort_regs(KeyT& a, KeyT& b, KeyT* s) {
+  bitonic_from<KeyT, 2>(a, b, s);
 }
 
 // ------------------------------------------------------------------ pass 1
@@ -257,56 +306,53 @@ __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
 }
 
 // ------------------------------------------------------------------ pass 2
-constexpr int kNT2 = 256;
-constexpr int kCap = 4096;     // partials held in LDS per round
-constexpr int kWin = kNT2;     // directory entries read per window
+constexpr int kNT2 = 1024;                 // pass-2 threads: one per cell of the tile
+static_assert(kNT2 == kTileCells, "pass 2 gives each thread one cell of the tile");
+constexpr int kCap = 4096;                 // partials staged per group
+constexpr int kPer = kCap / kNT2;          // partials each thread loads per group
+constexpr int kGroupChunks = 128;          // chunks per group
+constexpr int kMaskWords = kGroupChunks / 32;
+constexpr int kWin = kNT2;                 // directory entries read per window
 
 __device__ __forceinline__ void tile_body(const Item& it, int t) {
-  __shared__ float acc_w[kTileCells];
-  __shared__ float acc_wz[kTileCells];
-  __shared__ uint8_t hit[kTileCells];
-  __shared__ uint32_t e_chunk[kWin];
-  __shared__ uint32_t e_start[kWin];
-  __shared__ uint32_t e_cnt[kWin];
-  __shared__ uint32_t e_pre[kWin + 1];
-  __shared__ uint16_t u_l[kCap];
-  __shared__ float u_w[kCap];
-  __shared__ float u_wz[kCap];
+  __shared__ uint32_t s_mask[kMaskWords][kTileCells];  // chunks of the group holding each cell
+  __shared__ uint32_t s_start[kTileCells];             // per cell: count, then first slot
+  __shared__ float s_w[kCap];                          // the group's partials by (cell, chunk)
+  __shared__ float s_wz[kCap];
+  __shared__ uint32_t e_chunk[kWin];                   // touching chunks of the window
+  __shared__ uint32_t e_dir[kWin];                     // their directory words
+  __shared__ uint32_t e_pre[kWin + 1];                 // prefix of their partial counts
   __shared__ int s_isum[kNT2 / 64];
   __shared__ int s_g1;
 
-  const int tid = threadIdx.x;
+  const int l = threadIdx.x;  // the cell of the tile this thread owns
   const int B = it.B;
   const int T = it.T;
-  for (int l = tid; l < kTileCells; l += kNT2) {
-    acc_w[l] = 0.0f;
-    acc_wz[l] = 0.0f;
-    hit[l] = 0;
-  }
+  float acc_w = 0.0f;
+  float acc_wz = 0.0f;
+  bool hit = false;
 
   for (int k0 = 0; k0 < B; k0 += kWin) {
     // compact the chunks of this window that touched the tile, in chunk order
-    const int kk = k0 + tid;
+    const int kk = k0 + l;
     const uint32_t d = (kk < B) ? it.fs.dir[(int64_t)kk * T + t] : 0u;
     int L = 0;
     const int pos = block_exclusive_sum<kNT2>(d != 0u ? 1 : 0, L, s_isum);
     if (d != 0u) {
       e_chunk[pos] = (uint32_t)kk;
-      e_start[pos] = d >> 16;
-      e_cnt[pos] = d & 0xFFFFu;
+      e_dir[pos] = d;
     }
     __syncthreads();
     if (L == 0) continue;
     int totw = 0;
-    const int pre = block_exclusive_sum<kNT2>(tid < L ? (int)e_cnt[tid] : 0, totw, s_isum);
-    if (tid < L) e_pre[tid] = (uint32_t)pre;
-    if (tid == 0) e_pre[L] = (uint32_t)totw;
+    const int pre = block_exclusive_sum<kNT2>(l < L ? (int)(e_dir[l] & 0xFFFFu) : 0, totw, s_isum);
+    if (l < L) e_pre[l] = (uint32_t)pre;
+    if (l == 0) e_pre[L] = (uint32_t)totw;
     __syncthreads();
-    int g0 = 0;
-    while (g0 < L) {
-      // largest group [g0, g1) whose partials fit in LDS
-      if (tid == 0) {
-        int lo = g0 + 1, hi = L;
+    for (int g0 = 0; g0 < L;) {
+      // the group: chunks [g0, g1), at most kGroupChunks of them and kCap partials
+      if (l == 0) {
+        int lo = g0 + 1, hi = min(L, g0 + kGroupChunks);
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
           if (e_pre[mid] - e_pre[g0] <= (uint32_t)kCap) lo = mid;
@@ -314,68 +360,95 @@ __device__ __forceinline__ void tile_body(const Item& it, int t) {
         }
         s_g1 = lo;
       }
+#pragma unroll
+      for (int w = 0; w < kMaskWords; ++w) s_mask[w][l] = 0u;
+      s_start[l] = 0u;
       __syncthreads();
       const int g1 = s_g1;
       const uint32_t pbase = e_pre[g0];
       const int tot = (int)(e_pre[g1] - pbase);
-      // stage this group's partials in LDS, in (chunk, cell) order
-      for (int p = tid; p < tot; p += kNT2) {
-        const uint32_t gp = pbase + (uint32_t)p;
-        int lo = g0, hi = g1 - 1;  // last entry whose prefix is <= gp
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (e_pre[mid] <= gp) lo = mid;
-          else hi = mid - 1;
-        }
-        const int64_t idx = (int64_t)e_chunk[lo] * kChunk + e_start[lo] + (gp - e_pre[lo]);
-        u_l[p] = it.fs.rec_local[idx];
-        u_w[p] = it.fs.rec_w[idx];
-        u_wz[p] = it.fs.rec_wz[idx];
-      }
-      __syncthreads();
-      // chunk by chunk.  A chunk holds at most one partial per cell, and wave w
-      // owns the cells l with l % 4 == w: each wave walks every chunk segment in
-      // chunk order and adds its own cells' partials.  Program order within the
-      // wave keeps chunk order, so no block barrier is needed between chunks.
-      {
-        const int wid = tid >> 6;
-        const int lane = tid & 63;
-        for (int g = g0; g < g1; ++g) {
-          const int p0 = (int)(e_pre[g] - pbase);
-          const int p1 = (int)(e_pre[g + 1] - pbase);
-          for (int p = p0 + lane; p < p1; p += 64) {
-            const int l = u_l[p];
-            if ((l & (kNT2 / 64 - 1)) != wid) continue;
-            acc_w[l] = acc_w[l] + u_w[p];
-            acc_wz[l] = acc_wz[l] + u_wz[p];
-            hit[l] = 1;
+
+      // load this thread's partials; every load is issued before any is used
+      int pg[kPer], pl[kPer];
+      float pw[kPer], pwz[kPer];
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int p = l + j * kNT2;
+        pg[j] = -1;
+        pl[j] = 0;
+        pw[j] = 0.0f;
+        pwz[j] = 0.0f;
+        if (p < tot) {
+          const uint32_t gp = pbase + (uint32_t)p;
+          int lo = g0, hi = g1 - 1;  // the chunk whose partials include gp
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (e_pre[mid] <= gp) lo = mid;
+            else hi = mid - 1;
           }
+          pg[j] = lo;
+          const int64_t idx =
+              (int64_t)e_chunk[lo] * kChunk + (e_dir[lo] >> 16) + (gp - e_pre[lo]);
+          pl[j] = it.fs.rec_local[idx];
+          pw[j] = it.fs.rec_w[idx];
+          pwz[j] = it.fs.rec_wz[idx];
         }
       }
+      // which chunks of the group hold each cell (a chunk holds a cell at most once)
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        if (pg[j] < 0) continue;
+        const int gg = pg[j] - g0;
+        atomicOr(&s_mask[gg >> 5][pl[j]], 1u << (gg & 31));
+        atomicAdd(&s_start[pl[j]], 1u);
+      }
       __syncthreads();
+      const int my_cnt = (int)s_start[l];
+      int all = 0;
+      const int my_start = block_exclusive_sum<kNT2>(my_cnt, all, s_isum);
+      s_start[l] = (uint32_t)my_start;
+      __syncthreads();
+      // each partial's slot: its cell's first slot plus the number of earlier
+      // chunks of the group that hold the cell
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        if (pg[j] < 0) continue;
+        const int gg = pg[j] - g0;
+        const int c = pl[j];
+        int rank = __popc(s_mask[gg >> 5][c] & ((1u << (gg & 31)) - 1u));
+        for (int w = 0; w < (gg >> 5); ++w) rank += __popc(s_mask[w][c]);
+        const int slot = (int)s_start[c] + rank;
+        s_w[slot] = pw[j];
+        s_wz[slot] = pwz[j];
+      }
+      __syncthreads();
+      // the owned cell's partials, in chunk order
+      for (int k = 0; k < my_cnt; ++k) {
+        acc_w = acc_w + s_w[my_start + k];
+        acc_wz = acc_wz + s_wz[my_start + k];
+      }
+      hit = hit || my_cnt > 0;
+      __syncthreads();  // the next group reuses the arrays
       g0 = g1;
     }
   }
-  __syncthreads();
+  if (!hit) return;
 
-  // ---- information-form update of every touched cell
+  // ---- information-form update of the owned cell
   const int tx = t % it.tiles_x;
   const int ty = t / it.tiles_x;
-  for (int l = tid; l < kTileCells; l += kNT2) {
-    if (!hit[l]) continue;
-    const int ix = (tx << kTileLog) + (l & (kTile - 1));
-    const int iy = (ty << kTileLog) + (l >> kTileLog);
-    const int64_t cell = (int64_t)iy * it.c.nx + ix;
-    const float h0 = it.L.h[cell];
-    const float v0 = it.L.v[cell];
-    const float W = (1.0f / v0) + acc_w[l];
-    const float v1 = 1.0f / W;
-    const float h1 = ((h0 / v0) + acc_wz[l]) * v1;
-    it.L.h[cell] = h1;
-    it.L.v[cell] = v1;
-    it.L.t[cell] = it.t_now;
-    it.L.valid[cell] = 1;
-  }
+  const int ix = (tx << kTileLog) + (l & (kTile - 1));
+  const int iy = (ty << kTileLog) + (l >> kTileLog);
+  const int64_t cell = (int64_t)iy * it.c.nx + ix;
+  const float h0 = it.L.h[cell];
+  const float v0 = it.L.v[cell];
+  const float W = (1.0f / v0) + acc_w;
+  const float v1 = 1.0f / W;
+  const float h1 = ((h0 / v0) + acc_wz) * v1;
+  it.L.h[cell] = h1;
+  it.L.v[cell] = v1;
+  it.L.t[cell] = it.t_now;
+  it.L.valid[cell] = 1;
 }
 
 // ---------------------------------------------------------------- launches
@@ -436,12 +509,16 @@ size_t fuse_scratch_layout(int64_t max_points, int T, char* base, FuseScratch* o
 
 hipError_t launch_fuse(const Item& it, hipStream_t stream) {
   if (it.n <= 0) return hipSuccess;
-  if (fuse_needs_key64(it.T))
-    hipLaunchKernelGGL(k_fuse_chunk<uint64_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
-  else
-    hipLaunchKernelGGL(k_fuse_chunk<uint32_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
+  {
+    TimedLaunch tl("k_fuse_chunk", stream);
+    if (fuse_needs_key64(it.T))
+      hipLaunchKernelGGL(k_fuse_chunk<uint64_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
+    else
+      hipLaunchKernelGGL(k_fuse_chunk<uint32_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
+  }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
+  TimedLaunch tl("k_fuse_tile", stream);
   hipLaunchKernelGGL(k_fuse_tile, dim3(it.T), dim3(kNT2), 0, stream, it);
   return hipGetLastError();
 }

@@ -13,6 +13,20 @@
 
 namespace emx {
 
+// Brackets one plain kernel launch with timing events on its stream while
+// timing is on (emx_timing_begin); does nothing otherwise.
+class TimedLaunch {
+ public:
+  TimedLaunch(const char* name, hipStream_t s);
+  ~TimedLaunch();
+  TimedLaunch(const TimedLaunch&) = delete;
+  TimedLaunch& operator=(const TimedLaunch&) = delete;
+
+ private:
+  hipStream_t stream_;
+  long idx_;
+};
+
 // ------------------------------------------------------------------ fusion
 int tiles_x_of(int nx);
 int tiles_y_of(int ny);

@@ -1,0 +1,420 @@
+"""Continuous-batching server for many robots' elevation maps on one GPU.
+
+Robots submit frames (host point clouds with pose, time and map centre) as they
+arrive.  The server
+  * keeps every admitted map's state resident in device memory;
+  * admits maps against a fixed device-memory budget, which also covers a pool
+    for staging frames on the device and each lane's batch scratch;
+  * keeps per-map FIFO order with at most one frame of a map in flight, since
+    each frame updates its map's state;
+  * whenever a lane is free, forms a batch from the oldest waiting frames of
+    maps not in flight (up to the item limit and the staging room) and
+    launches it at once.  It does not wait for a batch to fill: frames that
+    arrive while other batches run join the next one (continuous batching).
+  * runs lanes on separate streams, so one batch's host-to-device copies and
+    kernels overlap another's.
+
+Each batch runs the whole per-frame path (move, fusion, clearing, normals,
+traversability) through emx_pipeline_batch.  That call gives every map the
+same bits it would get from the plain per-frame calls, so a frame's result does
+not depend on the batch it rode in.
+
+The device side sits behind a small executor interface (GpuExecutor here), so
+scheduling and admission can also run against a simulated executor.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import _emx
+
+__all__ = ["AdmissionError", "HbmBudget", "Request", "Server", "GpuExecutor", "FramePool",
+           "run_trace", "run_plain_trace", "latency_summary"]
+
+
+class AdmissionError(RuntimeError):
+    """A map or frame does not fit the device-memory budget or the limits."""
+
+
+class HbmBudget:
+    """Byte accounting of device memory against a fixed budget."""
+
+    def __init__(self, total: int):
+        self.total = int(total)
+        self.parts: Dict[object, int] = {}
+
+    @property
+    def used(self) -> int:
+        return sum(self.parts.values())
+
+    @property
+    def free(self) -> int:
+        return self.total - self.used
+
+    def reserve(self, key, nbytes: int):
+        if key in self.parts:
+            raise KeyError(f"{key!r} already reserved")
+        if nbytes > self.free:
+            raise AdmissionError(f"{key!r} needs {nbytes} bytes; {self.free} of {self.total} free")
+        self.parts[key] = int(nbytes)
+
+    def release(self, key):
+        self.parts.pop(key)
+
+
+class FramePool:
+    """First-fit allocator over one device region that stages frames.
+
+    Offsets and sizes are in float32 elements.  Free blocks are kept sorted
+    and merged with their neighbours on release."""
+
+    def __init__(self, capacity: int):
+        self.capacity = int(capacity)
+        self.free_blocks = [(0, self.capacity)] if capacity > 0 else []
+
+    def alloc(self, size: int) -> Optional[int]:
+        size = max(int(size), 1)
+        size = (size + 63) & ~63            # 256-byte granules
+        for k, (off, sz) in enumerate(self.free_blocks):
+            if sz >= size:
+                if sz == size:
+                    self.free_blocks.pop(k)
+                else:
+                    self.free_blocks[k] = (off + size, sz - size)
+                return off
+        return None
+
+    def release(self, off: int, size: int):
+        size = (max(int(size), 1) + 63) & ~63
+        fb = self.free_blocks
+        lo, hi = 0, len(fb)
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if fb[mid][0] < off:
+                lo = mid + 1
+            else:
+                hi = mid
+        fb.insert(lo, (off, size))
+        # merge with the right, then the left neighbour
+        if lo + 1 < len(fb) and fb[lo][0] + fb[lo][1] == fb[lo + 1][0]:
+            fb[lo] = (fb[lo][0], fb[lo][1] + fb[lo + 1][1])
+            fb.pop(lo + 1)
+        if lo > 0 and fb[lo - 1][0] + fb[lo - 1][1] == fb[lo][0]:
+            fb[lo - 1] = (fb[lo - 1][0], fb[lo - 1][1] + fb[lo][1])
+            fb.pop(lo)
+
+    @property
+    def largest_free(self) -> int:
+        return max((s for _, s in self.free_blocks), default=0)
+
+    @property
+    def free_total(self) -> int:
+        return sum(s for _, s in self.free_blocks)
+
+
+@dataclasses.dataclass
+class Request:
+    """One frame of one robot.  xyz: host float32 [3, n] (pinned for overlap)."""
+    robot: object
+    xyz: torch.Tensor
+    pose: np.ndarray
+    t_ms: int
+    center: tuple
+    arrival: float                  # seconds on the server clock
+    seq: int = 0
+    launch: float = math.nan        # when its batch was enqueued
+    done: float = math.nan          # when its batch finished on the device
+    batch: int = -1
+    lane: int = -1
+    batch_items: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.xyz.shape[1])
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class _Lane:
+    def __init__(self, k: int):
+        self.k = k
+        self.requests: List[Request] = []
+        self.regions: List[tuple] = []
+        self.busy = False
+
+
+class Server:
+    """Scheduler and admission over an executor (GpuExecutor or a simulation).
+
+    The executor provides: map_bytes(params), create_map(robot, params, cx, cy,
+    t0), drop_map(robot), lanes, pool_floats, lane_bytes, max_items,
+    max_batch_points, now(), launch(lane, requests, regions, batch_id),
+    done(lane), finish_time(lane)."""
+
+    def __init__(self, executor, budget_bytes: int):
+        self.ex = executor
+        self.budget = HbmBudget(budget_bytes)
+        self.budget.reserve("frame pool", 4 * executor.pool_floats)
+        for k in range(executor.lanes):
+            self.budget.reserve(("lane", k), executor.lane_bytes)
+        self.pool = FramePool(executor.pool_floats)
+        self.lanes = [_Lane(k) for k in range(executor.lanes)]
+        self.maps: Dict[object, int] = {}
+        self.waiting: Dict[object, collections.deque] = {}
+        self.inflight: set = set()
+        self.completed: List[Request] = []
+        self.batches = 0
+        self.batch_sizes: List[int] = []
+
+    # ------------------------------------------------------------ admission
+    def add_map(self, robot, params: dict, cx: float = 0.0, cy: float = 0.0, t0_ms: int = 0):
+        """Admit a robot's map if its state fits the budget; else AdmissionError."""
+        if robot in self.maps:
+            raise KeyError(f"robot {robot!r} already has a map")
+        nbytes = int(self.ex.map_bytes(params))
+        self.budget.reserve(("map", robot), nbytes)
+        try:
+            self.ex.create_map(robot, params, cx, cy, t0_ms)
+        except Exception:
+            self.budget.release(("map", robot))
+            raise
+        self.maps[robot] = nbytes
+        self.waiting[robot] = collections.deque()
+
+    def remove_map(self, robot):
+        if robot in self.inflight or self.waiting.get(robot):
+            raise RuntimeError(f"robot {robot!r} still has frames queued or in flight")
+        self.ex.drop_map(robot)
+        self.budget.release(("map", robot))
+        del self.maps[robot]
+        del self.waiting[robot]
+
+    def submit(self, req: Request):
+        if req.robot not in self.maps:
+            raise AdmissionError(f"robot {req.robot!r} has no admitted map")
+        if req.n > self.ex.max_batch_points or 3 * req.n > self.pool.capacity:
+            raise AdmissionError(f"frame of {req.n} points exceeds the staging limits")
+        self.waiting[req.robot].append(req)
+
+    # ----------------------------------------------------------- scheduling
+    def pending(self) -> int:
+        return sum(len(q) for q in self.waiting.values())
+
+    def idle(self) -> bool:
+        return not self.inflight and self.pending() == 0
+
+    def _retire(self):
+        for ln in self.lanes:
+            if ln.busy and self.ex.done(ln.k):
+                t = self.ex.finish_time(ln.k)
+                for r in ln.requests:
+                    r.done = t
+                    self.inflight.discard(r.robot)
+                    self.completed.append(r)
+                for off, size in ln.regions:
+                    self.pool.release(off, size)
+                ln.requests, ln.regions, ln.busy = [], [], False
+
+    def _form(self) -> List[Request]:
+        heads = sorted((q[0].arrival, q[0].seq, robot) for robot, q in self.waiting.items()
+                       if q and robot not in self.inflight)
+        picked, points = [], 0
+        for _, _, robot in heads:
+            r = self.waiting[robot][0]
+            if len(picked) == self.ex.max_items:
+                break
+            if points + r.n > self.ex.max_batch_points:
+                continue
+            picked.append(r)
+            points += r.n
+        return picked
+
+    def poll(self) -> int:
+        """Retire finished batches, then fill every free lane.  Returns the
+        number of batches launched."""
+        self._retire()
+        launched = 0
+        for ln in self.lanes:
+            if ln.busy:
+                continue
+            reqs = self._form()
+            if not reqs:
+                break
+            regions, taken = [], []
+            for r in reqs:
+                off = self.pool.alloc(3 * r.n)
+                if off is None:
+                    continue                      # waits for staging room
+                regions.append((off, 3 * r.n))
+                taken.append(r)
+            if not taken:
+                break
+            now = self.ex.now()
+            for r in taken:
+                self.waiting[r.robot].popleft()
+                self.inflight.add(r.robot)
+                r.launch = now
+                r.batch = self.batches
+                r.lane = ln.k
+                r.batch_items = len(taken)
+            self.ex.launch(ln.k, taken, [o for o, _ in regions], self.batches)
+            ln.requests, ln.regions, ln.busy = taken, regions, True
+            self.batches += 1
+            self.batch_sizes.append(len(taken))
+            launched += 1
+        return launched
+
+
+# ---------------------------------------------------------------- GPU side
+class GpuExecutor:
+    """Device side of the server: resident maps, a staging pool, and one
+    stream, batch executor and scratch buffer per lane."""
+
+    def __init__(self, largest_params: dict, lanes: int = 2, max_items: int = 64,
+                 max_batch_points: int = 4_000_000, pool_points: int = 16_000_000,
+                 weights: torch.Tensor = None, tuning: str = None, device=None):
+        from . import PipelineBatch, aligned_empty
+        self.device = torch.device(device if device is not None else "cuda")
+        self.lanes = int(lanes)
+        self.max_items = int(max_items)
+        self.max_batch_points = int(max_batch_points)
+        self.pool_floats = 3 * int(pool_points)
+        self.weights = weights
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.lanes)]
+        self.execs = [PipelineBatch(tuning, device=self.device) for _ in range(self.lanes)]
+        bound = _emx.batch_scratch_bound(self.execs[0].handle, _emx.make_params(largest_params),
+                                         self.max_items, self.max_batch_points)
+        if bound == 0:
+            raise AdmissionError(_emx.last_error())
+        self.lane_bytes = int(bound)
+        for ex in self.execs:
+            ex.reserve(bound)
+        self.pool = aligned_empty(4 * self.pool_floats, self.device).view(torch.float32)
+        self.ends = [torch.cuda.Event(enable_timing=True) for _ in range(self.lanes)]
+        self.maps = {}
+        self.t0_event = torch.cuda.Event(enable_timing=True)
+        self.t0_host = None
+        self.start_clock()
+
+    def start_clock(self):
+        torch.cuda.synchronize(self.device)
+        self.t0_event.record(torch.cuda.current_stream(self.device))
+        self.t0_event.synchronize()
+        self.t0_host = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0_host
+
+    def map_bytes(self, params: dict) -> int:
+        return _emx.state_bytes(_emx.make_params(params))
+
+    def create_map(self, robot, params, cx, cy, t0):
+        from . import ElevationMap
+        self.maps[robot] = ElevationMap(params, cx, cy, t0, device=self.device)
+
+    def drop_map(self, robot):
+        self.maps.pop(robot).close()
+
+    def launch(self, lane: int, requests, offsets, batch_id):
+        st = self.streams[lane]
+        base = self.pool.data_ptr()
+        items = (_emx.BatchItem * len(requests))()
+        with torch.cuda.stream(st):
+            for k, (r, off) in enumerate(zip(requests, offsets)):
+                n = r.n
+                if n:
+                    self.pool[off:off + 3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
+                it = items[k]
+                it.map = self.maps[r.robot].handle
+                it.frame = _emx.make_frame(base + 4 * off, base + 4 * (off + n),
+                                           base + 4 * (off + 2 * n), n, r.pose, r.t_ms)
+                it.cx, it.cy = float(r.center[0]), float(r.center[1])
+                it.d_weights = self.weights.data_ptr() if self.weights is not None else None
+                it.stages = _emx.STAGE_ALL if self.weights is not None else \
+                    _emx.STAGE_ALL & ~_emx.STAGE_TRAV
+            self.execs[lane].run_items(items, len(requests), st.cuda_stream)
+            self.ends[lane].record(st)
+
+    def done(self, lane: int) -> bool:
+        return self.ends[lane].query()
+
+    def finish_time(self, lane: int) -> float:
+        return self.t0_event.elapsed_time(self.ends[lane]) / 1e3
+
+
+def run_trace(server: Server, requests: List[Request], timeout_s: float = 120.0):
+    """Feed requests at their arrival times (server clock) until all finish."""
+    reqs = sorted(requests, key=lambda r: (r.arrival, r.seq))
+    if hasattr(server.ex, "start_clock"):
+        server.ex.start_clock()
+    i = 0
+    t_end = server.ex.now() + timeout_s
+    while i < len(reqs) or not server.idle():
+        now = server.ex.now()
+        while i < len(reqs) and reqs[i].arrival <= now:
+            server.submit(reqs[i])
+            i += 1
+        server.poll()
+        if now > t_end:
+            raise TimeoutError("trace did not finish")
+    return reqs
+
+
+def run_plain_trace(maps: dict, requests: List[Request], weights: torch.Tensor, device=None,
+                    max_points: int = 1_000_000):
+    """The per-frame baseline: each frame, at its arrival, is copied to the
+    device and run through the plain calls on one stream (no batching)."""
+    from . import aligned_empty
+    device = torch.device(device if device is not None else "cuda")
+    reqs = sorted(requests, key=lambda r: (r.arrival, r.seq))
+    st = torch.cuda.current_stream(device)
+    stage = aligned_empty(12 * max_points, device).view(torch.float32)
+    # one scratch buffer serves every map: the calls run in order on one stream
+    need = max(_emx.scratch_bytes(m.p, max_points) for m in maps.values())
+    scratch = aligned_empty(need, device)
+    ends = []
+    torch.cuda.synchronize(device)
+    t0e = torch.cuda.Event(enable_timing=True)
+    t0e.record(st)
+    t0e.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        while time.perf_counter() - t0 < r.arrival:
+            pass
+        m = maps[r.robot]
+        n = r.n
+        stage[:3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
+        x, y, z = stage[:n], stage[n:2 * n], stage[2 * n:3 * n]
+        r.launch = time.perf_counter() - t0
+        m.move_map(*r.center)
+        m.fuse_points(x, y, z, r.pose, r.t_ms, scratch=scratch)
+        m.clear_visibility(x, y, z, r.pose, r.t_ms, scratch=scratch)
+        m.compute_normals()
+        if weights is not None:
+            m.traversability(weights)
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(st)
+        ends.append((r, e))
+    torch.cuda.synchronize(device)
+    for r, e in ends:
+        r.done = t0e.elapsed_time(e) / 1e3
+    return reqs
+
+
+def latency_summary(reqs: List[Request]) -> dict:
+    lat = np.array([r.latency for r in reqs]) * 1e3
+    pts = sum(r.n for r in reqs)
+    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    return dict(frames=len(reqs), points=int(pts), span_s=float(span),
+                points_per_s=float(pts / span) if span > 0 else math.nan,
+                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                max_ms=float(lat.max()), mean_ms=float(lat.mean()))

@@ -458,6 +458,27 @@ def cfg3_rigs(n_robots: int = 64, seed_offset: int = 0):
     return robots
 
 
+def cfg3(device="cpu", n_robots: int = 64, n_frames: int = 1, seed_offset: int = 0):
+    """Frames for the robots of cfg3_rigs: each robot gets its own terrain
+    (20 boxes), a seeded trajectory and ``n_frames`` frames of its drawn size
+    from the mixed rig, 3% outliers.  Arrival times are drawn by the caller."""
+    items = []
+    for rb in cfg3_rigs(n_robots, seed_offset):
+        rng = np.random.default_rng(rb["seed"])
+        spec = rb["spec"]
+        terrain = make_terrain(rng, n_boxes=20, extent=0.5 * spec.nx * spec.resolution)
+        poses = Trajectory(rng, terrain).poses(n_frames)
+        frames, centers = [], []
+        for f, P in enumerate(poses):
+            rig = _mixed_rig(rng, rb["n_points"])
+            frames.append(make_frame(rng, terrain, P, rig, t_ms=100 * f, outlier_frac=0.03,
+                                     device=device))
+            centers.append((float(P[0, 3]), float(P[1, 3])))
+        items.append(dict(spec=spec, params=default_params(spec), frames=frames,
+                          centers=centers, rate_hz=rb["rate_hz"]))
+    return dict(items=items, weights=trav_weights())
+
+
 def cfg4(n_frames: int = 50, device="cpu", n_points: int = 4_000_000, seed_offset: int = 0):
     """2000x2000 map at 0.02 m; 4M-point frames from a 128-beam LiDAR (elevations
     U[-25, +15] deg, range 30 m); 10% outliers; 500 boxes."""
