@@ -4,12 +4,16 @@
 // The host fills a Batch table in pinned memory:
 //   - each item's state pointers, geometry and constants;
 //   - per stage, the prefix of work units over the items.
-// One graph then runs:
-//   - a copy of the table into the caller's scratch;
-//   - one persistent launch per stage: move, fusion pass 1, fusion pass 2,
-//     clearing setup, march and apply, then normals + traversability.
-// Every launch has a fixed grid and finds its work in the table, so the
-// captured graph is replayed for every batch that uses the same scratch buffer.
+// Then, on the caller's stream:
+//   - one copy of the table's header and its n items into the caller's
+//     scratch;
+//   - one graph of seven persistent launches: move, fusion pass 1, fusion
+//     pass 2, clearing setup, march and apply, then normals + traversability.
+// Every launch finds its work in the table, so a graph depends only on the
+// scratch address, the sort key width and the grid sizes.  Each stage's grid
+// is the tuned size capped at the stage's work rounded up to a power of two,
+// so a small batch does not launch thousands of idle workgroups, and few
+// distinct graphs arise.  Captured graphs are kept in a small LRU cache.
 // Two pinned tables alternate: the host fills one while the other may still
 // be read by the previous batch's copy.
 //
@@ -18,6 +22,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <cstddef>
 #include <cstdio>
 #include <new>
 
@@ -59,8 +64,21 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct GraphKey {
   void* scratch;
   int key64;
-  int buf;
+  int grid[7];
+
+  bool operator==(const GraphKey& o) const {
+    if (scratch != o.scratch || key64 != o.key64) return false;
+    for (int i = 0; i < 7; ++i)
+      if (grid[i] != o.grid[i]) return false;
+    return true;
+  }
 };
+
+int pow2_at_least(int64_t x) {
+  int g = 1;
+  while (g < x && g < (1 << 30)) g <<= 1;
+  return g;
+}
 
 }  // namespace
 
@@ -71,8 +89,8 @@ struct emx_batch {
   bool used[2];
   int next;
   hipStream_t cap;     // private stream for graph capture
-  static constexpr int kCache = 8;
-  GraphKey keys[kCache];
+  static constexpr int kCache = 16;
+  GraphKey keys[kCache];  // most recently used last
   hipGraphExec_t execs[kCache];
   int ncache;
 };
@@ -102,10 +120,14 @@ int64_t frame_points(const emx_batch_item& b) {
   return (b.stages & (EMX_STAGE_FUSE | EMX_STAGE_CLEAR)) ? b.frame.n : 0;
 }
 
-// Scratch layout: the device table, each item's fusion scratch, then one
-// clearing queue shared by the batch.
+// Scratch layout: the device table, the clearing queue counters (zeroed by the
+// batch's first launch), each item's fusion scratch, then one clearing queue
+// shared by the batch.
+constexpr size_t kCounterOffset = (sizeof(Batch) + 255) & ~(size_t)255;
+constexpr size_t kCounterBytes = kCtrWords * sizeof(uint32_t);
+
 size_t batch_layout(const emx_batch_item* items, int32_t n, int seg, char* base, Batch* tab) {
-  size_t off = align256(sizeof(Batch));
+  size_t off = align256(kCounterOffset + kCounterBytes);
   int64_t rays = 0;
   for (int32_t i = 0; i < n; ++i) {
     const int64_t np = frame_points(items[i]);
@@ -123,7 +145,7 @@ size_t batch_layout(const emx_batch_item* items, int32_t n, int seg, char* base,
   if (tab && base)
     for (int32_t i = 0; i < n; ++i) {
       tab->items[i].cq = cq;
-      tab->items[i].cq.counter = nullptr;  // set once the device table's address is known
+      tab->items[i].cq.counter = (uint32_t*)(base + kCounterOffset);
     }
   return off + c;
 }
@@ -228,7 +250,7 @@ size_t emx_batch_scratch_bound(const emx_batch* b, const emx_params* largest, in
   const int64_t recs = max_points + (int64_t)max_items * kChunk;
   const size_t fuse = fuse_scratch_layout(recs, tiles_of(*largest), nullptr, nullptr) +
                       (size_t)max_items * 5 * 256;
-  return align256(sizeof(Batch)) + fuse +
+  return align256(kCounterOffset + kCounterBytes) + fuse +
          clear_scratch_layout(max_points, b->tune.seg, nullptr, nullptr);
 }
 
@@ -261,7 +283,8 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
     if (e != hipSuccess) return hip_fail(e, "pipeline_batch");
   }
   Batch* tab = b->host[buf];
-  memset(tab, 0, sizeof(Batch));
+  const size_t upload = offsetof(Batch, items) + (size_t)n * sizeof(Item);
+  memset(tab, 0, upload);
   tab->n = n;
   Batch* d_tab = (Batch*)d_scratch;
   bool key64 = false;
@@ -302,10 +325,11 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
   }
   batch_layout(items, n, b->tune.seg, (char*)d_scratch, tab);
   tab->key64 = key64 ? 1 : 0;
+  int64_t clear_rays = 0;
   for (int32_t i = 0; i < n; ++i) {
     Item& it = tab->items[i];
-    it.cq.counter = d_tab->counter;
     it.cq.seg = b->tune.seg;
+    if (it.stages & EMX_STAGE_CLEAR) clear_rays += it.n;
     const uint32_t st = it.stages;
     const int64_t C = (int64_t)it.c.nx * it.c.ny;
     const bool moved = (st & EMX_STAGE_MOVE) && (it.sx != 0 || it.sy != 0);
@@ -322,24 +346,40 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
         ((st & (EMX_STAGE_NORMALS | EMX_STAGE_TRAV)) ? cells_units(it.c.nx, it.c.ny) : 0);
   }
 
-  // ---- enqueue: a cached graph, or the same sequence directly
-  hipStream_t st = (hipStream_t)stream;
+  // ---- grids: the tuned size, capped at the stage's work (power of two);
+  // the march gets about two threads per ray
   const Tuning& t = b->tune;
-  auto enqueue = [&](hipStream_t q) -> hipError_t {
-    hipError_t e = hipMemcpyAsync(d_tab, tab, sizeof(Batch), hipMemcpyHostToDevice, q);
-    if (e == hipSuccess) e = launch_move_batch(d_tab, t.grid_move, q);
-    if (e == hipSuccess) e = launch_fuse_batch(d_tab, key64, t.grid_chunk, t.grid_tile, q);
-    if (e == hipSuccess) e = launch_clear_batch(d_tab, t.grid_setup, t.grid_march, t.grid_apply, q);
-    if (e == hipSuccess) e = launch_cells_batch(d_tab, t.grid_cells, q);
-    return e;
+  auto cap = [](int tuned, int64_t units) {
+    return (int)(units < 1 ? 1 : (pow2_at_least(units) < tuned ? pow2_at_least(units) : tuned));
   };
+  GraphKey key;
+  key.scratch = d_scratch;
+  key.key64 = key64 ? 1 : 0;
+  key.grid[0] = cap(t.grid_move, tab->off[kBMove][n]);
+  key.grid[1] = cap(t.grid_chunk, tab->off[kBChunk][n]);
+  key.grid[2] = cap(t.grid_tile, tab->off[kBTile][n]);
+  key.grid[3] = cap(t.grid_setup, tab->off[kBSetup][n]);
+  key.grid[4] = cap(t.grid_march, (2 * clear_rays + 255) / 256);
+  key.grid[5] = cap(t.grid_apply, tab->off[kBApply][n]);
+  key.grid[6] = cap(t.grid_cells, tab->off[kBCells][n]);
+
+  // ---- enqueue: the table upload, then a cached graph or the same launches
+  hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipSuccess;
+  e = hipMemcpyAsync(d_tab, tab, upload, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "pipeline_batch: table upload");
+  auto enqueue = [&](hipStream_t q) -> hipError_t {
+    hipError_t r = launch_move_batch(d_tab, key.grid[0], q);
+    if (r == hipSuccess) r = launch_fuse_batch(d_tab, key64, key.grid[1], key.grid[2], q);
+    if (r == hipSuccess)
+      r = launch_clear_batch(d_tab, key.grid[3], key.grid[4], key.grid[5], q);
+    if (r == hipSuccess) r = launch_cells_batch(d_tab, key.grid[6], q);
+    return r;
+  };
   if (t.graph) {
     int slot = -1;
     for (int k = 0; k < b->ncache; ++k)
-      if (b->keys[k].scratch == d_scratch && b->keys[k].key64 == (int)key64 &&
-          b->keys[k].buf == buf)
-        slot = k;
+      if (b->keys[k] == key) slot = k;
     if (slot < 0) {
       hipGraph_t g = nullptr;
       hipGraphExec_t ex = nullptr;
@@ -352,7 +392,7 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
       if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
       if (g) (void)hipGraphDestroy(g);
       if (e != hipSuccess) return hip_fail(e, "pipeline_batch: graph capture");
-      if (b->ncache == emx_batch::kCache) {
+      if (b->ncache == emx_batch::kCache) {  // evict the least recently used
         (void)hipGraphExecDestroy(b->execs[0]);
         for (int k = 1; k < b->ncache; ++k) {
           b->keys[k - 1] = b->keys[k];
@@ -361,10 +401,19 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
         --b->ncache;
       }
       slot = b->ncache++;
-      b->keys[slot] = GraphKey{d_scratch, (int)key64, buf};
+      b->keys[slot] = key;
       b->execs[slot] = ex;
     }
-    e = hipGraphLaunch(b->execs[slot], st);
+    // move the entry to the most recently used end
+    const GraphKey k0 = b->keys[slot];
+    hipGraphExec_t x0 = b->execs[slot];
+    for (int k = slot + 1; k < b->ncache; ++k) {
+      b->keys[k - 1] = b->keys[k];
+      b->execs[k - 1] = b->execs[k];
+    }
+    b->keys[b->ncache - 1] = k0;
+    b->execs[b->ncache - 1] = x0;
+    e = hipGraphLaunch(x0, st);
   } else {
     e = enqueue(st);
   }

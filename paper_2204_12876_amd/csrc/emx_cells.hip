@@ -1,8 +1,10 @@
 // Per-cell passes: prior fill, robot-centric move, 3x3 normals, conv traversability.
 //
-// The stencils (normals, traversability) stage a 34x34 halo tile of heights
-// and validity in LDS.  Each 32x8 workgroup then produces a 32x32 output tile,
-// four rows per thread, so every height is read from HBM about 1.13 times.
+// The stencils (normals, traversability) stage an 18x18 halo tile of heights
+// and validity in LDS.  Each 256-thread workgroup then produces a 16x16 output
+// tile, one cell per thread: small tiles give a 400x400 map 625 workgroups,
+// enough to occupy every compute unit, at the cost of reading each height about
+// 1.27 times (mostly from cache).
 // The batched launch computes normals and traversability from one staged tile.
 #include "emx_kernels.h"
 
@@ -77,8 +79,9 @@ __device__ __forceinline__ void move_body(const Item& it, int64_t unit) {
 }
 
 // ---------------------------------------------------------------- stencil tile
-constexpr int kSW = 32;            // output tile width
-constexpr int kSH = 32;            // output tile height
+constexpr int kCellLog = 4;        // output tiles of 16 x 16 cells: one cell per thread
+constexpr int kSW = 1 << kCellLog;  // output tile width
+constexpr int kSH = 1 << kCellLog;  // output tile height
 constexpr int kHW = kSW + 2;       // halo tile
 constexpr int kHH = kSH + 2;
 
@@ -152,11 +155,11 @@ __device__ __forceinline__ float trav_at(const HaloTile& s, int lx, int ly, cons
   return T;
 }
 
-// Normals and/or traversability of one 32x32 output tile.
+// Normals and/or traversability of one output tile.
 __device__ __forceinline__ void cells_body(const Item& it, int64_t unit, bool do_n, bool do_t) {
   __shared__ HaloTile s;
   __shared__ float sw[89];
-  const int ux = blocks_of(it.c.nx, 5);
+  const int ux = blocks_of(it.c.nx, kCellLog);
   const int x0 = (int)(unit % ux) * kSW;
   const int y0 = (int)(unit / ux) * kSH;
   if (do_t && threadIdx.x < 89) sw[threadIdx.x] = it.w[threadIdx.x];
@@ -195,7 +198,11 @@ __global__ __launch_bounds__(kNTf) void k_trav(Item it) {
   cells_body(it, blockIdx.x, false, true);
 }
 
+// The batch's first launch: also zeroes the clearing queue counters, which
+// the later setup launch increments.
 __global__ __launch_bounds__(kNTf) void k_move_b(const Batch* bt) {
+  if (blockIdx.x == 0 && threadIdx.x < kSubQ)
+    bt->items[0].cq.counter[threadIdx.x * kCtrStride] = 0u;
   const int64_t total = bt->off[kBMove][bt->n];
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int i = batch_item(bt, kBMove, w);
@@ -217,7 +224,9 @@ __global__ __launch_bounds__(kNTf) void k_cells_b(const Batch* bt) {
 }  // namespace
 
 int64_t move_units(int nx, int ny) { return (int64_t)blocks_of(nx, 6) * ((ny + kMoveH - 1) / kMoveH); }
-int64_t cells_units(int nx, int ny) { return (int64_t)blocks_of(nx, 5) * blocks_of(ny, 5); }
+int64_t cells_units(int nx, int ny) {
+  return (int64_t)blocks_of(nx, kCellLog) * blocks_of(ny, kCellLog);
+}
 
 hipError_t launch_fill_prior(const Consts& c, const Layers& L, uint32_t* ctl, int nctl,
                              hipStream_t stream) {

@@ -135,11 +135,11 @@ struct Item {
 constexpr int kMaxItems = 64;
 enum BatchStage { kBMove = 0, kBChunk, kBTile, kBSetup, kBApply, kBCells, kBNum };
 
+// Only the header and the first n items are uploaded for a batch of n.
 struct Batch {
   int n;
   int key64;  // pass 1 sorts 64-bit keys for this batch
   int64_t off[kBNum][kMaxItems + 1];
-  uint32_t counter[kCtrWords];  // clearing sub-queue counters (uploaded as zero)
   Item items[kMaxItems];
 };
 

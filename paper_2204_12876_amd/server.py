@@ -139,6 +139,14 @@ class Request:
     def n(self) -> int:
         return int(self.xyz.shape[1])
 
+    def pose12(self):
+        """The pose as 12 Python floats (row-major 3x4), computed once."""
+        p = self.__dict__.get("_pose12")
+        if p is None:
+            p = [float(v) for v in np.asarray(self.pose, dtype=np.float64).reshape(12)]
+            self.__dict__["_pose12"] = p
+        return p
+
     @property
     def latency(self) -> float:
         return self.done - self.arrival
@@ -170,6 +178,7 @@ class Server:
         self.lanes = [_Lane(k) for k in range(executor.lanes)]
         self.maps: Dict[object, int] = {}
         self.waiting: Dict[object, collections.deque] = {}
+        self.ready: set = set()          # robots with a waiting frame
         self.inflight: set = set()
         self.completed: List[Request] = []
         self.batches = 0
@@ -204,10 +213,11 @@ class Server:
         if req.n > self.ex.max_batch_points or 3 * req.n > self.pool.capacity:
             raise AdmissionError(f"frame of {req.n} points exceeds the staging limits")
         self.waiting[req.robot].append(req)
+        self.ready.add(req.robot)
 
     # ----------------------------------------------------------- scheduling
     def pending(self) -> int:
-        return sum(len(q) for q in self.waiting.values())
+        return sum(len(self.waiting[r]) for r in self.ready)
 
     def idle(self) -> bool:
         return not self.inflight and self.pending() == 0
@@ -225,8 +235,8 @@ class Server:
                 ln.requests, ln.regions, ln.busy = [], [], False
 
     def _form(self) -> List[Request]:
-        heads = sorted((q[0].arrival, q[0].seq, robot) for robot, q in self.waiting.items()
-                       if q and robot not in self.inflight)
+        heads = sorted((self.waiting[robot][0].arrival, self.waiting[robot][0].seq, robot)
+                       for robot in self.ready if robot not in self.inflight)
         picked, points = [], 0
         for _, _, robot in heads:
             r = self.waiting[robot][0]
@@ -260,7 +270,10 @@ class Server:
                 break
             now = self.ex.now()
             for r in taken:
-                self.waiting[r.robot].popleft()
+                q = self.waiting[r.robot]
+                q.popleft()
+                if not q:
+                    self.ready.discard(r.robot)
                 self.inflight.add(r.robot)
                 r.launch = now
                 r.batch = self.batches
@@ -328,6 +341,8 @@ class GpuExecutor:
         st = self.streams[lane]
         base = self.pool.data_ptr()
         items = (_emx.BatchItem * len(requests))()
+        wptr = self.weights.data_ptr() if self.weights is not None else None
+        stages = _emx.STAGE_ALL if self.weights is not None else _emx.STAGE_ALL & ~_emx.STAGE_TRAV
         with torch.cuda.stream(st):
             for k, (r, off) in enumerate(zip(requests, offsets)):
                 n = r.n
@@ -335,12 +350,14 @@ class GpuExecutor:
                     self.pool[off:off + 3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
                 it = items[k]
                 it.map = self.maps[r.robot].handle
-                it.frame = _emx.make_frame(base + 4 * off, base + 4 * (off + n),
-                                           base + 4 * (off + 2 * n), n, r.pose, r.t_ms)
-                it.cx, it.cy = float(r.center[0]), float(r.center[1])
-                it.d_weights = self.weights.data_ptr() if self.weights is not None else None
-                it.stages = _emx.STAGE_ALL if self.weights is not None else \
-                    _emx.STAGE_ALL & ~_emx.STAGE_TRAV
+                f = it.frame
+                f.x, f.y, f.z = base + 4 * off, base + 4 * (off + n), base + 4 * (off + 2 * n)
+                f.n = n
+                f.pose[:] = r.pose12()
+                f.t_ms = r.t_ms
+                it.cx, it.cy = r.center
+                it.d_weights = wptr
+                it.stages = stages
             self.execs[lane].run_items(items, len(requests), st.cuda_stream)
             self.ends[lane].record(st)
 
@@ -411,10 +428,14 @@ def run_plain_trace(maps: dict, requests: List[Request], weights: torch.Tensor, 
 
 
 def latency_summary(reqs: List[Request]) -> dict:
+    """Latency (completion - arrival) percentiles and throughput; the wait
+    (launch - arrival) and device (completion - launch) parts as means."""
     lat = np.array([r.latency for r in reqs]) * 1e3
+    wait = np.array([r.launch - r.arrival for r in reqs]) * 1e3
     pts = sum(r.n for r in reqs)
     span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
     return dict(frames=len(reqs), points=int(pts), span_s=float(span),
                 points_per_s=float(pts / span) if span > 0 else math.nan,
                 p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                max_ms=float(lat.max()), mean_ms=float(lat.mean()))
+                max_ms=float(lat.max()), mean_ms=float(lat.mean()),
+                mean_wait_ms=float(wait.mean()), mean_run_ms=float((lat - wait).mean()))
