@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--batched-reps", type=int, default=20)
     ap.add_argument("--server-seconds", type=float, default=1.0)
     ap.add_argument("--server-robots", type=int, default=64)
+    ap.add_argument("--server-lanes", type=int, default=2)
     ap.add_argument("--tuning", default=None, help="batch tuning JSON (default: the tuned file)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy 256 MiB device to device once (a known-size kernel that "
@@ -428,20 +429,24 @@ def serving(args, dev, tuning):
 
     budget = 32 << 30
 
-    def run_server(reqs):
-        ex = GpuExecutor(largest, lanes=2, max_items=64, max_batch_points=8_000_000,
-                         pool_points=24_000_000, weights=w, tuning=tuning, device=dev)
+    def run_server(reqs, warm):
+        ex = GpuExecutor(largest, lanes=args.server_lanes, max_items=64,
+                         max_batch_points=8_000_000, pool_points=24_000_000, weights=w,
+                         device=dev)
         srv = Server(ex, budget)
         for k, it in enumerate(items):
             srv.add_map(k, it["params"], *host[k][2])
-        for _ in range(3):                  # both host tables of each lane captured
-            run_trace(srv, trace(0, saturated_frames=2))
+        run_trace(srv, warm)  # a short trace of the same kind: graph captures, clocks
         srv.completed.clear()
         srv.batch_sizes.clear()
+        b0, c0 = ex.graph_stats()
         run_trace(srv, reqs, timeout_s=120)
+        b1, c1 = ex.graph_stats()
         s = latency_summary(reqs)
         s["mean_batch_items"] = float(np.mean(srv.batch_sizes))
         s["batches"] = len(srv.batch_sizes)
+        s["batched_calls"] = b1 - b0
+        s["graph_captures_in_trace"] = c1 - c0
         s["hbm_budget_bytes"] = budget
         s["hbm_reserved_bytes"] = srv.budget.used
         return s
@@ -459,12 +464,12 @@ def serving(args, dev, tuning):
     poisson = trace(args.server_seconds)
     offered = sum(r.n for r in poisson) / args.server_seconds
     say(f"server trace: {len(poisson)} frames, offered {offered / 1e6:.0f} M points/s")
-    srv_p = run_server(poisson)
+    srv_p = run_server(poisson, trace(0.3))
     say(f"server p50 {srv_p['p50_ms']:.3f} p99 {srv_p['p99_ms']:.3f} ms")
     pln_p = run_plain(_fresh(poisson))
     say(f"plain  p50 {pln_p['p50_ms']:.3f} p99 {pln_p['p99_ms']:.3f} ms")
     sat = trace(0, saturated_frames=6)
-    srv_s = run_server(sat)
+    srv_s = run_server(sat, trace(0, saturated_frames=2))
     pln_s = run_plain(_fresh(sat))
     say(f"saturated: server {srv_s['points_per_s'] / 1e9:.2f} vs plain "
         f"{pln_s['points_per_s'] / 1e9:.2f} G points/s")

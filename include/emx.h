@@ -270,6 +270,11 @@ emx_status emx_batch_destroy(emx_batch* batch); /* waits for its last batch */
 /* The executor's tuning as JSON, written to buf (len bytes). */
 emx_status emx_batch_tuning(const emx_batch* batch, char* buf, size_t len);
 
+/* Batches run and graphs captured by this executor so far.  A capture
+ * happens the first time a batch needs a (scratch, key width, grid sizes)
+ * combination that is not in the executor's cache of 16 graphs. */
+emx_status emx_batch_stats(const emx_batch* batch, int64_t* batches, int64_t* captures);
+
 /* Device scratch bytes for this list of items (1..EMX_BATCH_MAX_ITEMS);
  * 0 if the list is invalid. */
 size_t emx_batch_scratch_bytes(const emx_batch* batch, const emx_batch_item* items,
@@ -285,9 +290,12 @@ size_t emx_batch_scratch_bound(const emx_batch* batch, const emx_params* largest
 
 /* Run the batch on `stream`.
  *   d_scratch: >= emx_batch_scratch_bytes(), 256-aligned.  Its first bytes
- *              hold the batch's device table.  A graph is cached per scratch
- *              address, so keep reusing the same buffer.  A scratch buffer
- *              must not be shared by batches in flight at the same time.
+ *              hold the batch's device table.  Graphs are cached per scratch
+ *              address, key width and grid sizes, so keep reusing the same
+ *              buffer.  A scratch buffer must not be shared by batches in
+ *              flight at the same time.
+ *   Each stage's grid is the tuned size capped at the stage's work rounded
+ *   up to a power of two (the march: about two threads per ray).
  *   Every item is checked before anything is enqueued; on an error no map
  *   changes.  Moves commit the maps' new centres when the call returns OK.
  *   The call may wait on the host for the batch before last to release its

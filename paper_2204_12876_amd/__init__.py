@@ -229,18 +229,33 @@ class PipelineBatch:
             self._scratch = aligned_empty(nbytes, self.device)
             self._scratch_bytes = int(nbytes)
 
+    def stats(self):
+        """(batches run, graphs captured)."""
+        return _emx.batch_stats(self.handle)
+
+    def scratch_buffer(self) -> torch.Tensor:
+        """The executor's scratch buffer (None before the first reserve or run)."""
+        return self._scratch
+
     def scratch_bound(self, largest_params: dict, max_items: int, max_points: int) -> int:
         return _emx.batch_scratch_bound(self.handle, make_params(largest_params), max_items,
                                         max_points)
 
     def run_items(self, arr, n: int, stream: int):
         """Run a ctypes array of emx_batch_item on ``stream``."""
+        if self._scratch is not None:
+            try:
+                _emx.pipeline_batch(self.handle, arr, n, self._scratch.data_ptr(),
+                                    self._scratch_bytes, stream)
+                return
+            except EmxError as e:
+                if e.status != _emx.EMX_ENOMEM:
+                    raise
         need = _emx.batch_scratch_bytes(self.handle, arr, n)
         if need == 0:
             raise EmxError(_emx.EMX_EINVAL, _emx.last_error())
-        if self._scratch is None or self._scratch_bytes < need:
-            # keep one buffer, generously sized: graphs are cached per scratch address
-            self.reserve(max(need, 2 * self._scratch_bytes))
+        # keep one buffer, generously sized: graphs are cached per scratch address
+        self.reserve(max(need, 2 * self._scratch_bytes))
         _emx.pipeline_batch(self.handle, arr, n, self._scratch.data_ptr(), self._scratch_bytes,
                             stream)
 

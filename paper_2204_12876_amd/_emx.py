@@ -82,6 +82,7 @@ _SIGS = {
     "emx_batch_destroy": (c_int32, [c_void_p]),
     "emx_batch_tuning": (c_int32, [c_void_p, c_char_p, c_size_t]),
     "emx_batch_scratch_bytes": (c_size_t, [c_void_p, POINTER(BatchItem), c_int32]),
+    "emx_batch_stats": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
     "emx_batch_scratch_bound": (c_size_t, [c_void_p, POINTER(Params), c_int32, c_int64]),
     "emx_timing_begin": (c_int32, []),
     "emx_timing_end": (c_int32, [c_char_p, c_size_t]),
@@ -250,6 +251,13 @@ def make_batch_items(items) -> "ctypes.Array":
 
 def batch_scratch_bytes(h: int, arr, n: int) -> int:
     return lib().emx_batch_scratch_bytes(c_void_p(h), arr, n)
+
+
+def batch_stats(h: int):
+    """(batches run, graphs captured) of a batch executor."""
+    a, b = c_int64(), c_int64()
+    check(lib().emx_batch_stats(c_void_p(h), byref(a), byref(b)))
+    return a.value, b.value
 
 
 def batch_scratch_bound(h: int, largest: Params, max_items: int, max_points: int) -> int:

@@ -21,14 +21,15 @@ from __future__ import annotations
 import json
 import time
 
+# 65536 means one workgroup per work unit for every batch of this size class.
 SPACE = {
-    "grid_chunk": [256, 512, 1024, 2048, 4096],
-    "grid_tile": [256, 512, 1024, 2048, 4096],
-    "grid_setup": [512, 1024, 2048, 4096],
-    "grid_march": [1024, 2048, 4096, 8192],
-    "grid_move": [256, 512, 1024, 2048],
-    "grid_apply": [256, 512, 1024, 2048],
-    "grid_cells": [256, 512, 1024, 2048],
+    "grid_chunk": [256, 512, 1024, 2048, 4096, 65536],
+    "grid_tile": [256, 512, 1024, 2048, 4096, 65536],
+    "grid_setup": [512, 1024, 2048, 4096, 8192, 65536],
+    "grid_march": [1024, 2048, 4096, 8192, 16384],
+    "grid_move": [256, 512, 1024, 2048, 8192, 65536],
+    "grid_apply": [256, 512, 1024, 2048, 8192, 65536],
+    "grid_cells": [256, 512, 1024, 2048, 8192, 65536],
     "seg": [16, 32, 64, 128],
 }
 

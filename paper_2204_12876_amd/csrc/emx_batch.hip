@@ -93,6 +93,8 @@ struct emx_batch {
   GraphKey keys[kCache];  // most recently used last
   hipGraphExec_t execs[kCache];
   int ncache;
+  int64_t batches;    // batches run
+  int64_t captures;   // graphs captured
 };
 
 namespace {
@@ -185,6 +187,8 @@ emx_status emx_batch_create(const char* tuning_json, emx_batch** out) {
     return fail(EMX_EINVAL, "tuning: seg must lie in [1, 255]");
   }
   b->ncache = 0;
+  b->batches = 0;
+  b->captures = 0;
   b->next = 0;
   b->host[0] = b->host[1] = nullptr;
   b->cap = nullptr;
@@ -232,6 +236,13 @@ emx_status emx_batch_tuning(const emx_batch* b, char* buf, size_t len) {
                          t.grid_move, t.grid_chunk, t.grid_tile, t.grid_setup, t.grid_march,
                          t.grid_apply, t.grid_cells, t.seg, t.graph);
   if (w < 0 || (size_t)w >= len) return fail(EMX_ENOMEM, "buffer too small");
+  return EMX_OK;
+}
+
+emx_status emx_batch_stats(const emx_batch* b, int64_t* batches, int64_t* captures) {
+  if (!b || !batches || !captures) return fail(EMX_EINVAL, "NULL argument");
+  *batches = b->batches;
+  *captures = b->captures;
   return EMX_OK;
 }
 
@@ -403,6 +414,7 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
       slot = b->ncache++;
       b->keys[slot] = key;
       b->execs[slot] = ex;
+      ++b->captures;
     }
     // move the entry to the most recently used end
     const GraphKey k0 = b->keys[slot];
@@ -420,6 +432,7 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
   if (e == hipSuccess) e = hipEventRecord(b->done[buf], st);
   if (e != hipSuccess) return hip_fail(e, "pipeline_batch");
   b->used[buf] = true;
+  ++b->batches;
   // the moves are enqueued: commit the maps' new geometry
   for (int32_t i = 0; i < n; ++i) {
     items[i].map->cur = cur[i];

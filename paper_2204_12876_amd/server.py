@@ -292,9 +292,23 @@ class GpuExecutor:
     """Device side of the server: resident maps, a staging pool, and one
     stream, batch executor and scratch buffer per lane."""
 
+    # Batches here are mostly small and of ever-changing composition:
+    #   - every stage but the march gets one workgroup per work unit, so a
+    #     small batch is not folded into rounds;
+    #   - launches are direct, not through captured graphs: a capture stalls
+    #     the host for milliseconds, and varying batch shapes would keep
+    #     capturing new graphs while frames wait.
+    DEFAULT_TUNING = {"grid_move": 65536, "grid_chunk": 65536, "grid_tile": 65536,
+                      "grid_setup": 65536, "grid_apply": 65536, "grid_cells": 65536,
+                      "graph": 0}
+
     def __init__(self, largest_params: dict, lanes: int = 2, max_items: int = 64,
                  max_batch_points: int = 4_000_000, pool_points: int = 16_000_000,
-                 weights: torch.Tensor = None, tuning: str = None, device=None):
+                 weights: torch.Tensor = None, tuning: str = None, single_plain: bool = True,
+                 device=None):
+        """single_plain: run a batch of one frame through the plain calls, which
+        give the same bits with less launch overhead."""
+        import json
         from . import PipelineBatch, aligned_empty
         self.device = torch.device(device if device is not None else "cuda")
         self.lanes = int(lanes)
@@ -302,8 +316,13 @@ class GpuExecutor:
         self.max_batch_points = int(max_batch_points)
         self.pool_floats = 3 * int(pool_points)
         self.weights = weights
+        self.single_plain = bool(single_plain)
+        tune = dict(self.DEFAULT_TUNING)
+        if tuning:
+            tune.update(json.loads(tuning))
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.lanes)]
-        self.execs = [PipelineBatch(tuning, device=self.device) for _ in range(self.lanes)]
+        self.execs = [PipelineBatch(json.dumps(tune), device=self.device)
+                      for _ in range(self.lanes)]
         bound = _emx.batch_scratch_bound(self.execs[0].handle, _emx.make_params(largest_params),
                                          self.max_items, self.max_batch_points)
         if bound == 0:
@@ -343,6 +362,9 @@ class GpuExecutor:
         items = (_emx.BatchItem * len(requests))()
         wptr = self.weights.data_ptr() if self.weights is not None else None
         stages = _emx.STAGE_ALL if self.weights is not None else _emx.STAGE_ALL & ~_emx.STAGE_TRAV
+        if self.single_plain and len(requests) == 1:
+            self._launch_plain(lane, requests[0], offsets[0])
+            return
         with torch.cuda.stream(st):
             for k, (r, off) in enumerate(zip(requests, offsets)):
                 n = r.n
@@ -361,8 +383,34 @@ class GpuExecutor:
             self.execs[lane].run_items(items, len(requests), st.cuda_stream)
             self.ends[lane].record(st)
 
+    def _launch_plain(self, lane: int, r, off: int):
+        """One frame through the plain calls on the lane's stream; the lane's
+        batch scratch (sized for a whole batch) serves as their scratch."""
+        st = self.streams[lane]
+        n = r.n
+        m = self.maps[r.robot]
+        scratch = self.execs[lane].scratch_buffer()
+        with torch.cuda.stream(st):
+            if n:
+                self.pool[off:off + 3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
+            x = self.pool[off:off + n]
+            y = self.pool[off + n:off + 2 * n]
+            z = self.pool[off + 2 * n:off + 3 * n]
+            m.move_map(*r.center)
+            m.fuse_points(x, y, z, r.pose, r.t_ms, scratch=scratch)
+            m.clear_visibility(x, y, z, r.pose, r.t_ms, scratch=scratch)
+            m.compute_normals()
+            if self.weights is not None:
+                m.traversability(self.weights)
+            self.ends[lane].record(st)
+
     def done(self, lane: int) -> bool:
         return self.ends[lane].query()
+
+    def graph_stats(self):
+        """(batches run through the batched call, graphs captured), all lanes."""
+        st = [ex.stats() for ex in self.execs]
+        return sum(a for a, _ in st), sum(b for _, b in st)
 
     def finish_time(self, lane: int) -> float:
         return self.t0_event.elapsed_time(self.ends[lane]) / 1e3
