@@ -102,6 +102,8 @@ size_t set_layout(const emx_params& p, char* base, Layers* L) {
   return 7 * l4 + 2 * l1 + lb;
 }
 
+size_t clr_bytes(const emx_params& p) { return align256((size_t)p.nx * (size_t)p.ny * 16); }
+
 int tiles_of(const emx_params& p) { return tiles_x_of(p.nx) * tiles_y_of(p.ny); }
 
 // A persistent grid of per_cu workgroups per compute unit of the current device.
@@ -195,7 +197,8 @@ emx_status emx_params_check(const emx_params* params) { return check_params(para
 
 size_t emx_state_bytes(const emx_params* params) {
   if (check_params(params) != EMX_OK) return 0;
-  return 2 * set_layout(*params, nullptr, nullptr) + kCtlWords * sizeof(uint32_t);
+  return 2 * set_layout(*params, nullptr, nullptr) + clr_bytes(*params) +
+         kCtlWords * sizeof(uint32_t);
 }
 
 size_t emx_scratch_bytes(const emx_params* params, int64_t max_points) {
@@ -238,8 +241,11 @@ emx_status emx_init_map(const emx_params* params, double cx, double cy, int64_t 
   m->set_bytes = set_layout(*params, nullptr, nullptr);
   set_layout(*params, m->state, &m->sets[0]);
   set_layout(*params, m->state + m->set_bytes, &m->sets[1]);
+  float4* clr = (float4*)(m->state + 2 * m->set_bytes);
+  m->sets[0].clr = clr;
+  m->sets[1].clr = clr;
   m->cur = 0;
-  m->ctl = (uint32_t*)(m->state + 2 * m->set_bytes);
+  m->ctl = (uint32_t*)(m->state + 2 * m->set_bytes + clr_bytes(*params));
   m->march_grid = persistent_grid(8);
   hipError_t e = launch_fill_prior(m->c, m->sets[0], m->ctl, kCtlWords, (hipStream_t)stream);
   if (e != hipSuccess) {

@@ -8,7 +8,9 @@
 // setup, two roles in one grid:
 //   - Block role: per block of 2^b x 2^b cells, the largest height of a cell
 //     that a ray could still remove: valid, older than the minimum age, with a
-//     normal.  It is -inf if there is none.
+//     normal.  It is -inf if there is none.  The same pass writes each cell's
+//     16-byte clearing record {h, or -inf if no ray may remove it, v, nx, ny},
+//     so that the march tests a sample with one load.
 //   - Ray role, one thread per point:
 //       - the ray's exact in-map range of k.  A sample's cell is in the map over
 //         a contiguous range of k, because q_k.x and q_k.y are monotone in k:
@@ -23,6 +25,8 @@
 //   - A sample at height q.z >= the block maximum passes above every cell that
 //     could be removed, since removal needs h > q.z.  It is skipped without
 //     reading the cell: exact pruning.
+//   - Other samples read their cell's clearing record (and the normal's z
+//     only if the height test passes).
 //   - Marks are idempotent byte stores, so the queue order never shows in the
 //     result.
 //   - The state is only read, so every ray sees the state as it was when the
@@ -131,7 +135,7 @@ __device__ __forceinline__ bool clearable(const Item& it, int64_t c) {
          !isnan(it.L.nz[c]);
 }
 
-// The full removal test of sample q (height qz) in cell c.
+// The full removal test of sample q (height qz) in cell c, from the layers.
 __device__ __forceinline__ void test_cell(const Item& it, const Ray& r, int c, float qz,
                                           float an2dd) {
   // one round trip: every field the test may need
@@ -149,12 +153,28 @@ __device__ __forceinline__ void test_cell(const Item& it, const Ray& r, int c, f
   if ((dot * dot) > an2dd) it.L.mark[c] = 1;
 }
 
+// The same test from the cell's clearing record, written by the setup: one
+// 16-byte load instead of seven, and the normal's z only when the height test
+// passes.  A cell no ray may clear holds -inf, which fails hd > 0 for every
+// finite sample height, so the decision is the same.
+__device__ __forceinline__ void test_cell_rec(const Item& it, const Ray& r, int c, float qz,
+                                              float an2dd) {
+  const float4 k = it.L.clr[c];
+  const float hd = k.x - qz;
+  if (!(hd > 0.0f) || !((hd * hd) > k.y)) return;
+  const float dot = (r.dx * k.z + r.dy * k.w) + r.dz * it.L.nz[c];
+  if ((dot * dot) > an2dd) it.L.mark[c] = 1;
+}
+
 constexpr int kUnroll = 4;
 
-// Test samples k in [ka, kb] of ray r against the map.  cm holds the block
-// maxima; with cm == nullptr every sample is tested (same result, no pruning).
+// Test samples k in [ka, kb] of ray r against the map.  With kRec, cm holds
+// the block maxima and the cells' clearing records are read; without, every
+// sample is tested against the layers (same result, no pruning), for use
+// while the setup is still writing maxima and records.
 // kUnroll samples at a time: their cells and block maxima are found without
 // branches, so the block-maximum loads issue together.
+template <bool kRec>
 __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka, int kb,
                                             int end_cell, const float* cm) {
   const float an2dd = it.c.an2 * ((r.dx * r.dx + r.dy * r.dy) + r.dz * r.dz);
@@ -180,12 +200,15 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
       const int ix = in ? (int)floorf(fx) : 0;
       const int iy = in ? (int)floorf(fy) : 0;
       cell[u] = iy * nx + ix;
-      const float m = cm ? cm[(iy >> bl) * bx + (ix >> bl)] : INFINITY;
+      const float m = kRec ? cm[(iy >> bl) * bx + (ix >> bl)] : INFINITY;
       cand[u] = in && (qz[u] < m) && cell[u] != end_cell;
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-      if (cand[u]) test_cell(it, r, cell[u], qz[u], an2dd);
+    for (int u = 0; u < kUnroll; ++u) {
+      if (!cand[u]) continue;
+      if (kRec) test_cell_rec(it, r, cell[u], qz[u], an2dd);
+      else test_cell(it, r, cell[u], qz[u], an2dd);
+    }
   }
 }
 
@@ -205,7 +228,10 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
       const int iy = y0 + (j >> it.bl);
       if (ix < it.c.nx && iy < it.c.ny) {
         const int64_t c = (int64_t)iy * it.c.nx + ix;
-        if (clearable(it, c)) v = fmaxf(v, it.L.h[c]);
+        const bool ok = clearable(it, c);
+        const float h = it.L.h[c];
+        it.L.clr[c] = make_float4(ok ? h : -INFINITY, it.L.v[c], it.L.nx[c], it.L.ny[c]);
+        if (ok) v = fmaxf(v, h);
       }
     }
 #pragma unroll
@@ -275,7 +301,7 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
     // sub-queue full: leave empty entries in any reserved slots and march
     // here, unpruned (the block maxima are still being written by this launch)
     for (int64_t e = first; e < first + nseg && e < cq.qcap; ++e) q[e] = make_uint2(0u, 0u);
-    march_range(it, r, k0, k1, end_cell, nullptr);
+    march_range<false>(it, r, k0, k1, end_cell, nullptr);
   }
 }
 
@@ -321,7 +347,7 @@ __device__ __forceinline__ void march_entry(const Item& it, const ClearQueue& cq
   r.dz = d.z;
   r.Kf = d.w;
   r.rK = 1.0 / (double)d.w;
-  march_range(it, r, ka, ka + cnt - 1, cq.ray_end[e.x], cm);
+  march_range<true>(it, r, ka, ka + cnt - 1, cq.ray_end[e.x], cm);
 }
 
 __device__ __forceinline__ void apply_body(const Item& it, int64_t unit) {

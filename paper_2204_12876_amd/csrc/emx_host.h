@@ -22,6 +22,7 @@ const char* last_error_text();
 emx_status check_params(const emx_params* p);
 Consts make_consts(const emx_params& p);
 size_t set_layout(const emx_params& p, char* base, Layers* L);
+size_t clr_bytes(const emx_params& p);  // the per-map clearing record array
 int tiles_of(const emx_params& p);
 int persistent_grid(int per_cu);
 bool center_cell(double c, double r, int64_t* out);
