@@ -19,7 +19,7 @@ namespace emx {
 
 // Points per fusion chunk.  This fixes the float32 summation order of the fused
 // sums, so it is a constant of the library, not a tunable.
-constexpr int kChunk = 2048;
+constexpr int kChunk = 1024;
 // Map tiles of 32x32 cells own the per-cell merge.
 constexpr int kTileLog = 5;
 constexpr int kTile = 1 << kTileLog;

@@ -1,7 +1,7 @@
 // Height fusion (Sec. II-C, Eq. 1 and Eq. 2) as a deterministic two-pass
 // sort-and-reduce, with no float atomics.
 //
-// Pass 1, chunk body: one workgroup per chunk of kChunk consecutive points.
+// Pass 1, chunk body: one workgroup per chunk of kChunk (1024) consecutive points.
 //   - Takes the per-point decisions: transform, range, bin, and the Mahalanobis
 //     gate against the frame-start prior.
 //   - Sorts the accepted points in LDS by (tile, cell in tile, point index).
@@ -28,8 +28,9 @@ namespace emx {
 
 namespace {
 
-constexpr int kNT1 = 1024;                // pass-1 threads: two keys each
-constexpr int kPBits = 11;                // point index within the chunk
+constexpr int kNT1 = kChunk / 2;          // pass-1 threads: two keys each
+constexpr int kPBits = 10;                // point index within the chunk
+static_assert((1 << kPBits) == kChunk, "the key's point field spans one chunk");
 constexpr int kSegBits = 2 * kTileLog;    // local cell within the tile
 // 32-bit keys hold (tile, local, point) while tile * kTileCells < 2^21.
 constexpr int64_t kMaxCells32 = (int64_t)1 << (32 - kPBits);
@@ -308,9 +309,9 @@ __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
 // ------------------------------------------------------------------ pass 2
 constexpr int kNT2 = 1024;                 // pass-2 threads: one per cell of the tile
 static_assert(kNT2 == kTileCells, "pass 2 gives each thread one cell of the tile");
-constexpr int kCap = 4096;                 // partials staged per group
+constexpr int kCap = 8192;                 // partials staged per group
 constexpr int kPer = kCap / kNT2;          // partials each thread loads per group
-constexpr int kGroupChunks = 128;          // chunks per group
+constexpr int kGroupChunks = 256;          // chunks per group
 constexpr int kMaskWords = kGroupChunks / 32;
 constexpr int kWin = kNT2;                 // directory entries read per window
 

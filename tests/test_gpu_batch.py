@@ -181,7 +181,7 @@ def test_batch_mixed_stages_and_wide_keys(dev):
     _say("batch mixed stages + wide keys")
     w = torch.from_numpy(synth.trav_weights()).to(dev)
     pb = PipelineBatch(device=dev)
-    shapes = [(1500, 1480, 0.02, 60000), (64, 64, 0.05, 5000), (40, 70, 0.05, 3000),
+    shapes = [(2080, 2100, 0.02, 60000), (64, 64, 0.05, 5000), (40, 70, 0.05, 3000),
               (128, 128, 0.04, 20000)]
     robots = _robots(dev, shapes, seed=2)
     sets = [_emx.STAGE_ALL, _emx.STAGE_FUSE, _emx.STAGE_NORMALS | _emx.STAGE_TRAV,

@@ -139,16 +139,16 @@ def test_fuse_ragged_tiles_spread(dev):
 
 
 def test_fuse_large_map_wide_keys(dev):
-    """A map of more than 2^21 cells (sort keys of 64 bits)."""
+    """A map of more than 4096 fusion tiles, 2^22 cells (sort keys of 64 bits)."""
     _say("fuse large map")
     rng = np.random.default_rng(13)
-    params = dict(nx=1500, ny=1480, resolution=0.02, noise_alpha=1e-3, gate_k=3.0, min_range=0.01)
+    params = dict(nx=2080, ny=2100, resolution=0.02, noise_alpha=1e-3, gate_k=3.0, min_range=0.01)
     p = O.Params.from_dict(params)
     m = _map(params, dev)
     st = O.init_map(p, 0.0, 0.0, 0)
     n = 60000
-    xs = rng.uniform(-14.9, 14.9, n).astype(F32)
-    ys = rng.uniform(-14.7, 14.7, n).astype(F32)
+    xs = rng.uniform(-20.7, 20.7, n).astype(F32)
+    ys = rng.uniform(-20.9, 20.9, n).astype(F32)
     zs = (0.05 * np.cos(xs) - 1.0 + 0.01 * rng.normal(size=n)).astype(F32)
     xs[:3000] = rng.uniform(0.0, 0.1, 3000).astype(F32)      # a dense corner
     ys[:3000] = rng.uniform(0.0, 0.1, 3000).astype(F32)
