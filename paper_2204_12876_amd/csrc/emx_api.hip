@@ -246,7 +246,7 @@ emx_status emx_init_map(const emx_params* params, double cx, double cy, int64_t 
   m->sets[1].clr = clr;
   m->cur = 0;
   m->ctl = (uint32_t*)(m->state + 2 * m->set_bytes + clr_bytes(*params));
-  m->march_grid = persistent_grid(8);
+  m->march_grid = persistent_grid(kMarchPerCU);
   hipError_t e = launch_fill_prior(m->c, m->sets[0], m->ctl, kCtlWords, (hipStream_t)stream);
   if (e != hipSuccess) {
     delete m;

@@ -161,7 +161,7 @@ emx_status emx_batch_create(const char* tuning_json, emx_batch** out) {
   emx_batch* b = new (std::nothrow) emx_batch;
   if (!b) return fail(EMX_ENOMEM, "host allocation failed");
   b->tune = Tuning();
-  b->tune.grid_march = persistent_grid(8);
+  b->tune.grid_march = persistent_grid(kMarchPerCU);
   b->tune.grid_setup = persistent_grid(8);
   if (tuning_json) {
     json_int(tuning_json, "grid_move", &b->tune.grid_move);

@@ -166,7 +166,7 @@ __device__ __forceinline__ void test_cell_rec(const Item& it, const Ray& r, int 
   if ((dot * dot) > an2dd) it.L.mark[c] = 1;
 }
 
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 16;
 
 // Test samples k in [ka, kb] of ray r against the map.  With kRec, cm holds
 // the block maxima and the cells' clearing records are read; without, every
@@ -369,16 +369,16 @@ __global__ __launch_bounds__(kNTc) void k_clear_setup(Item it) {
   setup_body(it, blockIdx.x, (int)blockIdx.x - it.nprep);
 }
 
+// The block maxima are read through the caches: they are small and shared by
+// every workgroup, and staging them in LDS per workgroup costs more than it saves.
 __global__ __launch_bounds__(kNTc) void k_clear_march(Item it) {
-  extern __shared__ float s_cmax[];
   __shared__ int64_t s_qoff[kSubQ + 1];
-  for (int j = threadIdx.x; j < it.nb; j += kNTc) s_cmax[j] = it.L.cmax[j];
   queue_prefix(it.cq, s_qoff);
   __syncthreads();
   const int64_t total = s_qoff[kSubQ];
   for (int64_t g = (int64_t)blockIdx.x * kNTc + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * kNTc)
-    march_entry(it, it.cq, queue_entry(it.cq, s_qoff, g), s_cmax);
+    march_entry(it, it.cq, queue_entry(it.cq, s_qoff, g), it.L.cmax);
 }
 
 __global__ __launch_bounds__(kNTc) void k_clear_apply(Item it) { apply_body(it, blockIdx.x); }
@@ -393,8 +393,7 @@ __global__ __launch_bounds__(kNTc) void k_clear_setup_b(const Batch* bt) {
 }
 
 // Every item of a batch shares one queue (the first item's view of it); a
-// queue entry's ray names its item.  Block maxima are read from HBM, since
-// the entries of one workgroup may belong to different maps.
+// queue entry's ray names its item.
 __global__ __launch_bounds__(kNTc) void k_clear_march_b(const Batch* bt) {
   __shared__ int64_t s_qoff[kSubQ + 1];
   const ClearQueue& cq = bt->items[0].cq;
@@ -422,9 +421,13 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+// Room for kQueueSamplesPerRay samples per ray on average plus two partial
+// segments per ray (a ray's range rarely ends on a segment boundary), and
+// slack for uneven sub-queue fill.  A full sub-queue is not an error: its
+// rays are marched in place by the setup, unpruned.
 int64_t clear_queue_cap(int64_t max_points, int seg) {
-  const int64_t segs = (max_points * kQueueSamplesPerRay + seg - 1) / seg;
-  return (segs + kSubQ - 1) / kSubQ;
+  const int64_t segs = (max_points * kQueueSamplesPerRay + seg - 1) / seg + 2 * max_points;
+  return (segs + segs / 8 + kSubQ - 1) / kSubQ;
 }
 
 size_t clear_scratch_layout(int64_t max_points, int seg, char* base, ClearQueue* out) {
@@ -463,8 +466,7 @@ hipError_t launch_clear(const Item& it, int march_grid, hipStream_t stream) {
     if (err != hipSuccess) return err;
     {
       TimedLaunch tl("k_clear_march", stream);
-      hipLaunchKernelGGL(k_clear_march, dim3((unsigned)march_grid), dim3(kNTc),
-                         (size_t)it.nb * sizeof(float), stream, it);
+      hipLaunchKernelGGL(k_clear_march, dim3((unsigned)march_grid), dim3(kNTc), 0, stream, it);
     }
     err = hipGetLastError();
     if (err != hipSuccess) return err;

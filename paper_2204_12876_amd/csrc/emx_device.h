@@ -47,14 +47,14 @@ struct Layers {
                   // (transient; one array per map, shared by both sets)
 };
 
-// Clearing prunes samples by square blocks of 2^b cells, b >= 3: the
-// smallest b whose block grid fits kMaxBlkBytes, so that it can sit in LDS.
-constexpr int kMaxBlkBytes = 48 * 1024;
+// Clearing prunes samples by square blocks of 8 x 8 cells: one cell per lane
+// of the wave that computes a block's maximum.  The maxima are read through
+// the caches, so their count is not bounded by LDS.
 __host__ __device__ inline int blocks_of(int n, int b) { return (n + (1 << b) - 1) >> b; }
 __host__ __device__ inline int block_log_of(int nx, int ny) {
-  int b = 3;
-  while ((long long)blocks_of(nx, b) * blocks_of(ny, b) * 4 > kMaxBlkBytes) ++b;
-  return b;
+  (void)nx;
+  (void)ny;
+  return 3;
 }
 
 // Float32 constants derived once on the host from emx_params.

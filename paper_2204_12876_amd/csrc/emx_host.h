@@ -12,8 +12,10 @@ namespace emx {
 // counters of the plain calls.
 constexpr int kCtlWords = kCtrWords;
 
-// Default clearing segment length (samples per queued segment).
-constexpr int kDefaultSeg = 32;
+// Default clearing segment length (samples per queued segment) and march
+// workgroups per compute unit, from a sweep of both on MI355X.
+constexpr int kDefaultSeg = 16;
+constexpr int kMarchPerCU = 16;
 
 emx_status fail(emx_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 emx_status hip_fail(hipError_t e, const char* what);
