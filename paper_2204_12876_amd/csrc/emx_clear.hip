@@ -8,9 +8,10 @@
 // setup, two roles in one grid:
 //   - Block role: per block of 2^b x 2^b cells, the largest height of a cell
 //     that a ray could still remove: valid, older than the minimum age, with a
-//     normal.  It is -inf if there is none.  The same pass writes each cell's
-//     16-byte clearing record {h, or -inf if no ray may remove it, v, nx, ny},
-//     so that the march tests a sample with one load.
+//     normal.  It is -inf if there is none.  In blocks with such a cell the
+//     same pass writes each cell's 16-byte clearing record {h, or -inf if no
+//     ray may remove it, v, nx, ny}, so that the march tests a sample with one
+//     load.  Other blocks prune every sample, so their records are never read.
 //   - Ray role, one thread per point:
 //       - the ray's exact in-map range of k.  A sample's cell is in the map over
 //         a contiguous range of k, because q_k.x and q_k.y are monotone in k:
@@ -222,21 +223,21 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
     const int side = 1 << it.bl;
     const int x0 = (b % it.bx) << it.bl;
     const int y0 = (b / it.bx) << it.bl;
-    float v = -INFINITY;
-    for (int j = lane; j < side * side; j += 64) {
-      const int ix = x0 + (j & (side - 1));
-      const int iy = y0 + (j >> it.bl);
-      if (ix < it.c.nx && iy < it.c.ny) {
-        const int64_t c = (int64_t)iy * it.c.nx + ix;
-        const bool ok = clearable(it, c);
-        const float h = it.L.h[c];
-        it.L.clr[c] = make_float4(ok ? h : -INFINITY, it.L.v[c], it.L.nx[c], it.L.ny[c]);
-        if (ok) v = fmaxf(v, h);
-      }
-    }
+    // one cell per lane (blocks are 8 x 8)
+    const int ix = x0 + (lane & (side - 1));
+    const int iy = y0 + (lane >> it.bl);
+    const bool inside = ix < it.c.nx && iy < it.c.ny;
+    const int64_t c = (int64_t)iy * it.c.nx + ix;
+    const bool ok = inside && clearable(it, c);
+    const float h = inside ? it.L.h[c] : 0.0f;
+    float v = ok ? h : -INFINITY;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
     if (lane == 0) it.L.cmax[b] = v;
+    // the march reads records only in blocks with a removable cell, where
+    // some sample may pass below the block maximum
+    if (v > -INFINITY && inside)
+      it.L.clr[c] = make_float4(ok ? h : -INFINITY, it.L.v[c], it.L.nx[c], it.L.ny[c]);
     return;
   }
   // ---- ray role

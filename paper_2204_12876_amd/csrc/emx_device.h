@@ -48,7 +48,7 @@ struct Layers {
 };
 
 // Clearing prunes samples by square blocks of 8 x 8 cells: one cell per lane
-// of the wave that computes a block's maximum.  The maxima are read through
+// of the wave that computes a block's maximum (the setup relies on it).  The maxima are read through
 // the caches, so their count is not bounded by LDS.
 __host__ __device__ inline int blocks_of(int n, int b) { return (n + (1 << b) - 1) >> b; }
 __host__ __device__ inline int block_log_of(int nx, int ny) {
