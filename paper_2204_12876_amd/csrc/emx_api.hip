@@ -147,7 +147,8 @@ emx_status make_item(const emx_map* m, const emx_frame* f, Item* it) {
   it->bx = blocks_of(m->p.nx, it->bl);
   it->by = blocks_of(m->p.ny, it->bl);
   it->nb = it->bx * it->by;
-  it->nprep = (it->nb + 3) / 4;
+  it->bpw = clear_blocks_per_wave(it->nb);
+  it->nprep = clear_block_units(it->nb);
   if (!f) return EMX_OK;
   for (int k = 0; k < 12; ++k)
     if (!isfinite(f->pose[k])) return fail(EMX_EINVAL, "pose has a non-finite entry");

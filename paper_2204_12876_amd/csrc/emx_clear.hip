@@ -217,27 +217,36 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
 __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
   const int lane = threadIdx.x & 63;
   if (unit < it.nprep) {
-    // ---- block role: one wave per block of cells
-    const int b = unit * (kNTc / 64) + (threadIdx.x >> 6);
-    if (b >= it.nb) return;  // whole wave leaves together
+    // ---- block role: each wave takes it.bpw (1 or 4) blocks of 8 x 8 cells,
+    // one cell of each per lane, so their loads are in flight together
+    const int b0 = (unit * (kNTc / 64) + (threadIdx.x >> 6)) * it.bpw;
     const int side = 1 << it.bl;
-    const int x0 = (b % it.bx) << it.bl;
-    const int y0 = (b / it.bx) << it.bl;
-    // one cell per lane (blocks are 8 x 8)
-    const int ix = x0 + (lane & (side - 1));
-    const int iy = y0 + (lane >> it.bl);
-    const bool inside = ix < it.c.nx && iy < it.c.ny;
-    const int64_t c = (int64_t)iy * it.c.nx + ix;
-    const bool ok = inside && clearable(it, c);
-    const float h = inside ? it.L.h[c] : 0.0f;
-    float v = ok ? h : -INFINITY;
+    int64_t c[kMaxBlocksPerWave];
+    bool inside[kMaxBlocksPerWave], ok[kMaxBlocksPerWave];
+    float h[kMaxBlocksPerWave], v[kMaxBlocksPerWave];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    if (lane == 0) it.L.cmax[b] = v;
-    // the march reads records only in blocks with a removable cell, where
-    // some sample may pass below the block maximum
-    if (v > -INFINITY && inside)
-      it.L.clr[c] = make_float4(ok ? h : -INFINITY, it.L.v[c], it.L.nx[c], it.L.ny[c]);
+    for (int j = 0; j < kMaxBlocksPerWave; ++j) {
+      const int b = b0 + j;
+      const int ix = ((b % it.bx) << it.bl) + (lane & (side - 1));
+      const int iy = ((b / it.bx) << it.bl) + (lane >> it.bl);
+      inside[j] = j < it.bpw && b < it.nb && ix < it.c.nx && iy < it.c.ny;
+      c[j] = inside[j] ? (int64_t)iy * it.c.nx + ix : 0;
+      ok[j] = inside[j] && clearable(it, c[j]);
+      h[j] = inside[j] ? it.L.h[c[j]] : 0.0f;
+      v[j] = ok[j] ? h[j] : -INFINITY;
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxBlocksPerWave; ++j) {
+      if (j >= it.bpw) break;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v[j] = fmaxf(v[j], __shfl_xor(v[j], o, 64));
+      if (lane == 0 && b0 + j < it.nb) it.L.cmax[b0 + j] = v[j];
+      // the march reads records only in blocks with a removable cell, where
+      // some sample may pass below the block maximum
+      if (v[j] > -INFINITY && inside[j])
+        it.L.clr[c[j]] = make_float4(ok[j] ? h[j] : -INFINITY, it.L.v[c[j]], it.L.nx[c[j]],
+                                     it.L.ny[c[j]]);
+    }
     return;
   }
   // ---- ray role
@@ -351,17 +360,46 @@ __device__ __forceinline__ void march_entry(const Item& it, const ClearQueue& cq
   march_range<true>(it, r, ka, ka + cnt - 1, cq.ray_end[e.x], cm);
 }
 
-__device__ __forceinline__ void apply_body(const Item& it, int64_t unit) {
-  const int64_t i = unit * kNTc + threadIdx.x;
-  if (unit == 0 && threadIdx.x < kSubQ) it.cq.counter[threadIdx.x * kCtrStride] = 0u;
-  if (i >= (int64_t)it.c.nx * it.c.ny) return;
-  const uint8_t m = it.L.mark[i];
-  if (it.out_cleared) it.out_cleared[i] = m;
+// Apply: 16 cells per thread, one 16-byte load of marks; a cell is reset
+// only where its mark is set (rare).
+constexpr int kApplyPer = 16;
+constexpr int kApplyCells = kNTc * kApplyPer;
+
+__device__ __forceinline__ void apply_cell(const Item& it, int64_t i, uint8_t m) {
   if (m) {
     it.L.h[i] = it.c.h_init;
     it.L.v[i] = it.c.v_init;
     it.L.valid[i] = 0;
     it.L.mark[i] = 0;
+  }
+}
+
+__device__ __forceinline__ void apply_body(const Item& it, int64_t unit) {
+  if (unit == 0 && threadIdx.x < kSubQ) it.cq.counter[threadIdx.x * kCtrStride] = 0u;
+  const int64_t C = (int64_t)it.c.nx * it.c.ny;
+  const int64_t i0 = unit * kApplyCells + (int64_t)threadIdx.x * kApplyPer;
+  if (i0 >= C) return;
+  uint8_t* out = it.out_cleared;
+  if (i0 + kApplyPer <= C) {
+    // the mark layer is 256-byte aligned and i0 a multiple of 16
+    const uint4 q = *reinterpret_cast<const uint4*>(it.L.mark + i0);
+    if (out) {
+      if (((uintptr_t)(out + i0) & 15u) == 0) {
+        *reinterpret_cast<uint4*>(out + i0) = q;
+      } else {
+        for (int j = 0; j < kApplyPer; ++j) out[i0 + j] = it.L.mark[i0 + j];
+      }
+    }
+    if ((q.x | q.y | q.z | q.w) == 0u) return;
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int j = 0; j < kApplyPer; ++j) apply_cell(it, i0 + j, (uint8_t)(w[j >> 2] >> (8 * (j & 3))));
+    return;
+  }
+  for (int64_t i = i0; i < C; ++i) {  // the ragged end of the map
+    const uint8_t m = it.L.mark[i];
+    if (out) out[i] = m;
+    apply_cell(it, i, m);
   }
 }
 
@@ -473,7 +511,7 @@ hipError_t launch_clear(const Item& it, int march_grid, hipStream_t stream) {
     if (err != hipSuccess) return err;
   }
   TimedLaunch tl("k_clear_apply", stream);
-  hipLaunchKernelGGL(k_clear_apply, dim3((unsigned)((cells + kNTc - 1) / kNTc)), dim3(kNTc), 0,
+  hipLaunchKernelGGL(k_clear_apply, dim3((unsigned)clear_apply_units(cells)), dim3(kNTc), 0,
                      stream, it);
   return hipGetLastError();
 }
@@ -481,7 +519,12 @@ hipError_t launch_clear(const Item& it, int march_grid, hipStream_t stream) {
 int clear_setup_units(int64_t n, int nprep) {
   return n > 0 ? nprep + (int)((n + kNTc - 1) / kNTc) : 0;
 }
-int64_t clear_apply_units(int64_t cells) { return (cells + kNTc - 1) / kNTc; }
+int clear_blocks_per_wave(int nb) { return nb >= 4096 ? kMaxBlocksPerWave : 1; }
+int clear_block_units(int nb) {
+  const int per = (kNTc / 64) * clear_blocks_per_wave(nb);
+  return (nb + per - 1) / per;
+}
+int64_t clear_apply_units(int64_t cells) { return (cells + kApplyCells - 1) / kApplyCells; }
 
 hipError_t launch_clear_batch(const Batch* d_batch, int grid_setup, int grid_march,
                               int grid_apply, hipStream_t stream) {

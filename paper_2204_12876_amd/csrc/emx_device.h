@@ -50,6 +50,9 @@ struct Layers {
 // Clearing prunes samples by square blocks of 8 x 8 cells: one cell per lane
 // of the wave that computes a block's maximum (the setup relies on it).  The maxima are read through
 // the caches, so their count is not bounded by LDS.
+// The setup's block role gives a wave 1 block, or 4 on maps of at least 4096
+// blocks, where more work per wave beats more waves.
+constexpr int kMaxBlocksPerWave = 4;
 __host__ __device__ inline int blocks_of(int n, int b) { return (n + (1 << b) - 1) >> b; }
 __host__ __device__ inline int block_log_of(int nx, int ny) {
   (void)nx;
@@ -129,6 +132,7 @@ struct Item {
   int64_t ray_base;  // this item's first ray in cq
   int tiles_x, T, B;
   int bl, bx, by, nb, nprep;
+  int bpw;           // clearing blocks per wave in the setup's block role
   int32_t index;     // position in its batch
 };
 

@@ -40,6 +40,9 @@ hipError_t launch_fuse_batch(const Batch* d_batch, bool key64, int grid_chunk, i
 int64_t clear_queue_cap(int64_t max_points, int seg);
 size_t clear_scratch_layout(int64_t max_points, int seg, char* base, ClearQueue* out);
 int clear_setup_units(int64_t n, int nprep);
+// Blocks per wave and workgroups of the setup's block role for nb pruning blocks.
+int clear_blocks_per_wave(int nb);
+int clear_block_units(int nb);
 int64_t clear_apply_units(int64_t cells);
 // The item's queue counters must be zero on entry; the call leaves them zero.
 hipError_t launch_clear(const Item& it, int march_grid, hipStream_t stream);

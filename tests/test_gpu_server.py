@@ -56,10 +56,12 @@ def _trace(seed, frames_per_robot=4, span_s=0.02):
             reqs.append(Request(robot=k, xyz=xyz, pose=P, t_ms=200 * (f + 1), center=(cx, cy),
                                 arrival=float(rng.uniform(0, span_s)), seq=seq))
             seq += 1
-    # per robot, frames arrive in order
+    # per robot, frames arrive in order; every robot's first frame at time 0,
+    # so that the first batches hold several frames whatever the device speed
     for k in range(len(SHAPES)):
         mine = sorted((r for r in reqs if r.robot == k), key=lambda r: r.t_ms)
         times = sorted(r.arrival for r in mine)
+        times[0] = 0.0
         for r, t in zip(mine, times):
             r.arrival = t
     return reqs
