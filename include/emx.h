@@ -108,8 +108,9 @@ const char* emx_last_error(void);
 /* Host-only check of a parameter block.  Returns EMX_OK or EMX_EINVAL. */
 emx_status emx_params_check(const emx_params* params);
 
-/* Device bytes of one map's state, including the second buffer set that
- * move_map writes into.  Returns 0 for invalid parameters. */
+/* Device bytes of one map's state: two buffer sets of layers (move_map writes
+ * the shifted map into the other set), 16 bytes of clearing scratch per cell
+ * and a small control block.  Returns 0 for invalid parameters. */
 size_t emx_state_bytes(const emx_params* params);
 
 /* Device scratch bytes emx_fuse_points and emx_clear_visibility need for
@@ -161,8 +162,9 @@ emx_status emx_move_map(emx_map* map, double cx, double cy, void* stream);
  *   valid = 1, t_upd = t_ms - t0.
  *   This equals Eq. 1 and 2 applied point by point, in exact arithmetic.
  *   The float32 sums are formed in a fixed order of the points.  That order
- *   depends only on the frame (chunks of 2048 points in index order), so
- *   results are identical from run to run.
+ *   depends only on the frame (chunks of 1024 points in index order: a pairwise
+ *   tree over a cell's points within a chunk, then chunk partials in chunk
+ *   order), so results are identical from run to run and across batching.
  * Cells with no accepted point are left bitwise unchanged.
  *   d_scratch:    >= emx_scratch_bytes(params, frame->n) bytes, 256-aligned.
  *   d_out_cell:   optional int32[n]: cell, or -1 (dropped or outside).
@@ -309,7 +311,8 @@ emx_status emx_pipeline_batch(emx_batch* batch, const emx_batch_item* items, int
  * events on its own stream; batched calls are not timed.  end waits for the
  * recorded events and writes a JSON object to buf (len bytes):
  *   {"<kernel>": [launches, total_ms], ...}
- * in order of first launch.  Meant for one host thread; the events add a
+ * in order of first launch, then forgets them: a second end without a new
+ * begin reports {}.  Meant for one host thread; the events add a
  * little time between kernels, not inside them. */
 emx_status emx_timing_begin(void);
 emx_status emx_timing_end(char* buf, size_t len);

@@ -99,6 +99,11 @@ emx_status emx_timing_end(char* buf, size_t len) {
     ++count[k];
     total[k] += ms;
   }
+  for (const Mark& m : g_marks) {  // the report is taken: recycle the events
+    g_free.push_back(m.a);
+    g_free.push_back(m.b);
+  }
+  g_marks.clear();
   size_t w = (size_t)snprintf(buf, len, "{");
   for (size_t k = 0; k < names.size() && w < len; ++k)
     w += (size_t)snprintf(buf + w, len - w, "%s\"%s\": [%ld, %.6f]", k ? ", " : "", names[k],

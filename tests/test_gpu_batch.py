@@ -6,6 +6,7 @@ launch geometry, or whether a captured graph or direct launches run it.
 Graphs are replayed over several frames, with the plain calls and host
 synchronisation between replays, and every replay is checked.
 """
+import json
 import math
 
 import numpy as np
@@ -285,3 +286,79 @@ def test_batch_rejects_bad_batches_without_touching_maps(dev):
     for mm in [a, b, c] + maps:
         mm.close()
     pb.close()
+
+
+def test_batch_stats_count_graph_captures(dev):
+    """A repeated batch shape replays its cached graph; a new shape captures."""
+    from paper_2204_12876_amd import BatchEntry, ElevationMap, PipelineBatch
+    _say("batch stats")
+    w = torch.from_numpy(synth.trav_weights()).to(dev)
+    pb = PipelineBatch('{"graph": 1}', device=dev)
+    m = ElevationMap(dict(nx=64, ny=64, resolution=0.05), device=dev)
+    x = torch.zeros(3000, device=dev)
+    pose = _pose((0.0, 0.0, 1.0))
+    for k in range(3):
+        pb.run([BatchEntry(m, x + 0.01 * k, x, x - 1.0, pose, 100 * (k + 1), center=(0.0, 0.0),
+                           weights=w)])
+    torch.cuda.synchronize()
+    assert pb.stats() == (3, 1)
+    y = torch.zeros(300000, device=dev)  # many more chunks: other grid sizes
+    pb.run([BatchEntry(m, y, y, y - 1.0, pose, 400, center=(0.0, 0.0), weights=w)])
+    torch.cuda.synchronize()
+    assert pb.stats() == (4, 2)
+    pb.close()
+    m.close()
+
+
+def test_batch_scratch_bound_covers_every_batch(dev):
+    from paper_2204_12876_amd import BatchEntry, ElevationMap, PipelineBatch, _emx
+    _say("batch scratch bound")
+    rng = np.random.default_rng(21)
+    largest = dict(nx=300, ny=280, resolution=0.05)
+    maps = [ElevationMap(dict(nx=int(rng.integers(3, 301)), ny=int(rng.integers(3, 281)),
+                              resolution=0.05), device=dev) for _ in range(20)]
+    x = torch.zeros(200000, device=dev)
+    pose = _pose((0.0, 0.0, 1.0))
+    for seg in (16, 32, 128):
+        pb = PipelineBatch(json.dumps({"seg": seg}), device=dev)
+        bound = pb.scratch_bound(largest, 20, 200000)
+        for trial in range(5):
+            n = int(rng.integers(1, 21))
+            sizes = rng.multinomial(200000, np.ones(n) / n)
+            entries = [BatchEntry(maps[i], x[:s], x[:s], x[:s], pose, 10,
+                                  stages=int(rng.integers(0, 32)) | _emx.STAGE_FUSE,
+                                  center=(0.0, 0.0), weights=torch.zeros(89, device=dev))
+                       for i, s in enumerate(sizes)]
+            arr = _emx.make_batch_items([e.item() for e in entries])
+            need = _emx.batch_scratch_bytes(pb.handle, arr, n)
+            assert 0 < need <= bound, (seg, n, need, bound)
+        pb.close()
+    for m in maps:
+        m.close()
+
+
+def test_kernel_timing_reports_each_kernel(dev):
+    from paper_2204_12876_amd import ElevationMap, _emx
+    _say("kernel timing")
+    d = synth.cfg0(n_frames=2)
+    m = ElevationMap(d["params"], device=dev)
+    w = torch.from_numpy(synth.trav_weights()).to(dev)
+    f0, f1 = d["frames"]
+    xyz0 = tuple(t.to(dev).contiguous() for t in (f0.x, f0.y, f0.z))
+    xyz1 = tuple(t.to(dev).contiguous() for t in (f1.x, f1.y, f1.z))
+    m.fuse_points(*xyz0, f0.pose, 0)
+    m.compute_normals()
+    torch.cuda.synchronize()
+    _emx.timing_begin()
+    m.move_map(0.5, 0.0)
+    m.fuse_points(*xyz1, f1.pose, 1000)
+    m.clear_visibility(*xyz1, f1.pose, 1000)
+    m.compute_normals()
+    m.traversability(w)
+    rep = _emx.timing_end()
+    for k in ("k_move", "k_fuse_chunk", "k_fuse_tile", "k_clear_setup", "k_clear_march",
+              "k_clear_apply", "k_normals", "k_trav"):
+        assert k in rep and rep[k][0] == 1 and rep[k][1] > 0.0, (k, rep)
+    m.compute_normals()               # not timed once ended
+    assert _emx.timing_end() == {}
+    m.close()
