@@ -167,14 +167,15 @@ __device__ __forceinline__ void test_cell_rec(const Item& it, const Ray& r, int 
   if ((dot * dot) > an2dd) it.L.mark[c] = 1;
 }
 
-constexpr int kUnroll = 16;
+constexpr int kUnroll = 8;
 
 // Test samples k in [ka, kb] of ray r against the map.  With kRec, cm holds
 // the block maxima and the cells' clearing records are read; without, every
 // sample is tested against the layers (same result, no pruning), for use
 // while the setup is still writing maxima and records.
 // kUnroll samples at a time: their cells and block maxima are found without
-// branches, so the block-maximum loads issue together.
+// branches, so the block-maximum loads issue together.  The march is bound by
+// instruction issue, so the per-sample work is kept to the sample itself.
 template <bool kRec>
 __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka, int kb,
                                             int end_cell, const float* cm) {
@@ -182,9 +183,8 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
   const int bl = it.bl;
   const int bx = it.bx;
   const float inv_r = it.c.inv_r;
-  const float nxf = it.c.nxf;
-  const float nyf = it.c.nyf;
   const int nx = it.c.nx;
+  const int ny = it.c.ny;
   for (int k = ka; k <= kb; k += kUnroll) {
     int cell[kUnroll];
     float qz[kUnroll];
@@ -195,14 +195,15 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
       const float qx = r.ox + t * r.dx;
       const float qy = r.oy + t * r.dy;
       qz[u] = r.oz + t * r.dz;
-      const float fx = qx * inv_r;
-      const float fy = qy * inv_r;
-      const bool in = (k + u <= kb) && fx >= 0.0f && fx < nxf && fy >= 0.0f && fy < nyf;
-      const int ix = in ? (int)floorf(fx) : 0;
-      const int iy = in ? (int)floorf(fy) : 0;
+      // [ka, kb] lies in the ray's in-map range, which the setup found with
+      // this very evaluation: qx * inv_r and qy * inv_r are in [0, nx) and
+      // [0, ny), so truncation is floor.  The clamp only keeps the unused
+      // samples past kb in bounds.
+      const int ix = min(max((int)(qx * inv_r), 0), nx - 1);
+      const int iy = min(max((int)(qy * inv_r), 0), ny - 1);
       cell[u] = iy * nx + ix;
       const float m = kRec ? cm[(iy >> bl) * bx + (ix >> bl)] : INFINITY;
-      cand[u] = in && (qz[u] < m) && cell[u] != end_cell;
+      cand[u] = (k + u <= kb) && (qz[u] < m) && cell[u] != end_cell;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
