@@ -162,9 +162,10 @@ emx_status emx_move_map(emx_map* map, double cx, double cy, void* stream);
  *   valid = 1, t_upd = t_ms - t0.
  *   This equals Eq. 1 and 2 applied point by point, in exact arithmetic.
  *   The float32 sums are formed in a fixed order of the points.  That order
- *   depends only on the frame (chunks of 1024 points in index order: a pairwise
- *   tree over a cell's points within a chunk, then chunk partials in chunk
- *   order), so results are identical from run to run and across batching.
+ *   depends only on the frame (chunks of 1024 points in index order: a
+ *   segmented scan over a chunk's points sorted by cell and index, then chunk
+ *   partials in chunk order), so results are identical from run to run and
+ *   across batching.
  * Cells with no accepted point are left bitwise unchanged.
  *   d_scratch:    >= emx_scratch_bytes(params, frame->n) bytes, 256-aligned.
  *   d_out_cell:   optional int32[n]: cell, or -1 (dropped or outside).

@@ -6,7 +6,8 @@
 //     gate against the frame-start prior.
 //   - Sorts the accepted points in LDS by (tile, cell in tile, point index).
 //   - Each cell's run is reduced to one partial, sum 1/sp2 and sum zm/sp2, by
-//     a pairwise tree aligned to the run start.
+//     a segmented inclusive scan over the sorted keys (thread, wave, then a
+//     carry across waves), read at the run's last key.
 //   - Writes the partials, grouped by tile, and a dense tile directory row for
 //     the chunk.
 // Pass 2, tile body: one workgroup per 32x32-cell map tile, one thread per cell.
@@ -18,10 +19,10 @@
 //   - Each thread adds its cell's list in chunk order and applies the
 //     information-form update once.
 //
-// The float32 sums therefore run in an order fixed by the frame alone: a
-// pairwise tree over a cell's points in point order within each chunk, then
-// chunk partials left to right in chunk order.  Results are bitwise identical
-// from run to run, whatever the tile size, grid shape or batching.
+// The float32 sums therefore run in an order fixed by the frame alone: the
+// scan over each chunk's sorted keys (chunks are fixed slices of the frame),
+// then chunk partials left to right in chunk order.  Results are bitwise
+// identical from run to run, whatever the tile size, grid shape or batching.
 #include "emx_kernels.h"
 
 namespace emx {
@@ -136,9 +137,6 @@ __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
   __shared__ float s_w[kChunk];
   __shared__ float s_wz[kChunk];
   __shared__ uint32_t s_seg[kChunk];   // (tile << kSegBits | local) of record r
-  __shared__ float s_vw[kChunk];       // per-key values in sorted order (tree sums)
-  __shared__ float s_vwz[kChunk];
-  __shared__ int16_t s_head[kChunk];   // position of each key's run head
   __shared__ int s_isum[kNT1 / 64];
 
   const int tid = threadIdx.x;
@@ -191,104 +189,113 @@ __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
   s_key[2 * tid + 1] = key[1];
   __syncthreads();
 
-  // ---- one partial per (tile, local) run.  Each run is reduced by a pairwise
-  // tree aligned to the run's first key: at level L the key at offset j
-  // (j a multiple of 2^(L+1)) absorbs the key at j + 2^L if that one is in the
-  // run.  The tree depends only on the run's length, never on where the run
-  // landed in the sorted array.
-  int heads = 0;
-  int hpos[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int q = 2 * tid + j;
-    const bool h = q < nacc && (q == 0 || (s_key[q - 1] >> kPBits) != (s_key[q] >> kPBits));
-    hpos[j] = h ? q : -1;
-    heads += h ? 1 : 0;
+  // ---- one partial per (tile, local) run, by a segmented inclusive scan over
+  // the sorted keys: within the thread, then across the wave's lanes, then a
+  // carry across waves.  A run's sum is the scan value at its last key.  The
+  // order of the additions is fixed by the chunk's sorted keys, which depend
+  // only on the frame.
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int q0 = 2 * tid;
+  const int q1 = q0 + 1;
+  const uint32_t k0 = (uint32_t)(s_key[q0] >> kPBits);
+  const uint32_t k1 = (uint32_t)(s_key[q1] >> kPBits);
+  // run heads; keys past nacc start segments of their own and hold zero
+  const bool f0 = q0 >= nacc || q0 == 0 || (uint32_t)(s_key[q0 - (q0 > 0)] >> kPBits) != k0;
+  const bool f1 = q1 >= nacc || k0 != k1;
+  float w0 = 0.0f, wz0 = 0.0f, w1 = 0.0f, wz1 = 0.0f;
+  if (q0 < nacc) {
+    const int p = (int)(s_key[q0] & (KeyT)(kChunk - 1));
+    w0 = s_w[p];
+    wz0 = s_wz[p];
   }
-  // run head of every key: inclusive max-scan of head positions
-  {
-    const int m0 = hpos[0];
-    const int m1 = max(hpos[0], hpos[1]);
-    const int lane = tid & 63;
-    const int wid = tid >> 6;
-    int x = m1;
+  if (q1 < nacc) {
+    const int p = (int)(s_key[q1] & (KeyT)(kChunk - 1));
+    w1 = s_w[p];
+    wz1 = s_wz[p];
+  }
+  // the thread's two keys, then the wave: (flag, value) pairs combine as
+  // earlier (+) later = later's flag ? later : earlier + later
+  bool tf = f0 || f1;
+  float tw = f1 ? w1 : w0 + w1;
+  float twz = f1 ? wz1 : wz0 + wz1;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x = max(x, y);
-    }
-    if (lane == 63) s_isum[wid] = x;
-    int ex = __shfl_up(x, 1, 64);
-    if (lane == 0) ex = -1;
-    __syncthreads();
-    int pre = -1;
-    for (int w = 0; w < wid; ++w) pre = max(pre, s_isum[w]);
-    __syncthreads();
-    ex = max(ex, pre);
-    s_head[2 * tid] = (int16_t)max(ex, m0);
-    s_head[2 * tid + 1] = (int16_t)max(ex, m1);
-    // values in sorted order
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int q = 2 * tid + j;
-      if (q < nacc) {
-        const int p = (int)(s_key[q] & (KeyT)(kChunk - 1));
-        s_vw[q] = s_w[p];
-        s_vwz[q] = s_wz[p];
+  for (int o = 1; o < 64; o <<= 1) {
+    const bool pf = __shfl_up((int)tf, o, 64) != 0;
+    const float pw = __shfl_up(tw, o, 64);
+    const float pwz = __shfl_up(twz, o, 64);
+    if (lane >= o) {
+      if (!tf) {
+        tw = pw + tw;
+        twz = pwz + twz;
       }
+      tf = tf || pf;
     }
+  }
+  __shared__ int s_wf[kNT1 / 64];
+  __shared__ float s_ww[kNT1 / 64];
+  __shared__ float s_wwz[kNT1 / 64];
+  if (lane == 63) {
+    s_wf[wid] = tf ? 1 : 0;
+    s_ww[wid] = tw;
+    s_wwz[wid] = twz;
+  }
+  // the exclusive prefix of this thread within its wave
+  bool ef = __shfl_up((int)tf, 1, 64) != 0;
+  float ew = __shfl_up(tw, 1, 64);
+  float ewz = __shfl_up(twz, 1, 64);
+  if (lane == 0) {
+    ef = false;
+    ew = 0.0f;
+    ewz = 0.0f;
   }
   __syncthreads();
-  // tree levels: ceil(log2(longest run)); a partner is in the run iff it
-  // has the same head
-  int levels = 0;
-  {
-    int longest = 0;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int q = 2 * tid + j;
-      if (q < nacc && (q == nacc - 1 || s_head[q + 1] != s_head[q]))
-        longest = max(longest, q - (int)s_head[q] + 1);
+  // carry from the preceding waves, combined in wave order
+  float cw = 0.0f, cwz = 0.0f;
+  for (int v = 0; v < wid; ++v) {
+    if (s_wf[v]) {
+      cw = s_ww[v];
+      cwz = s_wwz[v];
+    } else {
+      cw = cw + s_ww[v];
+      cwz = cwz + s_wwz[v];
     }
-    int all = 0;
-    const int lane = tid & 63;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) longest = max(longest, __shfl_xor(longest, o, 64));
-    if (lane == 0) s_isum[tid >> 6] = longest;
-    __syncthreads();
-    for (int w = 0; w < kNT1 / 64; ++w) all = max(all, s_isum[w]);
-    __syncthreads();
-    while ((1 << levels) < all) ++levels;
   }
-  for (int L = 0; L < levels; ++L) {
-    const int st = 1 << L;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int q = 2 * tid + j;
-      if (q >= nacc) continue;
-      const int off = q - (int)s_head[q];
-      if ((off & (2 * st - 1)) != 0) continue;
-      const int pq = q + st;
-      if (pq < nacc && s_head[pq] == s_head[q]) {
-        s_vw[q] = s_vw[q] + s_vw[pq];
-        s_vwz[q] = s_vwz[q] + s_vwz[pq];
-      }
-    }
-    __syncthreads();
+  float pw, pwz;  // sum of the run's keys before q0
+  if (lane == 0) {
+    pw = cw;
+    pwz = cwz;
+  } else if (ef) {
+    pw = ew;
+    pwz = ewz;
+  } else {
+    pw = cw + ew;
+    pwz = cwz + ewz;
   }
+  const float i0w = f0 ? w0 : pw + w0;
+  const float i0wz = f0 ? wz0 : pwz + wz0;
+  const float i1w = f1 ? w1 : i0w + w1;
+  const float i1wz = f1 ? wz1 : i0wz + wz1;
+  // run tails, one record each, in run order
+  const bool t0 = q0 < nacc && f1;
+  const bool t1 = q1 < nacc &&
+                  (q1 == nacc - 1 || (uint32_t)(s_key[q1 + (q1 + 1 < kChunk)] >> kPBits) != k1);
   int nrec = 0;
-  int r = block_exclusive_sum<kNT1>(heads, nrec, s_isum);
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    if (hpos[j] < 0) continue;
-    const int q = hpos[j];
-    const uint32_t sk = (uint32_t)(s_key[q] >> kPBits);
+  int r = block_exclusive_sum<kNT1>((t0 ? 1 : 0) + (t1 ? 1 : 0), nrec, s_isum);
+  if (t0) {
     const int64_t o = base + r;
-    it.fs.rec_local[o] = (uint16_t)(sk & (kTileCells - 1));
-    it.fs.rec_w[o] = s_vw[q];
-    it.fs.rec_wz[o] = s_vwz[q];
-    s_seg[r] = sk;
+    it.fs.rec_local[o] = (uint16_t)(k0 & (kTileCells - 1));
+    it.fs.rec_w[o] = i0w;
+    it.fs.rec_wz[o] = i0wz;
+    s_seg[r] = k0;
     ++r;
+  }
+  if (t1) {
+    const int64_t o = base + r;
+    it.fs.rec_local[o] = (uint16_t)(k1 & (kTileCells - 1));
+    it.fs.rec_w[o] = i1w;
+    it.fs.rec_wz[o] = i1wz;
+    s_seg[r] = k1;
   }
   __syncthreads();
 
