@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--points", type=int, default=300000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=12)
+    ap.add_argument("--cpu-frames", type=int, default=50)
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-server", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=20)
