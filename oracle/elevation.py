@@ -55,6 +55,14 @@ listed with its reason in the design notes):
   * Map geometry: cells are half-open and the map is robot-centric.  The centre
     cell is floor(c / r), computed in float64.  The translation is moved into
     map-local coordinates in float64 before rounding to float32.
+  * Time variance sigma_t^2 is added once per fusion to every valid cell the
+    fusion does not update.
+  * The wall/edge rule counts a frame's valid in-map points per cell before
+    any gate; in cells that hold an estimate and receive more than the
+    threshold, points below the estimate are ignored.
+  * Drift compensation averages z - h over valid in-map points in valid cells
+    whose traversability exceeds a threshold, and adds the mean to every valid
+    cell's height before fusion.
 """
 from __future__ import annotations
 
@@ -66,7 +74,7 @@ import numpy as np
 
 __all__ = [
     "Params", "MapState", "init_map", "local_pose", "point_decisions", "fuse",
-    "fuse_sequential", "clear_visibility", "apply_clear", "compute_normals",
+    "compensate_drift", "fuse_sequential", "clear_visibility", "apply_clear", "compute_normals",
     "traversability", "move_map", "f32_constants",
 ]
 
@@ -87,6 +95,8 @@ class Params:
     ray_step: float = 0.04
     clear_normal_alpha: float = 0.3
     clear_min_age_ms: int = 500
+    time_variance: float = 0.0     # sigma_t^2 added per fusion to cells it leaves alone
+    wall_min_count: int = 0        # wall/edge rule threshold; 0 turns the rule off
 
     @classmethod
     def from_dict(cls, d: dict) -> "Params":
@@ -114,6 +124,7 @@ def f32_constants(p: Params) -> dict:
         alpha=F32(p.noise_alpha),
         h_init=F32(p.init_height),
         v_init=F32(p.init_variance),
+        var_t=F32(p.time_variance),
     )
 
 
@@ -204,8 +215,17 @@ def point_decisions(p: Params, st: MapState, xs, ys, zs, pose):
         v0 = st.v.reshape(-1)[cc]
         e = zm - h0
         accept = inmap & ((e * e) <= (c["k2"] * (v0 + sp2)))
+        # Wall/edge rule (Sec. II-C): where more than wall_min_count of the
+        # frame's valid points fall into one cell that holds an estimate, the
+        # points below that estimate are ignored.  It acts before the gate.
+        walled = np.zeros_like(accept)
+        if p.wall_min_count > 0:
+            count = np.bincount(cell[inmap], minlength=p.nx * p.ny)
+            crowded = (count[cc] > p.wall_min_count) & (st.valid.reshape(-1)[cc] != 0)
+            walled = inmap & crowded & (zm < h0)
+            accept = accept & ~walled
     return dict(xm=xm, ym=ym, zm=zm, d2=d2, sp2=sp2, valid=valid, cell=cell,
-                accept=accept, R=R, t=t)
+                accept=accept, walled=walled, R=R, t=t)
 
 
 @dataclasses.dataclass
@@ -233,6 +253,7 @@ def fuse(p: Params, st: MapState, xs, ys, zs, pose, t_ms: int) -> FuseResult:
     float32 inputs.  Gate decisions come from ``point_decisions`` (float32).
     """
     d = point_decisions(p, st, xs, ys, zs, pose)
+    c32 = f32_constants(p)
     C = p.nx * p.ny
     acc = d["accept"]
     cell = d["cell"]
@@ -262,13 +283,53 @@ def fuse(p: Params, st: MapState, xs, ys, zs, pose, t_ms: int) -> FuseResult:
     new = st.copy()
     t_now = int(t_ms) - st.t0
     new.h = np.where(upd, h1, st.h.reshape(-1)).astype(F32).reshape(p.ny, p.nx)
-    new.v = np.where(upd, v1, st.v.reshape(-1)).astype(F32).reshape(p.ny, p.nx)
+    # Time variance (Sec. II-C): every valid cell this fusion does not update
+    # grows by sigma_t^2, once per fusion (the frame rate is the constant rate).
+    # It is one float32 addition of two stored float32 values.
+    v_keep = st.v.reshape(-1)
+    if p.time_variance != 0.0:
+        grow = ~upd & (st.valid.reshape(-1) != 0)
+        v_keep = np.where(grow, v_keep + c32["var_t"], v_keep)
+        v1 = np.where(grow, v_keep.astype(F64), v1)
+    new.v = np.where(upd, v1, v_keep).astype(F32).reshape(p.ny, p.nx)
     new.valid = np.where(upd, 1, st.valid.reshape(-1)).astype(np.uint8).reshape(p.ny, p.nx)
     new.t_upd = np.where(upd, t_now, st.t_upd.reshape(-1)).astype(np.int32).reshape(p.ny, p.nx)
     shp = (p.ny, p.nx)
     return FuseResult(cell=cell, accept=acc, h=h1.reshape(shp), v=v1.reshape(shp),
                       updated=upd.reshape(shp), n_acc=n_acc.reshape(shp),
                       h_scale=hs.reshape(shp), state=new)
+
+
+def compensate_drift(p: Params, st: MapState, xs, ys, zs, pose, trav_min: float):
+    """Height drift compensation (Sec. II-D).
+
+    Each valid in-map point whose cell holds an estimate on flat ground
+    (traversability defined and above trav_min) gives the error between its
+    height and the map, e_i = zm_i - h[cell_i].  The mean error over those n
+    points is added to the height of every valid cell; with n = 0 nothing
+    changes.  Returns (new state, mean as float64, n).
+
+    The error and the threshold test use the float32 values the map and the
+    transform hold; the mean is formed in float64 and then added once, in
+    float32, to each height.
+    """
+    d = point_decisions(p, st, xs, ys, zs, pose)
+    cell = d["cell"]
+    inmap = cell >= 0
+    cc = np.where(inmap, cell, 0)
+    trav = st.trav.reshape(-1)[cc]
+    with np.errstate(invalid="ignore"):
+        flat = ~np.isnan(trav) & (trav > F32(trav_min))
+    use = inmap & (st.valid.reshape(-1)[cc] != 0) & flat
+    n = int(use.sum())
+    new = st.copy()
+    if n == 0:
+        return new, 0.0, 0
+    err = d["zm"][use].astype(F64) - st.h.reshape(-1)[cc[use]].astype(F64)
+    mean = float(err.sum() / n)
+    keep = st.valid != 0
+    new.h = np.where(keep, st.h + F32(mean), st.h).astype(F32)
+    return new, mean, n
 
 
 def fuse_sequential(p: Params, st: MapState, xs, ys, zs, pose):
