@@ -76,6 +76,11 @@ typedef struct {
   float ray_step;            /* clearing ray step (Sec. II-E), > 0                   */
   float clear_normal_alpha;  /* alpha_n of Eq. 4, >= 0                               */
   int32_t clear_min_age_ms;  /* clearing needs age > this (Sec. II-E), >= 0          */
+  float time_variance;       /* sigma_t^2 (Sec. II-C): each fuse_points call adds it */
+                             /* to every valid cell it does not update; >= 0, 0 off  */
+  int32_t wall_min_count;    /* wall/edge rule (Sec. II-C): in a valid cell that     */
+                             /* receives more than this many of a frame's points,    */
+                             /* points below its height are ignored; >= 0, 0 off     */
 } emx_params;
 
 /* One point cloud in the sensor frame, structure of arrays. */
@@ -133,6 +138,21 @@ size_t emx_export_bytes(const emx_params* params);
 emx_status emx_init_map(const emx_params* params, double cx, double cy, int64_t t0_ms,
                         void* d_state, size_t state_bytes, void* stream, emx_map** out);
 
+/* Height drift compensation (Sec. II-D), meant to run just before
+ * emx_fuse_points on the same frame.  In float32, as emx_fuse_points decides:
+ * each valid point in the map whose cell is valid and has traversability
+ * above trav_min (NaN never is) contributes e = zm - h[cell], with e formed in
+ * float64.  Their mean, summed in float64 in a fixed order of the points, is
+ * added in float32 to the height of every valid cell; with no contributing
+ * point nothing changes.
+ *   d_scratch:     >= emx_drift_scratch_bytes(frame->n) bytes, 256-aligned.
+ *   d_out_mean:    optional double[1]: the mean (0 if none).
+ *   d_out_count:   optional int64[1]: the number of contributing points. */
+size_t emx_drift_scratch_bytes(int64_t max_points);
+emx_status emx_compensate_drift(emx_map* map, const emx_frame* frame, float trav_min,
+                                void* d_scratch, size_t scratch_bytes, double* d_out_mean,
+                                int64_t* d_out_count, void* stream);
+
 /* Release the host handle.  The caller frees d_state once the stream is idle. */
 emx_status emx_free_map(emx_map* map);
 
@@ -157,6 +177,9 @@ emx_status emx_move_map(emx_map* map, double cx, double cy, void* stream);
  *   Gate: e = zm - h0[cell]; accept iff e*e <= k2*(v0[cell] + sp2), with
  *   k2 = float32(gate_k^2).  h0 and v0 are the map's values when the call
  *   starts.
+ *   Wall/edge rule (wall_min_count > 0): a cell that is valid when the call
+ *   starts and receives more than wall_min_count of the frame's valid points
+ *   ignores those with zm < h0, before the gate (they are not accepted).
  * Per cell c with a non-empty accepted set A:
  *   W = 1/v0 + sum_A 1/sp2;  v = 1/W;  h = (h0/v0 + sum_A zm/sp2) * v
  *   valid = 1, t_upd = t_ms - t0.
@@ -166,7 +189,8 @@ emx_status emx_move_map(emx_map* map, double cx, double cy, void* stream);
  *   segmented scan over a chunk's points sorted by cell and index, then chunk
  *   partials in chunk order), so results are identical from run to run and
  *   across batching.
- * Cells with no accepted point are left bitwise unchanged.
+ * Cells with no accepted point are left bitwise unchanged, except that with
+ * time_variance > 0 each valid one gets v = v + float32(time_variance).
  *   d_scratch:    >= emx_scratch_bytes(params, frame->n) bytes, 256-aligned.
  *   d_out_cell:   optional int32[n]: cell, or -1 (dropped or outside).
  *   d_out_accept: optional uint8[n]: 1 iff the point passed the gate. */
@@ -239,7 +263,9 @@ emx_status emx_import_state(emx_map* map, const void* d_src, void* stream);
  *     run in the same order on that map: the same kernel bodies do the
  *     arithmetic, and every float32 sum has a fixed order.
  *   - The tuning selects only launch geometry (persistent grid sizes) and the
- *     clearing segment length.  It never changes results. */
+ *     clearing segment length.  It never changes results.
+ *   - Maps with time_variance or wall_min_count set are refused (EMX_EINVAL):
+ *     run those through the plain calls. */
 #define EMX_STAGE_MOVE 1u
 #define EMX_STAGE_FUSE 2u
 #define EMX_STAGE_CLEAR 4u

@@ -84,7 +84,7 @@ class ElevationMap:
         return _emx.make_frame(x.data_ptr(), y.data_ptr(), z.data_ptr(), n, pose, t_ms), n
 
     def scratch(self, n: int) -> torch.Tensor:
-        need = _emx.scratch_bytes(self.p, n)
+        need = max(_emx.scratch_bytes(self.p, n), _emx.drift_scratch_bytes(n))
         if self._scratch is None or self._scratch_bytes < need:
             self._scratch = aligned_empty(need, self.device)
             self._scratch_bytes = need
@@ -105,6 +105,19 @@ class ElevationMap:
                          out_cell.data_ptr() if out_cell is not None else 0,
                          out_accept.data_ptr() if out_accept is not None else 0,
                          _stream(self.device))
+
+    def compensate_drift(self, x, y, z, pose, t_ms: int, trav_min: float,
+                         scratch: torch.Tensor = None):
+        """Shift the valid heights by the frame's mean error on flat ground
+        (Sec. II-D); call before fuse_points with the same frame.  Returns
+        device tensors (mean float64[1], count int64[1]) without waiting."""
+        f, n = self._frame(x, y, z, pose, t_ms)
+        s = scratch if scratch is not None else self.scratch(n)
+        mean = torch.empty(1, dtype=torch.float64, device=self.device)
+        count = torch.empty(1, dtype=torch.int64, device=self.device)
+        _emx.compensate_drift(self.handle, f, float(trav_min), s.data_ptr(), s.numel(),
+                              mean.data_ptr(), count.data_ptr(), _stream(self.device))
+        return mean, count
 
     def clear_visibility(self, x, y, z, pose, t_ms: int, out_cleared: torch.Tensor = None,
                          scratch: torch.Tensor = None):

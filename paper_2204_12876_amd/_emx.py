@@ -38,7 +38,8 @@ class Params(Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("resolution", c_double),
                 ("init_height", c_float), ("init_variance", c_float), ("noise_alpha", c_float),
                 ("gate_k", c_float), ("min_range", c_float), ("ray_step", c_float),
-                ("clear_normal_alpha", c_float), ("clear_min_age_ms", c_int32)]
+                ("clear_normal_alpha", c_float), ("clear_min_age_ms", c_int32),
+                ("time_variance", c_float), ("wall_min_count", c_int32)]
 
 
 class Frame(Structure):
@@ -72,6 +73,9 @@ _SIGS = {
                                   c_void_p, c_void_p]),
     "emx_clear_visibility": (c_int32, [c_void_p, POINTER(Frame), c_void_p, c_size_t, c_void_p,
                                        c_void_p]),
+    "emx_drift_scratch_bytes": (c_size_t, [c_int64]),
+    "emx_compensate_drift": (c_int32, [c_void_p, POINTER(Frame), c_float, c_void_p, c_size_t,
+                                       c_void_p, c_void_p, c_void_p]),
     "emx_compute_normals": (c_int32, [c_void_p, c_void_p]),
     "emx_traversability": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "emx_layer": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
@@ -138,6 +142,8 @@ def make_params(d: dict) -> Params:
     p.ray_step = float(d.get("ray_step", d["resolution"]))
     p.clear_normal_alpha = float(d.get("clear_normal_alpha", 0.3))
     p.clear_min_age_ms = int(d.get("clear_min_age_ms", 500))
+    p.time_variance = float(d.get("time_variance", 0.0))
+    p.wall_min_count = int(d.get("wall_min_count", 0))
     return p
 
 
@@ -190,6 +196,18 @@ def fuse_points(h: int, f: Frame, d_scratch: int, nbytes: int, d_out_cell: int,
     check(lib().emx_fuse_points(c_void_p(h), byref(f), c_void_p(d_scratch), nbytes,
                                 c_void_p(d_out_cell or None), c_void_p(d_out_accept or None),
                                 c_void_p(stream)))
+
+
+def drift_scratch_bytes(max_points: int) -> int:
+    return lib().emx_drift_scratch_bytes(int(max_points))
+
+
+def compensate_drift(h: int, f: Frame, trav_min: float, d_scratch: int, nbytes: int,
+                     d_out_mean: int, d_out_count: int, stream: int):
+    check(lib().emx_compensate_drift(c_void_p(h), byref(f), float(trav_min),
+                                     c_void_p(d_scratch or None), nbytes,
+                                     c_void_p(d_out_mean or None), c_void_p(d_out_count or None),
+                                     c_void_p(stream)))
 
 
 def clear_visibility(h: int, f: Frame, d_scratch: int, nbytes: int, d_out_cleared: int,

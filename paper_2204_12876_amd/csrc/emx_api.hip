@@ -57,6 +57,9 @@ emx_status check_params(const emx_params* p) {
   if (!isfinite(p->clear_normal_alpha) || p->clear_normal_alpha < 0.0f)
     return fail(EMX_EINVAL, "clear_normal_alpha must be >= 0");
   if (p->clear_min_age_ms < 0) return fail(EMX_EINVAL, "clear_min_age_ms must be >= 0");
+  if (!isfinite(p->time_variance) || p->time_variance < 0.0f)
+    return fail(EMX_EINVAL, "time_variance must be >= 0");
+  if (p->wall_min_count < 0) return fail(EMX_EINVAL, "wall_min_count must be >= 0");
   return EMX_OK;
 }
 
@@ -76,6 +79,8 @@ Consts make_consts(const emx_params& p) {
   c.nxf = (float)p.nx;
   c.nyf = (float)p.ny;
   c.tau = p.clear_min_age_ms;
+  c.var_t = p.time_variance;
+  c.wall = p.wall_min_count;
   return c;
 }
 
@@ -208,7 +213,10 @@ size_t emx_scratch_bytes(const emx_params* params, int64_t max_points) {
     fail(EMX_EINVAL, "max_points must lie in [0, 2^31)");
     return 0;
   }
-  const size_t f = fuse_scratch_layout(max_points, tiles_of(*params), nullptr, nullptr);
+  const int64_t count_cells =
+      params->wall_min_count > 0 ? (int64_t)params->nx * params->ny : 0;
+  const size_t f = fuse_scratch_layout(max_points, tiles_of(*params), count_cells, nullptr,
+                                       nullptr);
   const size_t c = clear_scratch_layout(max_points, kDefaultSeg, nullptr, nullptr);
   return f > c ? f : c;
 }
@@ -293,14 +301,18 @@ emx_status emx_fuse_points(emx_map* m, const emx_frame* f, void* d_scratch, size
   if ((s = check_frame(f)) != EMX_OK) return s;
   Item it;
   if ((s = make_item(m, f, &it)) != EMX_OK) return s;
-  if (f->n == 0) return EMX_OK;
-  const size_t need = fuse_scratch_layout(f->n, it.T, nullptr, nullptr);
-  if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
-  if (((uintptr_t)d_scratch & 255u) != 0)
-    return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
-  if (scratch_bytes < need)
-    return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
-  fuse_scratch_layout(f->n, it.T, (char*)d_scratch, &it.fs);
+  if (f->n > 0) {
+    const int64_t count_cells = m->p.wall_min_count > 0 ? (int64_t)m->p.nx * m->p.ny : 0;
+    const size_t need = fuse_scratch_layout(f->n, it.T, count_cells, nullptr, nullptr);
+    if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
+    if (((uintptr_t)d_scratch & 255u) != 0)
+      return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
+    if (scratch_bytes < need)
+      return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
+    fuse_scratch_layout(f->n, it.T, count_cells, (char*)d_scratch, &it.fs);
+  } else if (m->p.time_variance == 0.0f) {
+    return EMX_OK;  // an empty frame changes nothing
+  }
   it.out_cell = d_out_cell;
   it.out_accept = d_out_accept;
   it.stages = kStageFuse;
@@ -332,6 +344,33 @@ emx_status emx_clear_visibility(emx_map* m, const emx_frame* f, void* d_scratch,
   it.stages = kStageClear;
   hipError_t e = launch_clear(it, m->march_grid, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "clear_visibility");
+  return EMX_OK;
+}
+
+size_t emx_drift_scratch_bytes(int64_t max_points) {
+  if (max_points < 0) return 0;
+  return drift_scratch_layout(max_points, nullptr, nullptr);
+}
+
+emx_status emx_compensate_drift(emx_map* m, const emx_frame* f, float trav_min, void* d_scratch,
+                                size_t scratch_bytes, double* d_out_mean, int64_t* d_out_count,
+                                void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if ((s = check_frame(f)) != EMX_OK) return s;
+  if (isnan(trav_min)) return fail(EMX_EINVAL, "trav_min is NaN");
+  Item it;
+  if ((s = make_item(m, f, &it)) != EMX_OK) return s;
+  const size_t need = drift_scratch_layout(f->n, nullptr, nullptr);
+  if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
+  if (((uintptr_t)d_scratch & 255u) != 0)
+    return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
+  if (scratch_bytes < need)
+    return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
+  DriftScratch ds;
+  drift_scratch_layout(f->n, (char*)d_scratch, &ds);
+  hipError_t e = launch_drift(it, trav_min, ds, d_out_mean, d_out_count, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "compensate_drift");
   return EMX_OK;
 }
 

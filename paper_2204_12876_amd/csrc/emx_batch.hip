@@ -107,6 +107,9 @@ emx_status check_items(const emx_batch_item* items, int32_t n) {
     if (s != EMX_OK) return s;
     if (items[i].stages & ~(uint32_t)EMX_STAGE_ALL)
       return fail(EMX_EINVAL, "item %d: unknown stage bits", i);
+    if (items[i].map->p.time_variance != 0.0f || items[i].map->p.wall_min_count != 0)
+      return fail(EMX_EINVAL,
+                  "item %d: maps with time_variance or wall_min_count use the plain calls", i);
     if ((items[i].stages & (EMX_STAGE_FUSE | EMX_STAGE_CLEAR)) &&
         (s = check_frame(&items[i].frame)) != EMX_OK)
       return s;
@@ -134,9 +137,9 @@ size_t batch_layout(const emx_batch_item* items, int32_t n, int seg, char* base,
   for (int32_t i = 0; i < n; ++i) {
     const int64_t np = frame_points(items[i]);
     if (items[i].stages & EMX_STAGE_FUSE) {
-      const size_t f = fuse_scratch_layout(np, tiles_of(items[i].map->p), nullptr, nullptr);
+      const size_t f = fuse_scratch_layout(np, tiles_of(items[i].map->p), 0, nullptr, nullptr);
       if (tab && base)
-        fuse_scratch_layout(np, tiles_of(items[i].map->p), base + off, &tab->items[i].fs);
+        fuse_scratch_layout(np, tiles_of(items[i].map->p), 0, base + off, &tab->items[i].fs);
       off = align256(off + f);
     }
     if (tab) tab->items[i].ray_base = rays;
@@ -259,7 +262,7 @@ size_t emx_batch_scratch_bound(const emx_batch* b, const emx_params* largest, in
   // Every item's chunk count is at most n_i / kChunk + 1 and its fusion
   // arrays are each padded by under 256 bytes, plus the item's own padding.
   const int64_t recs = max_points + (int64_t)max_items * kChunk;
-  const size_t fuse = fuse_scratch_layout(recs, tiles_of(*largest), nullptr, nullptr) +
+  const size_t fuse = fuse_scratch_layout(recs, tiles_of(*largest), 0, nullptr, nullptr) +
                       (size_t)max_items * 5 * 256;
   return align256(kCounterOffset + kCounterBytes) + fuse +
          clear_scratch_layout(max_points, b->tune.seg, nullptr, nullptr);

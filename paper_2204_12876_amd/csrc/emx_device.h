@@ -74,6 +74,8 @@ struct Consts {
   float nxf, nyf;  // nx, ny as float (exact)
   int nx, ny;
   int32_t tau;     // clear_min_age_ms
+  float var_t;     // time variance per fusion, 0 = off
+  int32_t wall;    // wall/edge rule threshold, 0 = off
 };
 
 // Sensor -> map-local transform, float32.
@@ -87,6 +89,7 @@ struct FuseScratch {
   float* rec_w;         // [B * kChunk] chunk partial of sum 1/sp2
   float* rec_wz;        // [B * kChunk] chunk partial of sum zm/sp2
   uint32_t* dir;        // [B * T]  (start << 16 | count) of a tile's partials in a chunk
+  uint32_t* count;      // [nx * ny] the frame's valid points per cell (wall rule), or null
 };
 
 // Where a clearing setup queues its ray segments.

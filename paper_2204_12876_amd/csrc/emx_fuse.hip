@@ -164,6 +164,11 @@ __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
         const float v0 = it.L.v[cell];
         const float d = e.zm - h0;
         acc = (d * d) <= (it.c.k2 * (v0 + e.sp2));
+        // wall/edge rule: in a crowded cell that holds an estimate, points
+        // below the estimate are ignored (before the gate)
+        if (it.fs.count && e.zm < h0 && it.fs.count[cell] > (uint32_t)it.c.wall &&
+            it.L.valid[cell])
+          acc = false;
       }
       if (it.out_cell) it.out_cell[i] = cell;
       if (it.out_accept) it.out_accept[i] = acc ? 1 : 0;
@@ -457,6 +462,46 @@ __device__ __forceinline__ void tile_body(const Item& it, int t) {
   it.L.v[cell] = v1;
   it.L.t[cell] = it.t_now;
   it.L.valid[cell] = 1;
+  if (it.c.var_t != 0.0f) it.L.mark[cell] = 1;  // updated: no time variance
+}
+
+// ------------------------------------------------------- wall rule: counts
+// The frame's valid in-map points per cell, by integer atomics (the counts do
+// not depend on their order).  The counts are zeroed by the launch before.
+__device__ __forceinline__ void count_body(const Item& it, int64_t chunk) {
+#pragma unroll
+  for (int j = 0; j < kChunk / kNT1; ++j) {
+    const int64_t i = chunk * kChunk + j * kNT1 + threadIdx.x;
+    if (i >= it.n) continue;
+    const PointEval e = eval_point(it.P, it.c, it.x[i], it.y[i], it.z[i]);
+    int ix, iy;
+    if (e.valid && bin_xy(e.xm, e.ym, it.c, ix, iy))
+      atomicAdd(it.fs.count + ((int64_t)iy * it.c.nx + ix), 1u);
+  }
+}
+
+// ------------------------------------------- time variance after a fusion
+// Valid cells that the fusion did not update (not flagged in the mark layer)
+// gain sigma_t^2; the flags are cleared, since clearing expects zero marks.
+constexpr int kNTv = 256;
+
+__device__ __forceinline__ void timevar_body(const Item& it, int64_t unit) {
+  const int64_t i = unit * kNTv + threadIdx.x;
+  if (i >= (int64_t)it.c.nx * it.c.ny) return;
+  if (it.L.mark[i]) {
+    it.L.mark[i] = 0;
+  } else if (it.L.valid[i]) {
+    it.L.v[i] = it.L.v[i] + it.c.var_t;
+  }
+}
+
+__global__ __launch_bounds__(kNT1) void k_fuse_count(Item it) { count_body(it, blockIdx.x); }
+
+__global__ __launch_bounds__(kNTv) void k_time_variance(Item it) { timevar_body(it, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------- launches
@@ -494,7 +539,8 @@ int tiles_x_of(int nx) { return (nx + kTile - 1) >> kTileLog; }
 int tiles_y_of(int ny) { return (ny + kTile - 1) >> kTileLog; }
 bool fuse_needs_key64(int T) { return (int64_t)T * kTileCells > kMaxCells32; }
 
-size_t fuse_scratch_layout(int64_t max_points, int T, char* base, FuseScratch* out) {
+size_t fuse_scratch_layout(int64_t max_points, int T, int64_t count_cells, char* base,
+                           FuseScratch* out) {
   const int64_t B = (max_points + kChunk - 1) / kChunk;
   const size_t nrec = (size_t)B * kChunk;
   size_t off = 0;
@@ -506,29 +552,56 @@ size_t fuse_scratch_layout(int64_t max_points, int T, char* base, FuseScratch* o
   off = align256(off + nrec * sizeof(float));
   const size_t o_dir = off;
   off = align256(off + (size_t)B * (size_t)T * sizeof(uint32_t));
+  const size_t o_cnt = off;
+  off = align256(off + (size_t)count_cells * sizeof(uint32_t));
   if (out && base) {
     out->rec_local = (uint16_t*)(base + o_local);
     out->rec_w = (float*)(base + o_w);
     out->rec_wz = (float*)(base + o_wz);
     out->dir = (uint32_t*)(base + o_dir);
+    out->count = count_cells > 0 ? (uint32_t*)(base + o_cnt) : nullptr;
   }
   return off;
 }
 
 hipError_t launch_fuse(const Item& it, hipStream_t stream) {
-  if (it.n <= 0) return hipSuccess;
-  {
-    TimedLaunch tl("k_fuse_chunk", stream);
-    if (fuse_needs_key64(it.T))
-      hipLaunchKernelGGL(k_fuse_chunk<uint64_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
-    else
-      hipLaunchKernelGGL(k_fuse_chunk<uint32_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
+  hipError_t err = hipSuccess;
+  const int64_t cells = (int64_t)it.c.nx * it.c.ny;
+  if (it.n > 0) {
+    if (it.fs.count) {  // wall/edge rule: the frame's points per cell first
+      {
+        TimedLaunch tl("k_zero_u32", stream);
+        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0,
+                           stream, it.fs.count, cells);
+      }
+      if ((err = hipGetLastError()) != hipSuccess) return err;
+      {
+        TimedLaunch tl("k_fuse_count", stream);
+        hipLaunchKernelGGL(k_fuse_count, dim3(it.B), dim3(kNT1), 0, stream, it);
+      }
+      if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
+    {
+      TimedLaunch tl("k_fuse_chunk", stream);
+      if (fuse_needs_key64(it.T))
+        hipLaunchKernelGGL(k_fuse_chunk<uint64_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
+      else
+        hipLaunchKernelGGL(k_fuse_chunk<uint32_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
+    }
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    {
+      TimedLaunch tl("k_fuse_tile", stream);
+      hipLaunchKernelGGL(k_fuse_tile, dim3(it.T), dim3(kNT2), 0, stream, it);
+    }
+    if ((err = hipGetLastError()) != hipSuccess) return err;
   }
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  TimedLaunch tl("k_fuse_tile", stream);
-  hipLaunchKernelGGL(k_fuse_tile, dim3(it.T), dim3(kNT2), 0, stream, it);
-  return hipGetLastError();
+  if (it.c.var_t != 0.0f) {  // time variance, also after an empty frame
+    TimedLaunch tl("k_time_variance", stream);
+    hipLaunchKernelGGL(k_time_variance, dim3((unsigned)((cells + kNTv - 1) / kNTv)), dim3(kNTv),
+                       0, stream, it);
+    err = hipGetLastError();
+  }
+  return err;
 }
 
 hipError_t launch_fuse_batch(const Batch* d_batch, bool key64, int grid_chunk, int grid_tile,

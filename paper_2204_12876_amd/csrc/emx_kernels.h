@@ -31,7 +31,10 @@ class TimedLaunch {
 int tiles_x_of(int nx);
 int tiles_y_of(int ny);
 bool fuse_needs_key64(int T);
-size_t fuse_scratch_layout(int64_t max_points, int T, char* base, FuseScratch* out);
+// count_cells: cells of the per-cell point counts of the wall/edge rule (0: none).
+size_t fuse_scratch_layout(int64_t max_points, int T, int64_t count_cells, char* base,
+                           FuseScratch* out);
+// Runs the time variance pass even when it.n == 0.
 hipError_t launch_fuse(const Item& it, hipStream_t stream);
 hipError_t launch_fuse_batch(const Batch* d_batch, bool key64, int grid_chunk, int grid_tile,
                              hipStream_t stream);
@@ -60,5 +63,15 @@ hipError_t launch_normals(const Item& it, hipStream_t stream);
 hipError_t launch_trav(const Item& it, hipStream_t stream);
 hipError_t launch_move_batch(const Batch* d_batch, int grid, hipStream_t stream);
 hipError_t launch_cells_batch(const Batch* d_batch, int grid, hipStream_t stream);
+
+// ------------------------------------------------------------------ drift
+struct DriftScratch {
+  void* res;            // the mean (double) and count (int64) of the last call
+  double* part_sum;     // [chunks] float64 partial sums of the errors
+  uint32_t* part_cnt;   // [chunks] contributing points per chunk
+};
+size_t drift_scratch_layout(int64_t max_points, char* base, DriftScratch* out);
+hipError_t launch_drift(const Item& it, float trav_min, const DriftScratch& ds,
+                        double* out_mean, int64_t* out_count, hipStream_t stream);
 
 }  // namespace emx

@@ -351,6 +351,9 @@ class GpuExecutor:
 
     def create_map(self, robot, params, cx, cy, t0):
         from . import ElevationMap
+        if params.get("time_variance", 0.0) or params.get("wall_min_count", 0):
+            # batched launches run the base fusion only
+            raise ValueError("maps with time_variance or wall_min_count are not served in batches")
         self.maps[robot] = ElevationMap(params, cx, cy, t0, device=self.device)
 
     def drop_map(self, robot):
