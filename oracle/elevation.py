@@ -63,6 +63,12 @@ listed with its reason in the design notes):
   * Drift compensation averages z - h over valid in-map points in valid cells
     whose traversability exceeds a threshold, and adds the mean to every valid
     cell's height before fusion.
+  * The upper bound uses the clearing's ray samples.  A sample lowers the
+    bound of its cell if that cell holds no estimate when the call starts;
+    the bound is the running minimum over calls, +inf until a ray passes.
+  * Overlap clearance takes the robot's position and height from the caller
+    and removes valid cells whose centre is within a horizontal radius and
+    whose height differs from the robot's by more than the threshold.
 """
 from __future__ import annotations
 
@@ -75,7 +81,7 @@ import numpy as np
 __all__ = [
     "Params", "MapState", "init_map", "local_pose", "point_decisions", "fuse",
     "compensate_drift", "fuse_sequential", "clear_visibility", "apply_clear", "compute_normals",
-    "traversability", "move_map", "f32_constants",
+    "traversability", "move_map", "f32_constants", "upper_bound", "overlap_clear", "move_layer",
 ]
 
 F32 = np.float32
@@ -357,38 +363,22 @@ def fuse_sequential(p: Params, st: MapState, xs, ys, zs, pose):
     return h.reshape(p.ny, p.nx), v.reshape(p.ny, p.nx)
 
 
-def clear_visibility(p: Params, st: MapState, xs, ys, zs, pose, t_ms: int,
-                     chunk: int = 1 << 16) -> np.ndarray:
-    """Visibility clean-up marks (Sec. II-E, Eq. 3 and Eq. 4), as bool [ny, nx].
+def _ray_samples(p: Params, st: MapState, xs, ys, zs, pose, chunk: int = 1 << 16):
+    """The in-map ray samples of a frame (Sec. II-E), in chunks of rays.
 
-    ``st`` is the snapshot the rays test against.  Its normals come from the
-    last normal computation.
-    A ray runs from the sensor origin o to the point.  Let (dx, dy, dz) be the
-    point minus o, and m = max(|dx|, |dy|).  K = ceil(m / step) and the samples
-    are q_k = o + (k/K)(dx, dy, dz) for k = 1..K-1; if m/step is not below
-    2^24 the ray is not marched.
-    A sample in cell c marks c when all of the following hold:
-      * c is in the map, c is valid, and c is not the end point's own cell;
-      * the age now - t_upd[c] exceeds the minimum age;
-      * the sample passes below h[c] minus the standard deviation
-        (hd = h[c] - q_z, with hd > 0 and hd*hd > v[c]);
-      * the ray is aligned with the cell normal: (r.n)^2 > alpha_n^2 * |r|^2.
-    All of it is evaluated in float32.
+    A ray runs from the sensor origin o to each valid point.  Let (dx, dy, dz)
+    be the point minus o, and m = max(|dx|, |dy|).  K = ceil(m / step) and the
+    samples are q_k = o + (k/K)(dx, dy, dz) for k = 1..K-1; if m/step is not
+    below 2^24 the ray is not marched.  Samples outside the map and samples in
+    the end point's own cell are left out.  All in float32.
+
+    Yields (cs, qz, dx, dy, dz): the samples' cells and heights, and each
+    sample's ray direction.
     """
     c = f32_constants(p)
     d = point_decisions(p, st, xs, ys, zs, pose)
-    t_now = int(t_ms) - st.t0
     o = d["t"]
     idx_valid = np.nonzero(d["valid"])[0]
-    marks = np.zeros(p.nx * p.ny, bool)
-    hf = st.h.reshape(-1)
-    vf = st.v.reshape(-1)
-    tf = st.t_upd.reshape(-1).astype(np.int64)
-    validf = st.valid.reshape(-1)
-    nxf = st.nrm[0].reshape(-1)
-    nyf = st.nrm[1].reshape(-1)
-    nzf = st.nrm[2].reshape(-1)
-    tau = int(p.clear_min_age_ms)
     for c0 in range(0, len(idx_valid), chunk):
         ii = idx_valid[c0:c0 + chunk]
         with np.errstate(all="ignore"):
@@ -413,12 +403,38 @@ def clear_visibility(p: Params, st: MapState, xs, ys, zs, pose, t_ms: int,
             qz = o[2] + tt * dz[rep]
         cs = _bin32(qx, qy, c["inv_r"], p.nx, p.ny)
         keep = (cs >= 0) & (cs != end_cell[rep])
-        cs = cs[keep]
         rk = rep[keep]
-        qz = qz[keep]
+        yield cs[keep], qz[keep], dx[rk], dy[rk], dz[rk]
+
+
+def clear_visibility(p: Params, st: MapState, xs, ys, zs, pose, t_ms: int,
+                     chunk: int = 1 << 16) -> np.ndarray:
+    """Visibility clean-up marks (Sec. II-E, Eq. 3 and Eq. 4), as bool [ny, nx].
+
+    ``st`` is the snapshot the rays test against.  Its normals come from the
+    last normal computation.  The samples are those of ``_ray_samples``.
+    A sample in cell c marks c when all of the following hold:
+      * c is valid (it is in the map and not the end point's own cell);
+      * the age now - t_upd[c] exceeds the minimum age;
+      * the sample passes below h[c] minus the standard deviation
+        (hd = h[c] - q_z, with hd > 0 and hd*hd > v[c]);
+      * the ray is aligned with the cell normal: (r.n)^2 > alpha_n^2 * |r|^2.
+    All of it is evaluated in float32.
+    """
+    c = f32_constants(p)
+    t_now = int(t_ms) - st.t0
+    marks = np.zeros(p.nx * p.ny, bool)
+    hf = st.h.reshape(-1)
+    vf = st.v.reshape(-1)
+    tf = st.t_upd.reshape(-1).astype(np.int64)
+    validf = st.valid.reshape(-1)
+    nxf = st.nrm[0].reshape(-1)
+    nyf = st.nrm[1].reshape(-1)
+    nzf = st.nrm[2].reshape(-1)
+    tau = int(p.clear_min_age_ms)
+    for cs, qz, dxk, dyk, dzk in _ray_samples(p, st, xs, ys, zs, pose, chunk):
         with np.errstate(all="ignore"):
             hd = hf[cs] - qz
-            dxk, dyk, dzk = dx[rk], dy[rk], dz[rk]
             dot = (dxk * nxf[cs] + dyk * nyf[cs]) + dzk * nzf[cs]
             dd = (dxk * dxk + dyk * dyk) + dzk * dzk
             cond = ((validf[cs] != 0) & ((t_now - tf[cs]) > tau) & (hd > F32(0))
@@ -426,6 +442,73 @@ def clear_visibility(p: Params, st: MapState, xs, ys, zs, pose, t_ms: int,
                     & ((dot * dot) > (c["an2"] * dd)))
         marks[cs[cond]] = True
     return marks.reshape(p.ny, p.nx)
+
+
+def upper_bound(p: Params, st: MapState, ub: np.ndarray, xs, ys, zs, pose,
+                chunk: int = 1 << 16) -> np.ndarray:
+    """Height upper bound layer (Sec. II-H), float32 [ny, nx]; +inf = no bound.
+
+    The ground under a ray cannot lie above the ray, or it would have been
+    seen.  So every ray sample (those of ``_ray_samples``, the clearing's own)
+    in a cell without an estimate (invalid in the snapshot ``st``) lowers that
+    cell's bound to the sample height: the new bound is the minimum of the old
+    one and the heights of all such samples.  Cells with an estimate keep
+    their bound.
+    """
+    out = np.asarray(ub, F32).reshape(-1).copy()
+    validf = st.valid.reshape(-1)
+    for cs, qz, _, _, _ in _ray_samples(p, st, xs, ys, zs, pose, chunk):
+        sel = validf[cs] == 0
+        np.minimum.at(out, cs[sel], qz[sel])
+    return out.reshape(p.ny, p.nx)
+
+
+def overlap_clear(p: Params, st: MapState, robot_xyz, radius: float,
+                  threshold: float) -> np.ndarray:
+    """Overlap clearance marks (Sec. II-F), bool [ny, nx].
+
+    A valid cell is removed when its centre lies within ``radius`` of the
+    robot in the horizontal plane and its height differs from the robot's
+    height by more than ``threshold``.  In float32, in map-local coordinates
+    (the robot position is moved into them in float64, like the pose):
+      * dx = (ix + 0.5) * r32 - rx,  dy = (iy + 0.5) * r32 - ry;
+      * near iff dx*dx + dy*dy <= float32(radius^2);
+      * far in height iff |h - rz| > threshold.
+    The removed cells go back to the prior as in ``apply_clear``.
+    """
+    ox = F64(st.cgx - p.nx // 2) * F64(p.resolution)
+    oy = F64(st.cgy - p.ny // 2) * F64(p.resolution)
+    rx = F32(F64(robot_xyz[0]) - ox)
+    ry = F32(F64(robot_xyz[1]) - oy)
+    rz = F32(robot_xyz[2])
+    r32 = F32(p.resolution)
+    rad = F64(F32(radius))
+    rad2 = F32(rad * rad)
+    thr = F32(threshold)
+    ix = np.arange(p.nx, dtype=F32)
+    iy = np.arange(p.ny, dtype=F32)
+    with np.errstate(all="ignore"):
+        dx = (ix + F32(0.5)) * r32 - rx
+        dy = (iy + F32(0.5)) * r32 - ry
+        near = ((dx * dx)[None, :] + (dy * dy)[:, None]) <= rad2
+        far = np.abs(st.h - rz) > thr
+    return (st.valid != 0) & near & far
+
+
+def move_layer(p: Params, st: MapState, layer: np.ndarray, cx: float, cy: float,
+               fill) -> np.ndarray:
+    """One extra layer through the robot-centric move of ``move_map``: cells
+    that stay keep their value, cells that enter take ``fill``."""
+    ngx = int(math.floor(cx / p.resolution))
+    ngy = int(math.floor(cy / p.resolution))
+    sx, sy = ngx - st.cgx, ngy - st.cgy
+    out = np.full_like(layer, fill)
+    ny, nx = p.ny, p.nx
+    x0, x1 = max(0, -sx), min(nx, nx - sx)
+    y0, y1 = max(0, -sy), min(ny, ny - sy)
+    if x0 < x1 and y0 < y1:
+        out[y0:y1, x0:x1] = layer[y0 + sy:y1 + sy, x0 + sx:x1 + sx]
+    return out
 
 
 def apply_clear(p: Params, st: MapState, marks: np.ndarray) -> MapState:
