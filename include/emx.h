@@ -81,6 +81,8 @@ typedef struct {
   int32_t wall_min_count;    /* wall/edge rule (Sec. II-C): in a valid cell that     */
                              /* receives more than this many of a frame's points,    */
                              /* points below its height are ignored; >= 0, 0 off     */
+  int32_t upper_bound;       /* 1: keep the upper bound layer (Sec. II-H), updated   */
+                             /* by emx_clear_visibility; 0: no such layer            */
 } emx_params;
 
 /* One point cloud in the sensor frame, structure of arrays. */
@@ -102,6 +104,9 @@ typedef struct {
 #define EMX_LAYER_NORMAL_Z 5   /* [float]                                          */
 #define EMX_LAYER_TRAV 6       /* [float]   traversability, NaN where undefined    */
 #define EMX_LAYER_VALID 7      /* [uint8]   1 once a point has been fused          */
+#define EMX_LAYER_UPPER 8      /* [float]   upper bound of the ground height, +inf  */
+                               /* where no ray has passed; only with upper_bound=1, */
+                               /* and not part of the export format                 */
 #define EMX_NUM_LAYERS 8
 
 /* Library version string (static storage). */
@@ -217,6 +222,10 @@ emx_status emx_fuse_points(emx_map* map, const emx_frame* frame, void* d_scratch
  * Rays test the state as it was when the call started.  Afterwards each
  * marked cell returns to (init_height, init_variance) and becomes invalid.
  * Normals and traversability are left for the next per-cell pass.
+ * Upper bound (Sec. II-H, maps with upper_bound = 1): the same samples, in
+ * cells that are invalid when the call starts, lower the cell's bound to q.z:
+ * upper[c] = min(upper[c], q.z over those samples).  A minimum has no order,
+ * so the layer is deterministic.  Cells enter with +inf (init, move).
  *   d_scratch:     >= emx_scratch_bytes(params, frame->n) bytes, 256-aligned;
  *                  may be NULL when n = 0.
  *   d_out_cleared: optional uint8[nx*ny], set to 1 for removed cells, 0 else. */
@@ -242,6 +251,51 @@ emx_status emx_compute_normals(emx_map* map, void* stream);
  *   NaN where the normal is NaN (border or any of the 9 cells invalid). */
 emx_status emx_traversability(emx_map* map, const float* d_weights, void* stream);
 
+/* Overlap clearance (Sec. II-F): removes old estimates of another floor
+ * near the robot.  In float32, in map-local metres (rx, ry are moved into
+ * them in float64, as the pose is):
+ *   dx = ((float)ix + 0.5f) * float32(r) - rx32,  dy likewise with iy, ry32;
+ *   a cell is removed iff valid, dx*dx + dy*dy <= float32(radius^2) and
+ *   |h - float32(rz)| > threshold.
+ * Removed cells return to (init_height, init_variance) and become invalid, as
+ * in emx_clear_visibility.
+ *   rx, ry, rz:    robot position in the world; rz is the robot's height.
+ *   radius:        horizontal radius in metres, >= 0.
+ *   threshold:     height difference in metres, >= 0.
+ *   d_out_cleared: optional uint8[nx*ny], 1 for removed cells, 0 else. */
+emx_status emx_overlap_clear(emx_map* map, double rx, double ry, double rz, float radius,
+                             float threshold, uint8_t* d_out_cleared, void* stream);
+
+/* Minimum-filter inpainting (Sec. II-I).  The invalid cells form regions
+ * connected through their four edge neighbours.  Each region takes the
+ * smallest height among the valid cells that share an edge with it (the
+ * minimum along its occlusion border); a region without such a cell is NaN.
+ * Valid cells keep their height.  The map is not changed.
+ *   d_out:     device float32[nx*ny], row-major like the layers.
+ *   d_scratch: >= emx_inpaint_scratch_bytes(params) bytes, 256-aligned. */
+size_t emx_inpaint_scratch_bytes(const emx_params* params);
+emx_status emx_inpaint_min(emx_map* map, float* d_out, void* d_scratch, size_t scratch_bytes,
+                           void* stream);
+
+/* Smoothing filters on a float32 grid (Sec. II-I: Gaussian, box blur,
+ * median).  Row-major [ny][nx] in and out; d_out must not overlap d_in.
+ * The window is ksize x ksize (ksize odd); border cells read the grid
+ * mirrored about the edge cell without repeating it (index -1 reads 1), so
+ * nx and ny must exceed ksize/2.
+ *   EMX_SMOOTH_BOX:      mean of the window; ksize 1..31.
+ *   EMX_SMOOTH_GAUSSIAN: separable weights w_i = exp(-i*i / (2 sigma^2)),
+ *                        i = -ksize/2..ksize/2, normalised to sum 1 (formed in
+ *                        double, rounded to float); along x, then along y;
+ *                        ksize 1..31, sigma > 0.
+ *   EMX_SMOOTH_MEDIAN:   the middle of the window's values; ksize 3 or 5.
+ * A NaN in the window makes the output NaN (box and Gaussian through the
+ * arithmetic, median by rule).  sigma is ignored except for the Gaussian. */
+#define EMX_SMOOTH_BOX 0
+#define EMX_SMOOTH_GAUSSIAN 1
+#define EMX_SMOOTH_MEDIAN 2
+emx_status emx_smooth(const float* d_in, float* d_out, int32_t nx, int32_t ny, int32_t kind,
+                      int32_t ksize, float sigma, void* stream);
+
 /* Device pointer of a layer of the current buffer set. */
 emx_status emx_layer(emx_map* map, int32_t layer, void** d_ptr);
 
@@ -264,8 +318,8 @@ emx_status emx_import_state(emx_map* map, const void* d_src, void* stream);
  *     arithmetic, and every float32 sum has a fixed order.
  *   - The tuning selects only launch geometry (persistent grid sizes) and the
  *     clearing segment length.  It never changes results.
- *   - Maps with time_variance or wall_min_count set are refused (EMX_EINVAL):
- *     run those through the plain calls. */
+ *   - Maps with time_variance, wall_min_count or upper_bound set are refused
+ *     (EMX_EINVAL): run those through the plain calls. */
 #define EMX_STAGE_MOVE 1u
 #define EMX_STAGE_FUSE 2u
 #define EMX_STAGE_CLEAR 4u

@@ -17,7 +17,7 @@ from . import _emx
 from ._emx import EmxError, make_params  # noqa: F401
 
 __all__ = ["ElevationMap", "PipelineBatch", "BatchEntry", "EmxError", "make_params", "lib_path",
-           "aligned_empty"]
+           "aligned_empty", "smooth"]
 
 lib_path = _emx.LIB_PATH
 
@@ -129,6 +129,36 @@ class ElevationMap:
         _emx.clear_visibility(self.handle, f, s.data_ptr(), s.numel(),
                               out_cleared.data_ptr() if out_cleared is not None else 0,
                               _stream(self.device))
+
+    def overlap_clear(self, robot_xyz, radius: float, threshold: float,
+                      out_cleared: torch.Tensor = None):
+        """Remove valid cells within ``radius`` of the robot (horizontally) whose
+        height differs from the robot's by more than ``threshold`` (Sec. II-F)."""
+        if out_cleared is not None and (out_cleared.dtype != torch.uint8
+                                        or out_cleared.numel() < self.nx * self.ny):
+            raise ValueError("out_cleared must be uint8 with nx*ny elements")
+        rx, ry, rz = (float(v) for v in robot_xyz)
+        _emx.overlap_clear(self.handle, rx, ry, rz, radius, threshold,
+                           out_cleared.data_ptr() if out_cleared is not None else 0,
+                           _stream(self.device))
+
+    def inpaint_min(self, out: torch.Tensor = None) -> torch.Tensor:
+        """Minimum-filter inpainting (Sec. II-I) of the height layer into a new
+        [ny, nx] float32 tensor (or ``out``); the map is not changed."""
+        if out is None:
+            out = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        elif (out.dtype != torch.float32 or out.numel() != self.nx * self.ny
+              or not out.is_contiguous() or out.device != self.device):
+            raise ValueError("out must be a contiguous float32 [ny, nx] tensor on the device")
+        need = _emx.inpaint_scratch_bytes(self.p)
+        s = aligned_empty(need, self.device)
+        _emx.inpaint_min(self.handle, out.data_ptr(), s.data_ptr(), need, _stream(self.device))
+        return out
+
+    def upper_bound(self) -> torch.Tensor:
+        """The upper bound layer (Sec. II-H), a [ny, nx] float32 view; the map
+        must have been created with upper_bound=1."""
+        return self.layer(_emx.LAYER_UPPER)
 
     def compute_normals(self):
         _emx.compute_normals(self.handle, _stream(self.device))
@@ -275,6 +305,28 @@ class PipelineBatch:
     def run(self, entries):
         arr = _emx.make_batch_items([e.item() for e in entries])
         self.run_items(arr, len(entries), _stream(self.device))
+
+
+_SMOOTH_KINDS = {"box": _emx.SMOOTH_BOX, "gaussian": _emx.SMOOTH_GAUSSIAN,
+                 "median": _emx.SMOOTH_MEDIAN}
+
+
+def smooth(x: torch.Tensor, kind: str, ksize: int, sigma: float = 0.0,
+           out: torch.Tensor = None) -> torch.Tensor:
+    """Box, Gaussian or median smoothing of a [ny, nx] float32 grid on the GPU
+    (Sec. II-I), with the border mirrored about the edge cells."""
+    if kind not in _SMOOTH_KINDS:
+        raise ValueError(f"kind must be one of {sorted(_SMOOTH_KINDS)}")
+    if x.dim() != 2 or x.dtype != torch.float32 or not x.is_contiguous() or not x.is_cuda:
+        raise ValueError("x must be a contiguous float32 [ny, nx] tensor on the GPU")
+    if out is None:
+        out = torch.empty_like(x)
+    elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous():
+        raise ValueError("out must match x")
+    ny, nx = x.shape
+    _emx.smooth(x.data_ptr(), out.data_ptr(), nx, ny, _SMOOTH_KINDS[kind], ksize, sigma,
+                _stream(x.device))
+    return out
 
 
 def pack_state(h, v, t_upd, valid, nrm, trav) -> np.ndarray:

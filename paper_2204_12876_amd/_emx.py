@@ -25,7 +25,7 @@ EMX_ESTATE = -5
 
 LAYER_HEIGHT, LAYER_VARIANCE, LAYER_TIME = 0, 1, 2
 LAYER_NORMAL_X, LAYER_NORMAL_Y, LAYER_NORMAL_Z = 3, 4, 5
-LAYER_TRAV, LAYER_VALID = 6, 7
+LAYER_TRAV, LAYER_VALID, LAYER_UPPER = 6, 7, 8
 
 
 class EmxError(RuntimeError):
@@ -39,7 +39,8 @@ class Params(Structure):
                 ("init_height", c_float), ("init_variance", c_float), ("noise_alpha", c_float),
                 ("gate_k", c_float), ("min_range", c_float), ("ray_step", c_float),
                 ("clear_normal_alpha", c_float), ("clear_min_age_ms", c_int32),
-                ("time_variance", c_float), ("wall_min_count", c_int32)]
+                ("time_variance", c_float), ("wall_min_count", c_int32),
+                ("upper_bound", c_int32)]
 
 
 class Frame(Structure):
@@ -76,6 +77,12 @@ _SIGS = {
     "emx_drift_scratch_bytes": (c_size_t, [c_int64]),
     "emx_compensate_drift": (c_int32, [c_void_p, POINTER(Frame), c_float, c_void_p, c_size_t,
                                        c_void_p, c_void_p, c_void_p]),
+    "emx_overlap_clear": (c_int32, [c_void_p, c_double, c_double, c_double, c_float, c_float,
+                                    c_void_p, c_void_p]),
+    "emx_inpaint_scratch_bytes": (c_size_t, [POINTER(Params)]),
+    "emx_inpaint_min": (c_int32, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "emx_smooth": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_float,
+                             c_void_p]),
     "emx_compute_normals": (c_int32, [c_void_p, c_void_p]),
     "emx_traversability": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "emx_layer": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
@@ -144,6 +151,7 @@ def make_params(d: dict) -> Params:
     p.clear_min_age_ms = int(d.get("clear_min_age_ms", 500))
     p.time_variance = float(d.get("time_variance", 0.0))
     p.wall_min_count = int(d.get("wall_min_count", 0))
+    p.upper_bound = int(d.get("upper_bound", 0))
     return p
 
 
@@ -196,6 +204,31 @@ def fuse_points(h: int, f: Frame, d_scratch: int, nbytes: int, d_out_cell: int,
     check(lib().emx_fuse_points(c_void_p(h), byref(f), c_void_p(d_scratch), nbytes,
                                 c_void_p(d_out_cell or None), c_void_p(d_out_accept or None),
                                 c_void_p(stream)))
+
+
+SMOOTH_BOX, SMOOTH_GAUSSIAN, SMOOTH_MEDIAN = 0, 1, 2
+
+
+def overlap_clear(h: int, rx: float, ry: float, rz: float, radius: float, threshold: float,
+                  d_out_cleared: int, stream: int):
+    check(lib().emx_overlap_clear(c_void_p(h), float(rx), float(ry), float(rz), float(radius),
+                                  float(threshold), c_void_p(d_out_cleared or None),
+                                  c_void_p(stream)))
+
+
+def inpaint_scratch_bytes(p: Params) -> int:
+    return lib().emx_inpaint_scratch_bytes(byref(p))
+
+
+def inpaint_min(h: int, d_out: int, d_scratch: int, nbytes: int, stream: int):
+    check(lib().emx_inpaint_min(c_void_p(h), c_void_p(d_out), c_void_p(d_scratch or None),
+                                nbytes, c_void_p(stream)))
+
+
+def smooth(d_in: int, d_out: int, nx: int, ny: int, kind: int, ksize: int, sigma: float,
+           stream: int):
+    check(lib().emx_smooth(c_void_p(d_in), c_void_p(d_out), int(nx), int(ny), int(kind),
+                           int(ksize), float(sigma), c_void_p(stream)))
 
 
 def drift_scratch_bytes(max_points: int) -> int:

@@ -12,7 +12,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libemx.so")
 
 SOURCES = ["emx_api.hip", "emx_batch.hip", "emx_timing.hip", "emx_fuse.hip", "emx_clear.hip",
-           "emx_cells.hip", "emx_drift.hip"]
+           "emx_cells.hip", "emx_drift.hip",
+           "emx_filters.hip"]
 
 # Decisions (binning, gate, ray samples) must follow the documented float32
 # operation order: no contraction into FMA, correctly rounded division/sqrt,

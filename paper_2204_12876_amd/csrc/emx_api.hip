@@ -60,6 +60,8 @@ emx_status check_params(const emx_params* p) {
   if (!isfinite(p->time_variance) || p->time_variance < 0.0f)
     return fail(EMX_EINVAL, "time_variance must be >= 0");
   if (p->wall_min_count < 0) return fail(EMX_EINVAL, "wall_min_count must be >= 0");
+  if (p->upper_bound != 0 && p->upper_bound != 1)
+    return fail(EMX_EINVAL, "upper_bound must be 0 or 1");
   return EMX_OK;
 }
 
@@ -84,8 +86,8 @@ Consts make_consts(const emx_params& p) {
   return c;
 }
 
-// One buffer set: seven 4-byte layers, two byte layers, then the clearing
-// block maxima; each 256-aligned.
+// One buffer set: seven 4-byte layers, two byte layers, the clearing block
+// maxima, then the upper bound layer if the map keeps one; each 256-aligned.
 size_t set_layout(const emx_params& p, char* base, Layers* L) {
   const size_t C = (size_t)p.nx * (size_t)p.ny;
   const size_t l4 = align256(C * 4);
@@ -103,8 +105,9 @@ size_t set_layout(const emx_params& p, char* base, Layers* L) {
     L->valid = (uint8_t*)(base + 7 * l4);
     L->mark = (uint8_t*)(base + 7 * l4 + l1);
     L->cmax = (float*)(base + 7 * l4 + 2 * l1);
+    L->ub = p.upper_bound ? (float*)(base + 7 * l4 + 2 * l1 + lb) : nullptr;
   }
-  return 7 * l4 + 2 * l1 + lb;
+  return 7 * l4 + 2 * l1 + lb + (p.upper_bound ? l4 : 0);
 }
 
 size_t clr_bytes(const emx_params& p) { return align256((size_t)p.nx * (size_t)p.ny * 16); }
@@ -374,6 +377,80 @@ emx_status emx_compensate_drift(emx_map* m, const emx_frame* f, float trav_min, 
   return EMX_OK;
 }
 
+emx_status emx_overlap_clear(emx_map* m, double rx, double ry, double rz, float radius,
+                             float threshold, uint8_t* d_out_cleared, void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if (!isfinite(rx) || !isfinite(ry) || !isfinite(rz))
+    return fail(EMX_EINVAL, "robot position must be finite");
+  if (!isfinite(radius) || radius < 0.0f) return fail(EMX_EINVAL, "radius must be >= 0");
+  if (!isfinite(threshold) || threshold < 0.0f)
+    return fail(EMX_EINVAL, "threshold must be >= 0");
+  const double ox = (double)(m->cgx - m->p.nx / 2) * m->p.resolution;
+  const double oy = (double)(m->cgy - m->p.ny / 2) * m->p.resolution;
+  OverlapArgs a;
+  a.c = m->c;
+  a.L = m->sets[m->cur];
+  a.r32 = (float)m->p.resolution;
+  a.rx = (float)(rx - ox);
+  a.ry = (float)(ry - oy);
+  a.rz = (float)rz;
+  a.rad2 = (float)((double)radius * (double)radius);
+  a.thr = threshold;
+  a.out = d_out_cleared;
+  if (!isfinite(a.rx) || !isfinite(a.ry) || !isfinite(a.rz))
+    return fail(EMX_EINVAL, "map-local robot position overflows float32");
+  hipError_t e = launch_overlap(a, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "overlap_clear");
+  return EMX_OK;
+}
+
+size_t emx_inpaint_scratch_bytes(const emx_params* params) {
+  if (!params || check_params(params) != EMX_OK) return 0;
+  return inpaint_scratch_bytes(params->nx, params->ny);
+}
+
+emx_status emx_inpaint_min(emx_map* m, float* d_out, void* d_scratch, size_t scratch_bytes,
+                           void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if (!d_out) return fail(EMX_EINVAL, "d_out is NULL");
+  if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
+  if (((uintptr_t)d_scratch & 255u) != 0)
+    return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
+  const size_t need = inpaint_scratch_bytes(m->p.nx, m->p.ny);
+  if (scratch_bytes < need)
+    return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
+  hipError_t e =
+      launch_inpaint(m->c, m->sets[m->cur], d_out, (char*)d_scratch, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "inpaint_min");
+  return EMX_OK;
+}
+
+emx_status emx_smooth(const float* d_in, float* d_out, int32_t nx, int32_t ny, int32_t kind,
+                      int32_t ksize, float sigma, void* stream) {
+  if (!d_in || !d_out) return fail(EMX_EINVAL, "d_in or d_out is NULL");
+  if (nx < 1 || ny < 1 || (int64_t)nx * ny > 2147483647LL)
+    return fail(EMX_EINVAL, "grid %d x %d out of range", nx, ny);
+  if (kind < EMX_SMOOTH_BOX || kind > EMX_SMOOTH_MEDIAN)
+    return fail(EMX_EINVAL, "unknown filter kind %d", kind);
+  if (ksize < 1 || (ksize & 1) == 0 || ksize > 31)
+    return fail(EMX_EINVAL, "ksize must be odd, 1..31 (got %d)", ksize);
+  if (kind == EMX_SMOOTH_MEDIAN && ksize != 3 && ksize != 5)
+    return fail(EMX_EINVAL, "the median takes ksize 3 or 5 (got %d)", ksize);
+  if (kind == EMX_SMOOTH_GAUSSIAN && !(isfinite(sigma) && sigma > 0.0f))
+    return fail(EMX_EINVAL, "sigma must be > 0");
+  if (nx <= ksize / 2 || ny <= ksize / 2)
+    return fail(EMX_EINVAL, "grid %d x %d too small for ksize %d", nx, ny, ksize);
+  const size_t bytes = (size_t)nx * (size_t)ny * sizeof(float);
+  const char* a = (const char*)d_in;
+  const char* b = (const char*)d_out;
+  if (a < b + bytes && b < a + bytes) return fail(EMX_EINVAL, "d_out overlaps d_in");
+  hipError_t e = launch_smooth(d_in, d_out, nx, ny, kind, ksize, sigma, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "smooth");
+  return EMX_OK;
+}
+
 emx_status emx_compute_normals(emx_map* m, void* stream) {
   emx_status s = check_map(m);
   if (s != EMX_OK) return s;
@@ -413,6 +490,10 @@ emx_status emx_layer(emx_map* m, int32_t layer, void** d_ptr) {
     case EMX_LAYER_NORMAL_Z: p = L.nz; break;
     case EMX_LAYER_TRAV: p = L.trav; break;
     case EMX_LAYER_VALID: p = L.valid; break;
+    case EMX_LAYER_UPPER:
+      if (!L.ub) return fail(EMX_EINVAL, "the map keeps no upper bound layer");
+      p = L.ub;
+      break;
     default: return fail(EMX_EINVAL, "unknown layer %d", layer);
   }
   *d_ptr = p;

@@ -107,9 +107,11 @@ emx_status check_items(const emx_batch_item* items, int32_t n) {
     if (s != EMX_OK) return s;
     if (items[i].stages & ~(uint32_t)EMX_STAGE_ALL)
       return fail(EMX_EINVAL, "item %d: unknown stage bits", i);
-    if (items[i].map->p.time_variance != 0.0f || items[i].map->p.wall_min_count != 0)
+    if (items[i].map->p.time_variance != 0.0f || items[i].map->p.wall_min_count != 0 ||
+        items[i].map->p.upper_bound != 0)
       return fail(EMX_EINVAL,
-                  "item %d: maps with time_variance or wall_min_count use the plain calls", i);
+                  "item %d: maps with time_variance, wall_min_count or upper_bound use the "
+                  "plain calls", i);
     if ((items[i].stages & (EMX_STAGE_FUSE | EMX_STAGE_CLEAR)) &&
         (s = check_frame(&items[i].frame)) != EMX_OK)
       return s;

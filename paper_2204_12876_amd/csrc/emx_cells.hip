@@ -37,6 +37,7 @@ __global__ __launch_bounds__(kNTf) void k_fill_prior(FillArgs a) {
   a.L.trav[i] = qnan;
   a.L.valid[i] = 0;
   a.L.mark[i] = 0;
+  if (a.L.ub) a.L.ub[i] = INFINITY;
 }
 
 // ------------------------------------------------------------------------ move
@@ -64,6 +65,7 @@ __device__ __forceinline__ void move_body(const Item& it, int64_t unit) {
     dst.nz[o] = src.nz[s];
     dst.trav[o] = src.trav[s];
     dst.valid[o] = src.valid[s];
+    if (dst.ub) dst.ub[o] = src.ub[s];
   } else {
     const float qnan = __builtin_nanf("");
     dst.h[o] = it.c.h_init;
@@ -74,8 +76,30 @@ __device__ __forceinline__ void move_body(const Item& it, int64_t unit) {
     dst.nz[o] = qnan;
     dst.trav[o] = qnan;
     dst.valid[o] = 0;
+    if (dst.ub) dst.ub[o] = INFINITY;
   }
   dst.mark[o] = 0;
+}
+
+// ------------------------------------------------------------ overlap clearance
+// Valid cells within a horizontal radius of the robot whose height differs
+// from the robot's by more than the threshold return to the prior.
+__global__ __launch_bounds__(kNTf) void k_overlap(OverlapArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * kNTf + threadIdx.x;
+  const int64_t C = (int64_t)a.c.nx * a.c.ny;
+  if (i >= C) return;
+  const int iy = (int)(i / a.c.nx);
+  const int ix = (int)(i - (int64_t)iy * a.c.nx);
+  const float dx = ((float)ix + 0.5f) * a.r32 - a.rx;
+  const float dy = ((float)iy + 0.5f) * a.r32 - a.ry;
+  const bool hit = a.L.valid[i] && ((dx * dx + dy * dy) <= a.rad2) &&
+                   (fabsf(a.L.h[i] - a.rz) > a.thr);
+  if (hit) {
+    a.L.h[i] = a.c.h_init;
+    a.L.v[i] = a.c.v_init;
+    a.L.valid[i] = 0;
+  }
+  if (a.out) a.out[i] = hit ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- stencil tile
@@ -240,6 +264,13 @@ hipError_t launch_fill_prior(const Consts& c, const Layers& L, uint32_t* ctl, in
   TimedLaunch tl("k_fill_prior", stream);
   hipLaunchKernelGGL(k_fill_prior, dim3((unsigned)((n + kNTf - 1) / kNTf)), dim3(kNTf), 0, stream,
                      a);
+  return hipGetLastError();
+}
+
+hipError_t launch_overlap(const OverlapArgs& a, hipStream_t stream) {
+  const int64_t C = (int64_t)a.c.nx * a.c.ny;
+  TimedLaunch tl("k_overlap", stream);
+  hipLaunchKernelGGL(k_overlap, dim3((unsigned)((C + kNTf - 1) / kNTf)), dim3(kNTf), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -34,6 +34,12 @@
 //     call started.
 // apply: resets marked cells to the prior, reports and clears the marks, and
 // rewinds the queue counters for the next call.
+//
+// Upper bound layer (Sec. II-H), on maps that keep one: a sample in a cell
+// without an estimate lowers the cell's bound to the sample height, by an
+// integer atomic minimum (order-free, so deterministic).  Such cells count in
+// the block maximum with their current bound, so pruning stays exact: a
+// sample at or above it can neither remove a cell nor lower a bound.
 #include "emx_kernels.h"
 
 namespace emx {
@@ -129,6 +135,15 @@ __device__ __forceinline__ void axis_range(const Ray& r, int K, float inv_r, flo
   hi = first_true(1, K - 1, crossing_guess(o, d, inc ? wlim : 0.0f, K), notQ) - 1;
 }
 
+// Lowers *a to v if v is smaller (v not NaN), as an integer atomic on the
+// float's bits: non-negative floats order like their bits as signed
+// integers, negative ones inversely to their bits as unsigned integers, and
+// every negative float's bits exceed every non-negative one's.
+__device__ __forceinline__ void atomic_min_f32(float* a, float v) {
+  if (!signbit(v)) atomicMin(reinterpret_cast<int*>(a), __float_as_int(v));
+  else atomicMax(reinterpret_cast<unsigned int*>(a), __float_as_uint(v));
+}
+
 // A cell can be removed only if it is valid, older than the minimum age and
 // has a normal.
 __device__ __forceinline__ bool clearable(const Item& it, int64_t c) {
@@ -148,7 +163,11 @@ __device__ __forceinline__ void test_cell(const Item& it, const Ray& r, int c, f
   const float nyc = it.L.ny[c];
   const float nzc = it.L.nz[c];
   const float hd = hc - qz;
-  if (!vc || !(((int64_t)it.t_now - (int64_t)tc) > (int64_t)it.c.tau) || isnan(nzc)) return;
+  if (!vc) {  // no estimate: the sample bounds the ground from above
+    if (it.L.ub) atomic_min_f32(it.L.ub + c, qz);
+    return;
+  }
+  if (!(((int64_t)it.t_now - (int64_t)tc) > (int64_t)it.c.tau) || isnan(nzc)) return;
   if (!(hd > 0.0f) || !((hd * hd) > varc)) return;
   const float dot = (r.dx * nxc + r.dy * nyc) + r.dz * nzc;
   if ((dot * dot) > an2dd) it.L.mark[c] = 1;
@@ -157,10 +176,16 @@ __device__ __forceinline__ void test_cell(const Item& it, const Ray& r, int c, f
 // The same test from the cell's clearing record, written by the setup: one
 // 16-byte load instead of seven, and the normal's z only when the height test
 // passes.  A cell no ray may clear holds -inf, which fails hd > 0 for every
-// finite sample height, so the decision is the same.
+// finite sample height, so the decision is the same.  On maps with an upper
+// bound layer, a cell without an estimate holds NaN in place of the height
+// (no other record does), which sends the sample to its bound.
 __device__ __forceinline__ void test_cell_rec(const Item& it, const Ray& r, int c, float qz,
                                               float an2dd) {
   const float4 k = it.L.clr[c];
+  if (isnan(k.x)) {
+    atomic_min_f32(it.L.ub + c, qz);
+    return;
+  }
   const float hd = k.x - qz;
   if (!(hd > 0.0f) || !((hd * hd) > k.y)) return;
   const float dot = (r.dx * k.z + r.dy * k.w) + r.dz * it.L.nz[c];
@@ -235,6 +260,9 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
       ok[j] = inside[j] && clearable(it, c[j]);
       h[j] = inside[j] ? it.L.h[c[j]] : 0.0f;
       v[j] = ok[j] ? h[j] : -INFINITY;
+      // with an upper bound layer, a sample below the bound of a cell without
+      // an estimate lowers it: such cells take part in the maximum too
+      if (it.L.ub && inside[j] && !it.L.valid[c[j]]) v[j] = it.L.ub[c[j]];
     }
 #pragma unroll
     for (int j = 0; j < kMaxBlocksPerWave; ++j) {
@@ -244,9 +272,12 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
       if (lane == 0 && b0 + j < it.nb) it.L.cmax[b0 + j] = v[j];
       // the march reads records only in blocks with a removable cell, where
       // some sample may pass below the block maximum
-      if (v[j] > -INFINITY && inside[j])
-        it.L.clr[c[j]] = make_float4(ok[j] ? h[j] : -INFINITY, it.L.v[c[j]], it.L.nx[c[j]],
-                                     it.L.ny[c[j]]);
+      if (v[j] > -INFINITY && inside[j]) {
+        // a NaN height can never be cleared (hd > 0 fails), so -inf serves
+        const bool bound = it.L.ub && !it.L.valid[c[j]];
+        const float hx = bound ? __builtin_nanf("") : (ok[j] && !isnan(h[j]) ? h[j] : -INFINITY);
+        it.L.clr[c[j]] = make_float4(hx, it.L.v[c[j]], it.L.nx[c[j]], it.L.ny[c[j]]);
+      }
     }
     return;
   }

@@ -43,6 +43,7 @@ struct Layers {
   uint8_t* valid;
   uint8_t* mark;  // clearing marks; all zero between calls
   float* cmax;    // per block: max height over cells a ray may clear (transient)
+  float* ub;      // upper bound of the ground height (+inf: none), or null
   float4* clr;    // per cell {h, or -inf if a ray may not clear it, v, nx, ny}
                   // (transient; one array per map, shared by both sets)
 };

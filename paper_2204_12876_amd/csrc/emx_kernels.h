@@ -59,10 +59,31 @@ int64_t cells_units(int nx, int ny);
 hipError_t launch_fill_prior(const Consts& c, const Layers& L, uint32_t* ctl, int nctl,
                              hipStream_t stream);
 hipError_t launch_move(const Item& it, hipStream_t stream);
+
+// Overlap clearance on one map's current layers (map-local float32 geometry).
+struct OverlapArgs {
+  Consts c;
+  Layers L;
+  float r32;       // resolution
+  float rx, ry;    // robot, map-local
+  float rz;        // robot height
+  float rad2;      // radius^2
+  float thr;       // height threshold
+  uint8_t* out;    // optional removed-cell flags
+};
+hipError_t launch_overlap(const OverlapArgs& a, hipStream_t stream);
 hipError_t launch_normals(const Item& it, hipStream_t stream);
 hipError_t launch_trav(const Item& it, hipStream_t stream);
 hipError_t launch_move_batch(const Batch* d_batch, int grid, hipStream_t stream);
 hipError_t launch_cells_batch(const Batch* d_batch, int grid, hipStream_t stream);
+
+// ---------------------------------------------------------------- filters
+size_t inpaint_scratch_bytes(int nx, int ny);
+hipError_t launch_inpaint(const Consts& c, const Layers& L, float* out, char* scratch,
+                          hipStream_t stream);
+// kind: 0 box, 1 Gaussian, 2 median; arguments validated by the caller.
+hipError_t launch_smooth(const float* in, float* out, int nx, int ny, int kind, int ksize,
+                         float sigma, hipStream_t stream);
 
 // ------------------------------------------------------------------ drift
 struct DriftScratch {

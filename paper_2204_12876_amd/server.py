@@ -351,9 +351,11 @@ class GpuExecutor:
 
     def create_map(self, robot, params, cx, cy, t0):
         from . import ElevationMap
-        if params.get("time_variance", 0.0) or params.get("wall_min_count", 0):
-            # batched launches run the base fusion only
-            raise ValueError("maps with time_variance or wall_min_count are not served in batches")
+        if (params.get("time_variance", 0.0) or params.get("wall_min_count", 0)
+                or params.get("upper_bound", 0)):
+            # batched launches run the base path only
+            raise ValueError("maps with time_variance, wall_min_count or upper_bound are not "
+                             "served in batches")
         self.maps[robot] = ElevationMap(params, cx, cy, t0, device=self.device)
 
     def drop_map(self, robot):

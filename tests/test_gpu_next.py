@@ -264,7 +264,7 @@ def test_batch_refuses_the_extensions(dev):
     _say("batch refusal")
     pb = PipelineBatch(device=dev)
     xyz = _dev(dev, np.zeros(10), np.zeros(10), np.full(10, -1.0))
-    for extra in (dict(time_variance=0.001), dict(wall_min_count=2)):
+    for extra in (dict(time_variance=0.001), dict(wall_min_count=2), dict(upper_bound=1)):
         params = dict(nx=16, ny=16, resolution=0.1, **extra)
         m = _map(params, dev)
         with pytest.raises(EmxError) as e:
