@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=50)
     ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-features", action="store_true")
     ap.add_argument("--skip-server", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=20)
     ap.add_argument("--server-seconds", type=float, default=1.0)
@@ -284,6 +285,109 @@ def plain_single_robot(args, dev):
                      "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_us": dk["avg_us"]},
     }
     return out, dict(frames=frames, centers=centers, params=params)
+
+
+# --------------------------------------------------- optional per-map features
+def features(args, dev, ctx):
+    """The features beyond the base path, on the same workload and frames: a
+    map with time variance, the wall/edge rule and the upper bound layer on,
+    run through the extended per-frame sequence (move, drift compensation,
+    fusion, clearing with the bound, normals, traversability, overlap
+    clearance, inpainting).  Each feature is then timed per kernel over the
+    frames; algorithmic bytes per call are stated in ``FEATURE_BYTES``."""
+    import torch
+
+    import synth
+    from paper_2204_12876_amd import ElevationMap, _emx, smooth
+
+    frames, centers, params = ctx["frames"], ctx["centers"], ctx["params"]
+    W = min(args.warmup, len(frames) // 2)
+    K = min(args.steps, len(frames) - W, 20)
+    C = params["nx"] * params["ny"]
+    pe = dict(params, time_variance=1e-4, wall_min_count=8, upper_bound=1)
+    w = torch.from_numpy(synth.trav_weights()).to(dev)
+    m = ElevationMap(pe, centers[0][0], centers[0][1], 0, device=dev)
+    scratch = m.scratch(max(f[0].numel() for f in frames))
+    trav_min = 0.0
+
+    def frame(k):
+        x, y, z, pose, t = frames[k]
+        m.move_map(*centers[k])
+        m.compensate_drift(x, y, z, pose, t, trav_min, scratch=scratch)
+        m.fuse_points(x, y, z, pose, t, scratch=scratch)
+        m.clear_visibility(x, y, z, pose, t, scratch=scratch)
+        m.compute_normals()
+        m.traversability(w)
+        m.overlap_clear(pose[:, 3], 1.0, 1.5)
+        return m.inpaint_min()
+
+    for k in range(W):
+        frame(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(K):
+        frame(W + j)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    say(f"extended sequence: {wall / K * 1e3:.3f} ms/frame")
+
+    g = m.state_numpy()
+    valid = float((g["valid"] != 0).sum())
+    n_mean = float(np.mean([frames[W + j][0].numel() for j in range(K)]))
+    cell = torch.empty(int(n_mean) + 1024, dtype=torch.int32, device=dev)
+    m2 = ElevationMap(params, centers[W][0], centers[W][1], 0, device=dev)
+    x, y, z, pose, t = frames[W]
+    m2.fuse_points(x, y, z, pose, t, out_cell=cell[:x.numel()])
+    c = cell[:x.numel()].cpu().numpy()
+    touched = float(np.unique(c[c >= 0]).size)
+    m2.close()
+    filled = m.inpaint_min()
+
+    def timed(fn, reps=K):
+        _emx.timing_begin()
+        for j in range(reps):
+            fn(j)
+        kt = _emx.timing_end()
+        return {k: v for k, v in kt.items()}
+
+    x0 = frames[W]
+    ops = {
+        "drift_compensation": (
+            lambda j: m.compensate_drift(*frames[W + j][:5], trav_min, scratch=scratch),
+            12 * n_mean + 9 * touched + C + 8 * valid),
+        "wall_rule_and_time_variance_fusion": (
+            lambda j: m.fuse_points(*frames[W + j][:5], scratch=scratch), None),
+        "upper_bound_clearing": (
+            lambda j: m.clear_visibility(*frames[W + j][:5], scratch=scratch), None),
+        "overlap_clearance": (lambda j: m.overlap_clear(x0[3][:, 3], 1.0, 1.5), 5 * C),
+        "inpaint_min": (lambda j: m.inpaint_min(), 9 * C),
+        "smooth_box_5": (lambda j: smooth(filled, "box", 5), 8 * C),
+        "smooth_gaussian_5": (lambda j: smooth(filled, "gaussian", 5, 1.0), 8 * C),
+        "smooth_median_5": (lambda j: smooth(filled, "median", 5), 8 * C),
+    }
+    out = {"workload": "the plain workload's map and frames with time_variance, "
+                       "wall_min_count=8 and upper_bound on",
+           "extended_ms_per_frame": wall / K * 1e3, "frames": K}
+    for name, (fn, ab) in ops.items():
+        kt = timed(fn)
+        per_call_us = sum(tot for _, tot in kt.values()) / K * 1e3
+        ent = {"kernels": {k: {"launches": cnt, "avg_us": tot / cnt * 1e3}
+                           for k, (cnt, tot) in kt.items()},
+               "us_per_call": per_call_us}
+        if ab is not None and per_call_us > 0:
+            gbps = ab / (per_call_us * 1e-6) / 1e9
+            ent.update(alg_bytes=ab, alg_GBps=gbps, frac_hbm=gbps / HBM_PEAK_GBS)
+        out[name] = ent
+    # the feature kernels inside the extended fusion: counts and time variance
+    fk = out["wall_rule_and_time_variance_fusion"]["kernels"]
+    extra = {k: fk[k] for k in ("k_zero_u32", "k_fuse_count", "k_time_variance") if k in fk}
+    ab = {"k_zero_u32": 4 * C, "k_fuse_count": 12 * n_mean + 8 * touched,
+          "k_time_variance": 2 * C + 8 * valid}
+    for k, e in extra.items():
+        e["alg_bytes"] = ab[k]
+        e["alg_GBps"] = ab[k] / (e["avg_us"] * 1e-6) / 1e9
+    m.close()
+    return out
 
 
 # ------------------------------------------------------------ batched, 16 maps
@@ -592,6 +696,8 @@ def main():
         "data": "synthetic",
     }
     out.update(plain)
+    if not args.skip_features:
+        out["features"] = features(args, dev, ctx)
     if not args.skip_batched:
         out["batched"] = batched_maps(args, dev, tuning)
     if not args.skip_server:

@@ -2,20 +2,21 @@
 //
 // Minimum-filter inpainting: the invalid cells form regions connected through
 // their edge neighbours; each region takes the smallest height on its border.
-// Five per-cell launches:
-//   1. init: every invalid cell is its own parent; every region minimum is
-//      "none";
-//   2. union: each invalid cell joins its right and lower invalid
-//      neighbours.  The union-find links the larger root below the smaller
-//      one with an integer atomic minimum, so links only ever point to smaller
-//      indices: no cycles, and each region ends with its smallest cell as the
-//      root whatever the order of the unions;
-//   3. flatten: each invalid cell points straight at its root;
-//   4. border: each valid cell offers its height to the roots of its invalid
-//      edge neighbours, by an integer atomic minimum over an order-preserving
-//      key of the float;
-//   5. fill: invalid cells read their root's minimum (NaN if none).
-// Every step is order-free, so the output is deterministic.
+// A union-find over the grid labels the regions.  Links only ever point from
+// a larger cell index to a smaller one (an integer atomic minimum), so there
+// are no cycles and each region ends with its smallest cell as the root,
+// whatever the order of the unions.  Four per-cell launches:
+//   1. local: per 32 x 32 tile, in LDS, the union of the tile's invalid cells
+//      and, per tile-local region, the minimum border height offered from
+//      inside the tile.  Writes each invalid cell's parent (its local root)
+//      and the local minimum at each local root;
+//   2. merge: invalid cells on a tile edge unite with their invalid
+//      neighbours across it, in the global parent array;
+//   3. border: local roots pass their minimum to their final root, and valid
+//      cells on a tile edge offer their height across it;
+//   4. fill: invalid cells read their final root's minimum (NaN if none).
+// Minima are integer atomics over an order-preserving key of the float, so
+// the output is deterministic.
 //
 // Smoothing (box, Gaussian, median) works on 16 x 16 output tiles.  A
 // workgroup stages the tile and its mirrored halo in LDS; box and Gaussian
@@ -43,10 +44,14 @@ constexpr uint32_t kNoKey = 0xffffffffu;
 struct InpaintArgs {
   Consts c;
   Layers L;
-  int32_t* parent;  // [cells] root chain of invalid cells; -1 for valid ones
-  uint32_t* best;   // [cells] per root: key of the smallest border height
+  int32_t* parent;  // [cells] parent chain of invalid cells (global indices)
+  uint32_t* best;   // [cells] at local roots: key of the smallest border height
   float* out;       // [cells]
+  int tiles_x;
 };
+
+constexpr int kIT = 32;                // inpainting tile side
+constexpr int kNTl = kIT * kIT;        // one thread per tile cell
 
 __device__ __forceinline__ int32_t find_root(const int32_t* parent, int32_t x) {
   // parents change under concurrent unions: read them through the atomics path
@@ -58,10 +63,24 @@ __device__ __forceinline__ int32_t find_root(const int32_t* parent, int32_t x) {
   return x;
 }
 
+// find_root that also halves the path: each visited cell is pointed at its
+// grandparent.  The write is an atomic minimum, so it can never undo a link
+// made meanwhile (parents only decrease, and stay ancestors).
+__device__ __forceinline__ int32_t find_halve(int32_t* parent, int32_t x) {
+  int32_t p = __atomic_load_n(parent + x, __ATOMIC_RELAXED);
+  while (p != x) {
+    const int32_t g = __atomic_load_n(parent + p, __ATOMIC_RELAXED);
+    if (g != p) atomicMin(parent + x, g);
+    x = p;
+    p = g;
+  }
+  return x;
+}
+
 __device__ __forceinline__ void unite(int32_t* parent, int32_t a, int32_t b) {
   while (true) {
-    a = find_root(parent, a);
-    b = find_root(parent, b);
+    a = find_halve(parent, a);
+    b = find_halve(parent, b);
     if (a == b) return;
     if (a < b) {
       const int32_t t = a;
@@ -75,54 +94,145 @@ __device__ __forceinline__ void unite(int32_t* parent, int32_t a, int32_t b) {
   }
 }
 
-__global__ __launch_bounds__(kNTi) void k_inp_init(InpaintArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * kNTi + threadIdx.x;
-  if (i >= (int64_t)a.c.nx * a.c.ny) return;
-  a.parent[i] = a.L.valid[i] ? -1 : (int32_t)i;
-  a.best[i] = kNoKey;
+// The same union-find on a tile's LDS array of local indices.
+__device__ __forceinline__ int lds_find(volatile int* par, int x) {
+  int p = par[x];
+  while (p != x) {
+    x = p;
+    p = par[x];
+  }
+  return x;
 }
 
-__global__ __launch_bounds__(kNTi) void k_inp_union(InpaintArgs a) {
+__device__ __forceinline__ void lds_unite(int* par, int a, int b) {
+  volatile int* vp = par;
+  while (true) {
+    a = lds_find(vp, a);
+    b = lds_find(vp, b);
+    if (a == b) return;
+    if (a < b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const int old = atomicMin(par + a, b);
+    if (old == a) return;
+    a = old;
+  }
+}
+
+__global__ __launch_bounds__(kNTl) void k_inp_local(InpaintArgs a) {
+  __shared__ int s_par[kNTl];
+  __shared__ uint32_t s_best[kNTl];
+  const int nx = a.c.nx;
+  const int ny = a.c.ny;
+  const int tid = threadIdx.x;
+  const int lx = tid % kIT;
+  const int ly = tid / kIT;
+  const int x0 = (int)(blockIdx.x % a.tiles_x) * kIT;
+  const int y0 = (int)(blockIdx.x / a.tiles_x) * kIT;
+  const int gx = x0 + lx;
+  const int gy = y0 + ly;
+  const bool in = gx < nx && gy < ny;
+  const int64_t i = (int64_t)gy * nx + gx;
+  const bool ok = in && a.L.valid[i];
+  const bool hole = in && !ok;
+  // Rows first, without atomics: a hole's parent is the first cell of its
+  // run of holes along the row (a tile row is half a wave: one ballot).
+  const uint64_t bal = __ballot(hole);
+  const uint32_t row = (uint32_t)(bal >> (tid & 32));
+  const uint32_t gaps = ~row & ((1u << lx) - 1u);   // non-holes left of lx
+  const int start = gaps ? 32 - __builtin_clz(gaps) : 0;
+  s_par[tid] = hole ? ly * kIT + start : -1;
+  s_best[tid] = kNoKey;
+  __syncthreads();
+  // Then columns: join a run to the run above where they first overlap.
+  if (hole && ly > 0 && s_par[tid - kIT] >= 0 && (lx == start || s_par[tid - kIT - 1] < 0))
+    lds_unite(s_par, ly * kIT + start, tid - kIT);
+  __syncthreads();
+  // offers from valid cells to holes of the same tile: per direction, the
+  // lanes of a wave that offer to one region are reduced first, so that each
+  // region takes one LDS atomic per wave
+  {
+    volatile int* vp = s_par;
+    const uint32_t k = ok ? f32_key(a.L.h[i]) : kNoKey;
+    const int nb[4] = {lx > 0 ? tid - 1 : -1, lx + 1 < kIT && gx + 1 < nx ? tid + 1 : -1,
+                       ly > 0 ? tid - kIT : -1, ly + 1 < kIT && gy + 1 < ny ? tid + kIT : -1};
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      int r = (ok && nb[d] >= 0 && vp[nb[d]] >= 0) ? lds_find(vp, nb[d]) : -1;
+      uint64_t pend = __ballot(r >= 0);
+      while (pend) {
+        const int leader = __builtin_ctzll(pend);
+        const int R = __shfl(r, leader, 64);
+        uint32_t m = r == R ? k : kNoKey;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, o, 64));
+        if ((threadIdx.x & 63) == leader) atomicMin(s_best + R, m);
+        if (r == R) r = -1;
+        pend = __ballot(r >= 0);
+      }
+    }
+  }
+  __syncthreads();
+  if (hole) {
+    const int r = lds_find(s_par, tid);
+    a.parent[i] = (int32_t)((int64_t)(y0 + r / kIT) * nx + x0 + r % kIT);
+    a.best[i] = r == tid ? s_best[tid] : kNoKey;
+  }
+}
+
+__global__ __launch_bounds__(kNTi) void k_inp_merge(InpaintArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kNTi + threadIdx.x;
   const int nx = a.c.nx;
-  if (i >= (int64_t)nx * a.c.ny || a.L.valid[i]) return;
+  if (i >= (int64_t)nx * a.c.ny) return;
   const int iy = (int)(i / nx);
   const int ix = (int)(i - (int64_t)iy * nx);
-  if (ix + 1 < nx && !a.L.valid[i + 1]) unite(a.parent, (int32_t)i, (int32_t)(i + 1));
-  if (iy + 1 < a.c.ny && !a.L.valid[i + nx]) unite(a.parent, (int32_t)i, (int32_t)(i + nx));
-}
-
-__global__ __launch_bounds__(kNTi) void k_inp_flatten(InpaintArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * kNTi + threadIdx.x;
-  if (i >= (int64_t)a.c.nx * a.c.ny || a.L.valid[i]) return;
-  a.parent[i] = find_root(a.parent, (int32_t)i);
+  const bool right = (ix % kIT) == kIT - 1 && ix + 1 < nx;
+  const bool down = (iy % kIT) == kIT - 1 && iy + 1 < a.c.ny;
+  if (!(right || down) || a.L.valid[i]) return;
+  // Along an edge, hole pairs next to each other are already joined on both
+  // sides: only the first pair of each run of pairs unites.
+  if (right && !a.L.valid[i + 1] &&
+      (iy % kIT == 0 || a.L.valid[i - nx] || a.L.valid[i - nx + 1]))
+    unite(a.parent, (int32_t)i, (int32_t)(i + 1));
+  if (down && !a.L.valid[i + nx] && (ix % kIT == 0 || a.L.valid[i - 1] || a.L.valid[i + nx - 1]))
+    unite(a.parent, (int32_t)i, (int32_t)(i + nx));
 }
 
 __global__ __launch_bounds__(kNTi) void k_inp_border(InpaintArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kNTi + threadIdx.x;
   const int nx = a.c.nx;
   const int ny = a.c.ny;
-  if (i >= (int64_t)nx * ny || !a.L.valid[i]) return;
+  if (i >= (int64_t)nx * ny) return;
   const int iy = (int)(i / nx);
   const int ix = (int)(i - (int64_t)iy * nx);
-  const uint32_t k = f32_key(a.L.h[i]);
-  int32_t last = -1;  // neighbours in one region share a root: offer it once
-  const int64_t nb[4] = {ix > 0 ? i - 1 : -1, ix + 1 < nx ? i + 1 : -1,
-                         iy > 0 ? i - nx : -1, iy + 1 < ny ? i + nx : -1};
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    if (nb[d] < 0 || a.L.valid[nb[d]]) continue;
-    const int32_t r = a.parent[nb[d]];
-    if (r == last) continue;
-    last = r;
-    if (k < a.best[r]) atomicMin(a.best + r, k);
+  if (!a.L.valid[i]) {
+    // a local root hands its tile's minimum to the final root
+    const uint32_t k = a.best[i];
+    if (k == kNoKey) return;
+    const int32_t r = find_root(a.parent, (int32_t)i);
+    if (r != (int32_t)i) atomicMin(a.best + r, k);
+    return;
   }
+  // valid cells offer their height to holes across a tile edge
+  const int tx = ix % kIT;
+  const int ty = iy % kIT;
+  if (tx != 0 && tx != kIT - 1 && ty != 0 && ty != kIT - 1) return;
+  const uint32_t k = f32_key(a.L.h[i]);
+  if (tx == 0 && ix > 0 && !a.L.valid[i - 1]) atomicMin(a.best + find_root(a.parent, (int32_t)(i - 1)), k);
+  if (tx == kIT - 1 && ix + 1 < nx && !a.L.valid[i + 1])
+    atomicMin(a.best + find_root(a.parent, (int32_t)(i + 1)), k);
+  if (ty == 0 && iy > 0 && !a.L.valid[i - nx])
+    atomicMin(a.best + find_root(a.parent, (int32_t)(i - nx)), k);
+  if (ty == kIT - 1 && iy + 1 < ny && !a.L.valid[i + nx])
+    atomicMin(a.best + find_root(a.parent, (int32_t)(i + nx)), k);
 }
 
 __global__ __launch_bounds__(kNTi) void k_inp_fill(InpaintArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kNTi + threadIdx.x;
   if (i >= (int64_t)a.c.nx * a.c.ny) return;
-  a.out[i] = a.L.valid[i] ? a.L.h[i] : key_f32(a.best[a.parent[i]]);
+  a.out[i] = a.L.valid[i] ? a.L.h[i] : key_f32(a.best[find_root(a.parent, (int32_t)i)]);
 }
 
 // -------------------------------------------------------------- smoothing
@@ -248,21 +358,18 @@ hipError_t launch_inpaint(const Consts& c, const Layers& L, float* out, char* sc
   a.parent = (int32_t*)scratch;
   a.best = (uint32_t*)(scratch + align256((size_t)C * 4));
   a.out = out;
+  a.tiles_x = (c.nx + kIT - 1) / kIT;
+  const unsigned tiles = (unsigned)(a.tiles_x * ((c.ny + kIT - 1) / kIT));
   const dim3 grid((unsigned)((C + kNTi - 1) / kNTi));
   hipError_t e;
   {
-    TimedLaunch tl("k_inp_init", stream);
-    hipLaunchKernelGGL(k_inp_init, grid, dim3(kNTi), 0, stream, a);
+    TimedLaunch tl("k_inp_local", stream);
+    hipLaunchKernelGGL(k_inp_local, dim3(tiles), dim3(kNTl), 0, stream, a);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   {
-    TimedLaunch tl("k_inp_union", stream);
-    hipLaunchKernelGGL(k_inp_union, grid, dim3(kNTi), 0, stream, a);
-  }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  {
-    TimedLaunch tl("k_inp_flatten", stream);
-    hipLaunchKernelGGL(k_inp_flatten, grid, dim3(kNTi), 0, stream, a);
+    TimedLaunch tl("k_inp_merge", stream);
+    hipLaunchKernelGGL(k_inp_merge, grid, dim3(kNTi), 0, stream, a);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   {

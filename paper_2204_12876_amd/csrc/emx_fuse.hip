@@ -466,17 +466,46 @@ __device__ __forceinline__ void tile_body(const Item& it, int t) {
 }
 
 // ------------------------------------------------------- wall rule: counts
-// The frame's valid in-map points per cell, by integer atomics (the counts do
-// not depend on their order).  The counts are zeroed by the launch before.
+// The frame's valid in-map points per cell.  Near the sensor thousands of
+// points share a cell, and global atomics on one address serialise, so each
+// workgroup first counts its chunk in an LDS hash table (open addressing,
+// twice as many slots as points: a free slot always exists) and then adds one
+// count per distinct cell.  Integer sums do not depend on their order.  The
+// counts are zeroed by the launch before.
+constexpr int kCountSlotsLog = 11;
+constexpr int kCountSlots = 1 << kCountSlotsLog;
+static_assert(kCountSlots >= 2 * kChunk, "the table must keep a free slot");
+
 __device__ __forceinline__ void count_body(const Item& it, int64_t chunk) {
+  __shared__ uint32_t s_key[kCountSlots];  // cell + 1, 0 = empty
+  __shared__ uint32_t s_cnt[kCountSlots];
+  for (int j = threadIdx.x; j < kCountSlots; j += kNT1) {
+    s_key[j] = 0u;
+    s_cnt[j] = 0u;
+  }
+  __syncthreads();
 #pragma unroll
   for (int j = 0; j < kChunk / kNT1; ++j) {
     const int64_t i = chunk * kChunk + j * kNT1 + threadIdx.x;
     if (i >= it.n) continue;
     const PointEval e = eval_point(it.P, it.c, it.x[i], it.y[i], it.z[i]);
     int ix, iy;
-    if (e.valid && bin_xy(e.xm, e.ym, it.c, ix, iy))
-      atomicAdd(it.fs.count + ((int64_t)iy * it.c.nx + ix), 1u);
+    if (!e.valid || !bin_xy(e.xm, e.ym, it.c, ix, iy)) continue;
+    const uint32_t key = (uint32_t)iy * (uint32_t)it.c.nx + (uint32_t)ix + 1u;
+    uint32_t h = (key * 2654435761u) >> (32 - kCountSlotsLog);
+    while (true) {
+      const uint32_t prev = atomicCAS(s_key + h, 0u, key);
+      if (prev == 0u || prev == key) {
+        atomicAdd(s_cnt + h, 1u);
+        break;
+      }
+      h = (h + 1u) & (kCountSlots - 1);
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < kCountSlots; j += kNT1) {
+    const uint32_t key = s_key[j];
+    if (key) atomicAdd(it.fs.count + (key - 1u), s_cnt[j]);
   }
 }
 

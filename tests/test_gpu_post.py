@@ -154,7 +154,8 @@ def test_overlap_clear(dev, seed):
 
 # ---------------------------------------------------------------- inpainting
 @pytest.mark.parametrize("shape,frac", [((7, 5), 0.5), ((90, 130), 0.35), ((300, 257), 0.6),
-                                        ((64, 64), 0.0), ((33, 20), 1.0)])
+                                        ((64, 64), 0.0), ((33, 20), 1.0), ((517, 611), 0.45),
+                                        ((260, 190), 0.03)])
 def test_inpaint_min(dev, shape, frac):
     _say("inpaint", shape, frac)
     ny, nx = shape
