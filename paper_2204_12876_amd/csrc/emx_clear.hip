@@ -209,23 +209,23 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
   const int bx = it.bx;
   const float inv_r = it.c.inv_r;
   const int nx = it.c.nx;
-  const int ny = it.c.ny;
   for (int k = ka; k <= kb; k += kUnroll) {
     int cell[kUnroll];
     float qz[kUnroll];
     bool cand[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const float t = t_of(r, k + u);
+      // [ka, kb] lies in the ray's in-map range, which the setup found with
+      // this very evaluation (f_of): qx * inv_r and qy * inv_r are in [0, nx)
+      // and [0, ny), so truncation is floor and the cell is in the map.  The
+      // unused slots past kb evaluate sample kb again, so they stay in the map
+      // too; they are never candidates.
+      const float t = t_of(r, min(k + u, kb));
       const float qx = r.ox + t * r.dx;
       const float qy = r.oy + t * r.dy;
       qz[u] = r.oz + t * r.dz;
-      // [ka, kb] lies in the ray's in-map range, which the setup found with
-      // this very evaluation: qx * inv_r and qy * inv_r are in [0, nx) and
-      // [0, ny), so truncation is floor.  The clamp only keeps the unused
-      // samples past kb in bounds.
-      const int ix = min(max((int)(qx * inv_r), 0), nx - 1);
-      const int iy = min(max((int)(qy * inv_r), 0), ny - 1);
+      const int ix = (int)(qx * inv_r);
+      const int iy = (int)(qy * inv_r);
       cell[u] = iy * nx + ix;
       const float m = kRec ? cm[(iy >> bl) * bx + (ix >> bl)] : INFINITY;
       cand[u] = (k + u <= kb) && (qz[u] < m) && cell[u] != end_cell;
