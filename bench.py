@@ -5,8 +5,9 @@ Headline workload: one robot.
   * 300k-point frames: a 64-beam dome LiDAR plus four depth frustums.
   * The frames follow a seeded smooth trajectory over a synthetic terrain.
 One step is one frame through the whole per-frame path, the ABI calls in
-order: move_map, fuse_points, clear_visibility, compute_normals,
-traversability.  Every frame is generated on the device before timing starts.
+order: move_map, fuse_points, clear_visibility, normals_traversability (the
+normals and the traversability filter in one pass).  Every frame is generated
+on the device before timing starts.
   * value: the timed frames submitted back to back (inputs resident in HBM),
     points per second of wall time between two device synchronisations.
   * latency_ms: the same frames with the host waiting for each one
@@ -39,7 +40,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "points fused/sec and p99 update latency: batched server vs per-frame plain"
 HBM_PEAK_GBS = 8000.0
-STAGES = ("move_map", "fuse_points", "clear_visibility", "compute_normals", "traversability")
+STAGES = ("move_map", "fuse_points", "clear_visibility", "normals_traversability")
 TUNING_FILE = os.path.join(ROOT, "paper_2204_12876_amd", "tuning_mi355x.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_400x400_300k.txt")
 
@@ -98,6 +99,8 @@ def kernel_alg_bytes(name: str, n: int, C: int, touched: float, updated: float) 
         normal once (25 B); apply reads the marks and writes the output mask;
       normals: h, valid in (5 B), three components out (12 B);
       traversability: h, valid in, one float out (9 B);
+      normals and traversability in one pass: h, valid in, four floats out
+        (21 B);
       move: every layer read and written once (2 x 29 B)."""
     return {
         "k_fuse_chunk": 12 * n + 8 * touched,
@@ -107,6 +110,7 @@ def kernel_alg_bytes(name: str, n: int, C: int, touched: float, updated: float) 
         "k_clear_apply": 2 * C,
         "k_normals": 17 * C,
         "k_trav": 9 * C,
+        "k_normals_trav": 21 * C,
         "k_move": 58 * C,
     }.get(name, 0.0)
 
@@ -115,6 +119,7 @@ KERNEL_SOURCE = {"k_fuse_chunk": "emx_fuse.hip", "k_fuse_tile": "emx_fuse.hip",
                  "k_clear_setup": "emx_clear.hip", "k_clear_march": "emx_clear.hip",
                  "k_clear_apply": "emx_clear.hip", "k_move": "emx_cells.hip",
                  "k_normals": "emx_cells.hip", "k_trav": "emx_cells.hip",
+                 "k_normals_trav": "emx_cells.hip",
                  "k_fill_prior": "emx_cells.hip"}
 
 
@@ -191,12 +196,9 @@ def plain_single_robot(args, dev):
         m.clear_visibility(x, y, z, pose, t, scratch=scratch)
         if ev is not None:
             ev[3].record(stream)
-        m.compute_normals()
+        m.normals_traversability(w)
         if ev is not None:
             ev[4].record(stream)
-        m.traversability(w)
-        if ev is not None:
-            ev[5].record(stream)
 
     def fresh():
         m = ElevationMap(params, centers[0][0], centers[0][1], 0, device=dev)
@@ -219,7 +221,8 @@ def plain_single_robot(args, dev):
 
     # ---- latency: the host waits for every frame; events per stage
     m = fresh()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)]
+           for _ in range(K)]
     lat = np.zeros(K)
     for j in range(K):
         s = time.perf_counter()
@@ -316,8 +319,7 @@ def features(args, dev, ctx):
         m.compensate_drift(x, y, z, pose, t, trav_min, scratch=scratch)
         m.fuse_points(x, y, z, pose, t, scratch=scratch)
         m.clear_visibility(x, y, z, pose, t, scratch=scratch)
-        m.compute_normals()
-        m.traversability(w)
+        m.normals_traversability(w)
         m.overlap_clear(pose[:, 3], 1.0, 1.5)
         return m.inpaint_min()
 
@@ -444,8 +446,7 @@ def batched_maps(args, dev, tuning):
             m.move_map(0.0, 0.0)
             m.fuse_points(x, y, z, pose, 100 * rep, scratch=scratch)
             m.clear_visibility(x, y, z, pose, 100 * rep, scratch=scratch)
-            m.compute_normals()
-            m.traversability(w)
+            m.normals_traversability(w)
 
     for rep in range(3):
         plain(rep)

@@ -251,6 +251,11 @@ emx_status emx_compute_normals(emx_map* map, void* stream);
  *   NaN where the normal is NaN (border or any of the 9 cells invalid). */
 emx_status emx_traversability(emx_map* map, const float* d_weights, void* stream);
 
+/* emx_compute_normals then emx_traversability in one pass over the map (one
+ * launch; each tile's heights are staged once).  Results are bitwise those of
+ * the two calls. */
+emx_status emx_normals_traversability(emx_map* map, const float* d_weights, void* stream);
+
 /* Overlap clearance (Sec. II-F): removes old estimates of another floor
  * near the robot.  In float32, in map-local metres (rx, ry are moved into
  * them in float64, as the pose is):

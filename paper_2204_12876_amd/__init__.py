@@ -168,6 +168,13 @@ class ElevationMap:
             raise ValueError("weights must be 89 float32 values on the map's device")
         _emx.traversability(self.handle, weights.contiguous().data_ptr(), _stream(self.device))
 
+    def normals_traversability(self, weights: torch.Tensor):
+        """compute_normals then traversability, in one pass over the map."""
+        if weights.dtype != torch.float32 or weights.numel() != 89 or weights.device != self.device:
+            raise ValueError("weights must be 89 float32 values on the map's device")
+        _emx.normals_traversability(self.handle, weights.contiguous().data_ptr(),
+                                    _stream(self.device))
+
     # ----------------------------------------------------------------- state
     def layer(self, layer_id: int) -> torch.Tensor:
         """A [ny, nx] view of one layer of the current buffer set."""

@@ -85,6 +85,7 @@ _SIGS = {
                              c_void_p]),
     "emx_compute_normals": (c_int32, [c_void_p, c_void_p]),
     "emx_traversability": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "emx_normals_traversability": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "emx_layer": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
     "emx_map_info": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int64)]),
     "emx_export_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
@@ -255,6 +256,10 @@ def compute_normals(h: int, stream: int):
 
 def traversability(h: int, d_weights: int, stream: int):
     check(lib().emx_traversability(c_void_p(h), c_void_p(d_weights), c_void_p(stream)))
+
+
+def normals_traversability(h: int, d_weights: int, stream: int):
+    check(lib().emx_normals_traversability(c_void_p(h), c_void_p(d_weights), c_void_p(stream)))
 
 
 def layer(h: int, layer_id: int) -> int:

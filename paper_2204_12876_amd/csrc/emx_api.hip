@@ -475,6 +475,19 @@ emx_status emx_traversability(emx_map* m, const float* d_weights, void* stream) 
   return EMX_OK;
 }
 
+emx_status emx_normals_traversability(emx_map* m, const float* d_weights, void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if (!d_weights) return fail(EMX_EINVAL, "d_weights is NULL");
+  Item it;
+  make_item(m, nullptr, &it);
+  it.w = d_weights;
+  it.stages = kStageNormals | kStageTrav;
+  hipError_t e = launch_normals_trav(it, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "normals_traversability");
+  return EMX_OK;
+}
+
 emx_status emx_layer(emx_map* m, int32_t layer, void** d_ptr) {
   emx_status s = check_map(m);
   if (s != EMX_OK) return s;

@@ -221,6 +221,10 @@ __global__ __launch_bounds__(kNTf) void k_normals(Item it) {
 __global__ __launch_bounds__(kNTf) void k_trav(Item it) {
   cells_body(it, blockIdx.x, false, true);
 }
+// Both from one staged tile: the heights are read once.
+__global__ __launch_bounds__(kNTf) void k_normals_trav(Item it) {
+  cells_body(it, blockIdx.x, true, true);
+}
 
 // The batch's first launch: also zeroes the clearing queue counters, which
 // the later setup launch increments.
@@ -292,6 +296,13 @@ hipError_t launch_trav(const Item& it, hipStream_t stream) {
   TimedLaunch tl("k_trav", stream);
   hipLaunchKernelGGL(k_trav, dim3((unsigned)cells_units(it.c.nx, it.c.ny)), dim3(kNTf), 0, stream,
                      it);
+  return hipGetLastError();
+}
+
+hipError_t launch_normals_trav(const Item& it, hipStream_t stream) {
+  TimedLaunch tl("k_normals_trav", stream);
+  hipLaunchKernelGGL(k_normals_trav, dim3((unsigned)cells_units(it.c.nx, it.c.ny)), dim3(kNTf), 0,
+                     stream, it);
   return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ struct OverlapArgs {
 hipError_t launch_overlap(const OverlapArgs& a, hipStream_t stream);
 hipError_t launch_normals(const Item& it, hipStream_t stream);
 hipError_t launch_trav(const Item& it, hipStream_t stream);
+hipError_t launch_normals_trav(const Item& it, hipStream_t stream);
 hipError_t launch_move_batch(const Batch* d_batch, int grid, hipStream_t stream);
 hipError_t launch_cells_batch(const Batch* d_batch, int grid, hipStream_t stream);
 

@@ -404,9 +404,10 @@ class GpuExecutor:
             m.move_map(*r.center)
             m.fuse_points(x, y, z, r.pose, r.t_ms, scratch=scratch)
             m.clear_visibility(x, y, z, r.pose, r.t_ms, scratch=scratch)
-            m.compute_normals()
             if self.weights is not None:
-                m.traversability(self.weights)
+                m.normals_traversability(self.weights)
+            else:
+                m.compute_normals()
             self.ends[lane].record(st)
 
     def done(self, lane: int) -> bool:
@@ -468,9 +469,10 @@ def run_plain_trace(maps: dict, requests: List[Request], weights: torch.Tensor, 
         m.move_map(*r.center)
         m.fuse_points(x, y, z, r.pose, r.t_ms, scratch=scratch)
         m.clear_visibility(x, y, z, r.pose, r.t_ms, scratch=scratch)
-        m.compute_normals()
         if weights is not None:
-            m.traversability(weights)
+            m.normals_traversability(weights)
+        else:
+            m.compute_normals()
         e = torch.cuda.Event(enable_timing=True)
         e.record(st)
         ends.append((r, e))

@@ -294,7 +294,15 @@ def test_normals_and_traversability(dev, shape):
     assert_normals_parity(g, O.compute_normals(p, st.h, st.valid))
     T, S = O.traversability(st.h, st.valid, synth.trav_weights())
     assert_trav_parity(g, T, S)
+    # the one-pass call gives the two calls' bits
+    m2 = _map(params, dev)
+    load_state(m2, st)
+    m2.normals_traversability(w)
+    g2 = m2.state_numpy()
+    for k in ("nrm", "trav"):
+        assert np.array_equal(g[k].view(np.uint32), g2[k].view(np.uint32)), k
     m.close()
+    m2.close()
 
 
 # --------------------------------------------------------------------------- move
