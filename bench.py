@@ -5,9 +5,10 @@ Headline workload: one robot.
   * 300k-point frames: a 64-beam dome LiDAR plus four depth frustums.
   * The frames follow a seeded smooth trajectory over a synthetic terrain.
 One step is one frame through the whole per-frame path, the ABI calls in
-order: move_map, fuse_points, clear_visibility, normals_traversability (the
-normals and the traversability filter in one pass).  Every frame is generated
-on the device before timing starts.
+order: move_fuse_points (the robot-centric move inside the fusion),
+clear_visibility, normals_traversability (the normals and the traversability
+filter in one pass).  Every frame is generated on the device before timing
+starts.
   * value: the timed frames submitted back to back (inputs resident in HBM),
     points per second of wall time between two device synchronisations.
   * latency_ms: the same frames with the host waiting for each one
@@ -28,6 +29,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import platform
 import sys
@@ -40,7 +42,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "points fused/sec and p99 update latency: batched server vs per-frame plain"
 HBM_PEAK_GBS = 8000.0
-STAGES = ("move_map", "fuse_points", "clear_visibility", "normals_traversability")
+STAGES = ("move_fuse_points", "clear_visibility", "normals_traversability")
 TUNING_FILE = os.path.join(ROOT, "paper_2204_12876_amd", "tuning_mi355x.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_400x400_300k.txt")
 
@@ -88,12 +90,14 @@ def frame_stats(cell: np.ndarray, acc: np.ndarray) -> dict:
                 updated=np.unique(cell[acc.astype(bool)]).size)
 
 
-def kernel_alg_bytes(name: str, n: int, C: int, touched: float, updated: float) -> float:
+def kernel_alg_bytes(name: str, n: int, C: int, touched: float, updated: float,
+                     moved: float = 0.0) -> float:
     """Bytes each kernel must move at the least, per launch.
       fusion pass 1: the points (12 B) and the prior h, v of each distinct
         in-map cell they hit (8 B);
       fusion pass 2: prior h, v read and h, v, t_upd, valid written for each
-        updated cell (8 + 13 B);
+        updated cell (8 + 13 B); with the move folded in (a frame whose centre
+        cell changes), also every layer read and written once (2 x 29 B);
       clearing: setup reads the points and h, t_upd, valid per cell for the
         block maxima (9 B); the march reads each cell's h, v, t_upd, valid and
         normal once (25 B); apply reads the marks and writes the output mask;
@@ -104,7 +108,7 @@ def kernel_alg_bytes(name: str, n: int, C: int, touched: float, updated: float) 
       move: every layer read and written once (2 x 29 B)."""
     return {
         "k_fuse_chunk": 12 * n + 8 * touched,
-        "k_fuse_tile": 21 * updated,
+        "k_fuse_tile": 21 * updated + 58 * C * moved,
         "k_clear_setup": 12 * n + 9 * C,
         "k_clear_march": 25 * C,
         "k_clear_apply": 2 * C,
@@ -187,18 +191,16 @@ def plain_single_robot(args, dev):
         x, y, z, pose, t = frames[k]
         if ev is not None:
             ev[0].record(stream)
-        m.move_map(*centers[k])
+        m.move_fuse_points(*centers[k], x, y, z, pose, t, scratch=scratch, out_cell=cell,
+                           out_accept=acc)
         if ev is not None:
             ev[1].record(stream)
-        m.fuse_points(x, y, z, pose, t, scratch=scratch, out_cell=cell, out_accept=acc)
-        if ev is not None:
-            ev[2].record(stream)
         m.clear_visibility(x, y, z, pose, t, scratch=scratch)
         if ev is not None:
-            ev[3].record(stream)
+            ev[2].record(stream)
         m.normals_traversability(w)
         if ev is not None:
-            ev[4].record(stream)
+            ev[3].record(stream)
 
     def fresh():
         m = ElevationMap(params, centers[0][0], centers[0][1], 0, device=dev)
@@ -255,10 +257,15 @@ def plain_single_robot(args, dev):
     touched = float(np.mean([s["touched"] for s in stats]))
     updated = float(np.mean([s["updated"] for s in stats]))
     n_mean = n_pts / K
+    # the share of timed frames whose centre cell changes (the move is folded
+    # into fusion pass 2 for those)
+    r = params["resolution"]
+    cell_of = [(math.floor(cx / r), math.floor(cy / r)) for cx, cy in centers]
+    moved = float(np.mean([cell_of[W + j] != cell_of[W + j - 1] for j in range(K)]))
     kernels = {}
     for name, (cnt, tot_ms) in kt.items():
         avg_us = tot_ms / cnt * 1e3
-        ab = kernel_alg_bytes(name, n_mean, C, touched, updated)
+        ab = kernel_alg_bytes(name, n_mean, C, touched, updated, moved)
         kernels[name] = {"launches": cnt, "avg_us": avg_us, "alg_bytes": ab,
                          "alg_GBps": ab / (avg_us * 1e-6) / 1e9 if avg_us > 0 else None}
     dom = max((k for k in kernels if k != "k_fill_prior"),
@@ -280,7 +287,7 @@ def plain_single_robot(args, dev):
         "maps_per_s": K / wall,
         "stage_ms": stage_ms,
         "kernels": kernels,
-        "cells_touched": touched, "cells_updated": updated,
+        "cells_touched": touched, "cells_updated": updated, "frames_moved": moved,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dk["alg_GBps"] / HBM_PEAK_GBS,
@@ -443,8 +450,7 @@ def batched_maps(args, dev, tuning):
 
     def plain(rep):
         for m, (x, y, z, pose) in zip(mp, fr):
-            m.move_map(0.0, 0.0)
-            m.fuse_points(x, y, z, pose, 100 * rep, scratch=scratch)
+            m.move_fuse_points(0.0, 0.0, x, y, z, pose, 100 * rep, scratch=scratch)
             m.clear_visibility(x, y, z, pose, 100 * rep, scratch=scratch)
             m.normals_traversability(w)
 

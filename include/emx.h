@@ -203,6 +203,16 @@ emx_status emx_fuse_points(emx_map* map, const emx_frame* frame, void* d_scratch
                            size_t scratch_bytes, int32_t* d_out_cell,
                            uint8_t* d_out_accept, void* stream);
 
+/* emx_move_map(map, cx, cy) then emx_fuse_points(map, frame, ...), with the
+ * results of the two calls bit for bit.  The move runs inside the fusion's
+ * passes (the prior is read through the shift and each moved cell is written
+ * by the thread that updates it), which saves a pass over the map.  The pose
+ * is taken relative to the moved map.  Arguments are as for the two calls;
+ * everything is checked before anything is enqueued. */
+emx_status emx_move_fuse_points(emx_map* map, double cx, double cy, const emx_frame* frame,
+                                void* d_scratch, size_t scratch_bytes, int32_t* d_out_cell,
+                                uint8_t* d_out_accept, void* stream);
+
 /* Visibility clean-up by ray casting (Sec. II-E, Eq. 3 and Eq. 4).
  *
  * Every valid point casts a ray from the sensor origin o = t32.  This includes

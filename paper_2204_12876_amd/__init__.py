@@ -119,6 +119,21 @@ class ElevationMap:
                               mean.data_ptr(), count.data_ptr(), _stream(self.device))
         return mean, count
 
+    def move_fuse_points(self, cx: float, cy: float, x, y, z, pose, t_ms: int,
+                         out_cell: torch.Tensor = None, out_accept: torch.Tensor = None,
+                         scratch: torch.Tensor = None):
+        """move_map(cx, cy) then fuse_points(...), bit for bit, in one pass."""
+        f, n = self._frame(x, y, z, pose, t_ms)
+        s = scratch if scratch is not None else self.scratch(n)
+        if out_cell is not None and (out_cell.dtype != torch.int32 or out_cell.numel() < n):
+            raise ValueError("out_cell must be int32 with n elements")
+        if out_accept is not None and (out_accept.dtype != torch.uint8 or out_accept.numel() < n):
+            raise ValueError("out_accept must be uint8 with n elements")
+        _emx.move_fuse_points(self.handle, float(cx), float(cy), f, s.data_ptr(), s.numel(),
+                              out_cell.data_ptr() if out_cell is not None else 0,
+                              out_accept.data_ptr() if out_accept is not None else 0,
+                              _stream(self.device))
+
     def clear_visibility(self, x, y, z, pose, t_ms: int, out_cleared: torch.Tensor = None,
                          scratch: torch.Tensor = None):
         f, n = self._frame(x, y, z, pose, t_ms)

@@ -72,6 +72,8 @@ _SIGS = {
     "emx_move_map": (c_int32, [c_void_p, c_double, c_double, c_void_p]),
     "emx_fuse_points": (c_int32, [c_void_p, POINTER(Frame), c_void_p, c_size_t, c_void_p,
                                   c_void_p, c_void_p]),
+    "emx_move_fuse_points": (c_int32, [c_void_p, c_double, c_double, POINTER(Frame), c_void_p,
+                                       c_size_t, c_void_p, c_void_p, c_void_p]),
     "emx_clear_visibility": (c_int32, [c_void_p, POINTER(Frame), c_void_p, c_size_t, c_void_p,
                                        c_void_p]),
     "emx_drift_scratch_bytes": (c_size_t, [c_int64]),
@@ -242,6 +244,13 @@ def compensate_drift(h: int, f: Frame, trav_min: float, d_scratch: int, nbytes: 
                                      c_void_p(d_scratch or None), nbytes,
                                      c_void_p(d_out_mean or None), c_void_p(d_out_count or None),
                                      c_void_p(stream)))
+
+
+def move_fuse_points(h: int, cx: float, cy: float, f: Frame, d_scratch: int, nbytes: int,
+                     d_out_cell: int, d_out_accept: int, stream: int):
+    check(lib().emx_move_fuse_points(c_void_p(h), float(cx), float(cy), byref(f),
+                                     c_void_p(d_scratch), nbytes, c_void_p(d_out_cell or None),
+                                     c_void_p(d_out_accept or None), c_void_p(stream)))
 
 
 def clear_visibility(h: int, f: Frame, d_scratch: int, nbytes: int, d_out_cleared: int,

@@ -297,13 +297,34 @@ emx_status emx_move_map(emx_map* m, double cx, double cy, void* stream) {
   return EMX_OK;
 }
 
-emx_status emx_fuse_points(emx_map* m, const emx_frame* f, void* d_scratch, size_t scratch_bytes,
-                           int32_t* d_out_cell, uint8_t* d_out_accept, void* stream) {
+// fuse_points, optionally preceded by the move to (cx, cy).  Every argument
+// is checked before anything is enqueued.  With a non-zero shift and points,
+// the move runs inside the fusion: pass 1 reads the prior through the shift
+// and pass 2 writes every moved cell before updating it.
+static emx_status fuse_impl(emx_map* m, const emx_frame* f, bool move, double cx, double cy,
+                            void* d_scratch, size_t scratch_bytes, int32_t* d_out_cell,
+                            uint8_t* d_out_accept, void* stream) {
   emx_status s = check_map(m);
   if (s != EMX_OK) return s;
   if ((s = check_frame(f)) != EMX_OK) return s;
+  int64_t ngx = m->cgx, ngy = m->cgy;
+  int sx = 0, sy = 0;
+  if (move && !plan_move(m, cx, cy, &ngx, &ngy, &sx, &sy))
+    return fail(EMX_EINVAL, "map centre out of range");
+  const bool shift = sx != 0 || sy != 0;
+  // the item on the moved map: new origin, the other buffer set
+  emx_map moved = *m;
+  if (shift) {
+    moved.cgx = ngx;
+    moved.cgy = ngy;
+    moved.cur = 1 - m->cur;
+  }
   Item it;
-  if ((s = make_item(m, f, &it)) != EMX_OK) return s;
+  if ((s = make_item(&moved, f, &it)) != EMX_OK) return s;
+  it.Lsrc = m->sets[m->cur];
+  it.sx = sx;
+  it.sy = sy;
+  const bool run = f->n > 0 || m->p.time_variance != 0.0f;
   if (f->n > 0) {
     const int64_t count_cells = m->p.wall_min_count > 0 ? (int64_t)m->p.nx * m->p.ny : 0;
     const size_t need = fuse_scratch_layout(f->n, it.T, count_cells, nullptr, nullptr);
@@ -313,15 +334,38 @@ emx_status emx_fuse_points(emx_map* m, const emx_frame* f, void* d_scratch, size
     if (scratch_bytes < need)
       return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
     fuse_scratch_layout(f->n, it.T, count_cells, (char*)d_scratch, &it.fs);
-  } else if (m->p.time_variance == 0.0f) {
-    return EMX_OK;  // an empty frame changes nothing
   }
   it.out_cell = d_out_cell;
   it.out_accept = d_out_accept;
   it.stages = kStageFuse;
-  hipError_t e = launch_fuse(it, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "fuse_points");
+  hipError_t e = hipSuccess;
+  if (shift && f->n > 0) {
+    it.fuse_move = 1;
+    e = launch_fuse(it, (hipStream_t)stream);
+  } else {
+    if (shift) e = launch_move(it, (hipStream_t)stream);
+    if (e == hipSuccess && run) e = launch_fuse(it, (hipStream_t)stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, move ? "move_fuse_points" : "fuse_points");
+  if (shift) {
+    m->cur = moved.cur;
+    m->cgx = ngx;
+    m->cgy = ngy;
+  }
   return EMX_OK;
+}
+
+emx_status emx_fuse_points(emx_map* m, const emx_frame* f, void* d_scratch, size_t scratch_bytes,
+                           int32_t* d_out_cell, uint8_t* d_out_accept, void* stream) {
+  return fuse_impl(m, f, false, 0.0, 0.0, d_scratch, scratch_bytes, d_out_cell, d_out_accept,
+                   stream);
+}
+
+emx_status emx_move_fuse_points(emx_map* m, double cx, double cy, const emx_frame* f,
+                                void* d_scratch, size_t scratch_bytes, int32_t* d_out_cell,
+                                uint8_t* d_out_accept, void* stream) {
+  return fuse_impl(m, f, true, cx, cy, d_scratch, scratch_bytes, d_out_cell, d_out_accept,
+                   stream);
 }
 
 emx_status emx_clear_visibility(emx_map* m, const emx_frame* f, void* d_scratch,

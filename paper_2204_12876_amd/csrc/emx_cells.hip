@@ -44,41 +44,14 @@ __global__ __launch_bounds__(kNTf) void k_fill_prior(FillArgs a) {
 constexpr int kMoveW = 64;  // a move unit is 64 x 4 cells
 constexpr int kMoveH = kNTf / kMoveW;
 
-// dst(ix, iy) <- src(ix + sx, iy + sy), or the prior where that is outside.
+// One thread per cell of a 64 x 4 unit.
 __device__ __forceinline__ void move_body(const Item& it, int64_t unit) {
   const int ux = blocks_of(it.c.nx, 6);
   const int ix = (int)(unit % ux) * kMoveW + (threadIdx.x & (kMoveW - 1));
   const int iy = (int)(unit / ux) * kMoveH + (threadIdx.x / kMoveW);
   if (ix >= it.c.nx || iy >= it.c.ny) return;
-  const Layers& src = it.Lsrc;
-  const Layers& dst = it.L;
-  const int64_t o = (int64_t)iy * it.c.nx + ix;
-  const int jx = ix + it.sx;
-  const int jy = iy + it.sy;
-  if (jx >= 0 && jx < it.c.nx && jy >= 0 && jy < it.c.ny) {
-    const int64_t s = (int64_t)jy * it.c.nx + jx;
-    dst.h[o] = src.h[s];
-    dst.v[o] = src.v[s];
-    dst.t[o] = src.t[s];
-    dst.nx[o] = src.nx[s];
-    dst.ny[o] = src.ny[s];
-    dst.nz[o] = src.nz[s];
-    dst.trav[o] = src.trav[s];
-    dst.valid[o] = src.valid[s];
-    if (dst.ub) dst.ub[o] = src.ub[s];
-  } else {
-    const float qnan = __builtin_nanf("");
-    dst.h[o] = it.c.h_init;
-    dst.v[o] = it.c.v_init;
-    dst.t[o] = 0;
-    dst.nx[o] = qnan;
-    dst.ny[o] = qnan;
-    dst.nz[o] = qnan;
-    dst.trav[o] = qnan;
-    dst.valid[o] = 0;
-    if (dst.ub) dst.ub[o] = INFINITY;
-  }
-  dst.mark[o] = 0;
+  float h, v;
+  move_cell(it, ix, iy, h, v);
 }
 
 // ------------------------------------------------------------ overlap clearance

@@ -126,6 +126,7 @@ struct Item {
   int64_t n;
   int32_t t_now;
   int sx, sy;   // move shift in cells
+  int fuse_move; // fusion also performs the move from Lsrc (shift sx, sy) into L
   uint32_t stages;
   const float* w;  // traversability weights (89)
   int32_t* out_cell;
@@ -180,6 +181,52 @@ __device__ __forceinline__ bool bin_xy(float xm, float ym, const Consts& c, int&
   ix = (int)floorf(fx);
   iy = (int)floorf(fy);
   return true;
+}
+
+// ---------------------------------------------------------------- move
+// Source cell of local cell (ix, iy) under the move by (sx, sy), or -1 where
+// the cell enters the map.
+__device__ __forceinline__ int64_t move_source(const Item& it, int ix, int iy) {
+  const int jx = ix + it.sx;
+  const int jy = iy + it.sy;
+  if (jx < 0 || jx >= it.c.nx || jy < 0 || jy >= it.c.ny) return -1;
+  return (int64_t)jy * it.c.nx + jx;
+}
+
+// dst(ix, iy) <- src(ix + sx, iy + sy), or the prior where that is outside;
+// the mark is cleared.  Returns the cell's height and variance.
+__device__ __forceinline__ void move_cell(const Item& it, int ix, int iy, float& h, float& v) {
+  const Layers& src = it.Lsrc;
+  const Layers& dst = it.L;
+  const int64_t o = (int64_t)iy * it.c.nx + ix;
+  const int64_t s = move_source(it, ix, iy);
+  if (s >= 0) {
+    h = src.h[s];
+    v = src.v[s];
+    dst.h[o] = h;
+    dst.v[o] = v;
+    dst.t[o] = src.t[s];
+    dst.nx[o] = src.nx[s];
+    dst.ny[o] = src.ny[s];
+    dst.nz[o] = src.nz[s];
+    dst.trav[o] = src.trav[s];
+    dst.valid[o] = src.valid[s];
+    if (dst.ub) dst.ub[o] = src.ub[s];
+  } else {
+    const float qnan = __builtin_nanf("");
+    h = it.c.h_init;
+    v = it.c.v_init;
+    dst.h[o] = h;
+    dst.v[o] = v;
+    dst.t[o] = 0;
+    dst.nx[o] = qnan;
+    dst.ny[o] = qnan;
+    dst.nz[o] = qnan;
+    dst.trav[o] = qnan;
+    dst.valid[o] = 0;
+    if (dst.ub) dst.ub[o] = INFINITY;
+  }
+  dst.mark[o] = 0;
 }
 
 // ---------------------------------------------------------------- block scans

@@ -130,7 +130,9 @@ __device__ __forceinline__ void bitonic_sort_regs(KeyT& a, KeyT& b, KeyT* s) {
 }
 
 // ------------------------------------------------------------------ pass 1
-template <typename KeyT>
+// kMove: the fusion also performs the item's move (the prior is read from the
+// source set through the shift).
+template <typename KeyT, bool kMove = false>
 __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
   constexpr KeyT kNoKey = (KeyT)~(KeyT)0;
   __shared__ KeyT s_key[kChunk];
@@ -160,14 +162,18 @@ __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
       int ix = 0, iy = 0;
       if (e.valid && bin_xy(e.xm, e.ym, it.c, ix, iy)) {
         cell = iy * it.c.nx + ix;
-        const float h0 = it.L.h[cell];
-        const float v0 = it.L.v[cell];
+        // the prior: the map's cell, or with a fused move the moved-in cell
+        // of the source set (the prior values where the cell enters)
+        const int64_t sc = kMove ? move_source(it, ix, iy) : cell;
+        const Layers& P = kMove ? it.Lsrc : it.L;
+        const float h0 = sc >= 0 ? P.h[sc] : it.c.h_init;
+        const float v0 = sc >= 0 ? P.v[sc] : it.c.v_init;
         const float d = e.zm - h0;
         acc = (d * d) <= (it.c.k2 * (v0 + e.sp2));
         // wall/edge rule: in a crowded cell that holds an estimate, points
         // below the estimate are ignored (before the gate)
-        if (it.fs.count && e.zm < h0 && it.fs.count[cell] > (uint32_t)it.c.wall &&
-            it.L.valid[cell])
+        if (it.fs.count && e.zm < h0 && it.fs.count[cell] > (uint32_t)it.c.wall && sc >= 0 &&
+            P.valid[sc])
           acc = false;
       }
       if (it.out_cell) it.out_cell[i] = cell;
@@ -344,6 +350,15 @@ __device__ __forceinline__ void tile_body(const Item& it, int t) {
   float acc_w = 0.0f;
   float acc_wz = 0.0f;
   bool hit = false;
+  const int tx = t % it.tiles_x;
+  const int ty = t / it.tiles_x;
+  const int ix = (tx << kTileLog) + (l & (kTile - 1));
+  const int iy = (ty << kTileLog) + (l >> kTileLog);
+  const int64_t cell = (int64_t)iy * it.c.nx + ix;
+  // a fused move: every cell of the tile takes its moved-in values first (the
+  // same thread updates it below, so the update sees them)
+  float h0 = 0.0f, v0 = 0.0f;
+  if (it.fuse_move && ix < it.c.nx && iy < it.c.ny) move_cell(it, ix, iy, h0, v0);
 
   for (int k0 = 0; k0 < B; k0 += kWin) {
     // compact the chunks of this window that touched the tile, in chunk order
@@ -448,13 +463,10 @@ __device__ __forceinline__ void tile_body(const Item& it, int t) {
   if (!hit) return;
 
   // ---- information-form update of the owned cell
-  const int tx = t % it.tiles_x;
-  const int ty = t / it.tiles_x;
-  const int ix = (tx << kTileLog) + (l & (kTile - 1));
-  const int iy = (ty << kTileLog) + (l >> kTileLog);
-  const int64_t cell = (int64_t)iy * it.c.nx + ix;
-  const float h0 = it.L.h[cell];
-  const float v0 = it.L.v[cell];
+  if (!it.fuse_move) {
+    h0 = it.L.h[cell];
+    v0 = it.L.v[cell];
+  }
   const float W = (1.0f / v0) + acc_w;
   const float v1 = 1.0f / W;
   const float h1 = ((h0 / v0) + acc_wz) * v1;
@@ -534,9 +546,9 @@ __global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int64_t n) {
 }
 
 // ---------------------------------------------------------------- launches
-template <typename KeyT>
+template <typename KeyT, bool kMove>
 __global__ __launch_bounds__(kNT1) void k_fuse_chunk(Item it) {
-  chunk_body<KeyT>(it, blockIdx.x);
+  chunk_body<KeyT, kMove>(it, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kNT2) void k_fuse_tile(Item it) { tile_body(it, blockIdx.x); }
@@ -612,10 +624,14 @@ hipError_t launch_fuse(const Item& it, hipStream_t stream) {
     }
     {
       TimedLaunch tl("k_fuse_chunk", stream);
-      if (fuse_needs_key64(it.T))
-        hipLaunchKernelGGL(k_fuse_chunk<uint64_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
-      else
-        hipLaunchKernelGGL(k_fuse_chunk<uint32_t>, dim3(it.B), dim3(kNT1), 0, stream, it);
+      const bool k64 = fuse_needs_key64(it.T);
+      if (it.fuse_move) {
+        if (k64) hipLaunchKernelGGL((k_fuse_chunk<uint64_t, true>), dim3(it.B), dim3(kNT1), 0, stream, it);
+        else hipLaunchKernelGGL((k_fuse_chunk<uint32_t, true>), dim3(it.B), dim3(kNT1), 0, stream, it);
+      } else {
+        if (k64) hipLaunchKernelGGL((k_fuse_chunk<uint64_t, false>), dim3(it.B), dim3(kNT1), 0, stream, it);
+        else hipLaunchKernelGGL((k_fuse_chunk<uint32_t, false>), dim3(it.B), dim3(kNT1), 0, stream, it);
+      }
     }
     if ((err = hipGetLastError()) != hipSuccess) return err;
     {

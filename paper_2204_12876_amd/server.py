@@ -401,8 +401,7 @@ class GpuExecutor:
             x = self.pool[off:off + n]
             y = self.pool[off + n:off + 2 * n]
             z = self.pool[off + 2 * n:off + 3 * n]
-            m.move_map(*r.center)
-            m.fuse_points(x, y, z, r.pose, r.t_ms, scratch=scratch)
+            m.move_fuse_points(*r.center, x, y, z, r.pose, r.t_ms, scratch=scratch)
             m.clear_visibility(x, y, z, r.pose, r.t_ms, scratch=scratch)
             if self.weights is not None:
                 m.normals_traversability(self.weights)
@@ -466,8 +465,7 @@ def run_plain_trace(maps: dict, requests: List[Request], weights: torch.Tensor, 
         stage[:3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
         x, y, z = stage[:n], stage[n:2 * n], stage[2 * n:3 * n]
         r.launch = time.perf_counter() - t0
-        m.move_map(*r.center)
-        m.fuse_points(x, y, z, r.pose, r.t_ms, scratch=scratch)
+        m.move_fuse_points(*r.center, x, y, z, r.pose, r.t_ms, scratch=scratch)
         m.clear_visibility(x, y, z, r.pose, r.t_ms, scratch=scratch)
         if weights is not None:
             m.normals_traversability(weights)
