@@ -10,7 +10,11 @@
  *   - inverse-variance (Kalman) fusion of height and variance (Sec. II-C, Eq. 1, 2);
  *   - visibility ray clearing (Sec. II-E, Eq. 3, 4);
  *   - 3x3 surface normals (Sec. II-A);
- *   - a small convolutional traversability filter (Sec. II-G).
+ *   - a small convolutional traversability filter (Sec. II-G);
+ * and the method's further per-frame steps: time variance and the wall/edge
+ * rule in the fusion (Sec. II-C), height drift compensation (Sec. II-D),
+ * overlap clearance (Sec. II-F), the upper bound layer (Sec. II-H), and the
+ * locomotion filters: minimum-filter inpainting and smoothing (Sec. II-I).
  *
  * Conventions shared by every call:
  *   - Pointers named d_* are device (HBM) pointers.  All other pointers are host
@@ -28,10 +32,12 @@
  *   - Kernel faults surface at the caller's next stream synchronisation.
  *   - A map must not be used from two streams at once.  Distinct maps are
  *     independent.
- *   - Floating point: every result is computed in IEEE float32.  Decisions use a
- *     fixed operation order, round-to-nearest and no fused multiply-add.  Those
+ *   - Floating point: every result is computed in IEEE float32 (drift
+ *     compensation sums its errors in float64).  Decisions use a fixed
+ *     operation order, round-to-nearest and no fused multiply-add.  Those
  *     decisions are the range check, cell index, gate, ray samples and clearing
- *     predicate; the order is stated below.
+ *     predicate; the order is stated below.  Every sum has a fixed order, so
+ *     results are the same from run to run.
  *
  * Map geometry (the paper is silent on it; these are this library's conventions):
  *   - Cells are half-open squares of side r.  Global cell (gx, gy) covers
@@ -119,8 +125,9 @@ const char* emx_last_error(void);
 emx_status emx_params_check(const emx_params* params);
 
 /* Device bytes of one map's state: two buffer sets of layers (move_map writes
- * the shifted map into the other set), 16 bytes of clearing scratch per cell
- * and a small control block.  Returns 0 for invalid parameters. */
+ * the shifted map into the other set; with upper_bound = 1 each set also holds
+ * the upper bound layer), 16 bytes of clearing scratch per cell and a small
+ * control block.  Returns 0 for invalid parameters. */
 size_t emx_state_bytes(const emx_params* params);
 
 /* Device scratch bytes emx_fuse_points and emx_clear_visibility need for
