@@ -351,7 +351,10 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
     const bool moved = (st & EMX_STAGE_MOVE) && (it.sx != 0 || it.sy != 0);
     const bool fuse = (st & EMX_STAGE_FUSE) && it.n > 0;
     const bool clear = (st & EMX_STAGE_CLEAR) != 0;
-    tab->off[kBMove][i + 1] = tab->off[kBMove][i] + (moved ? move_units(it.c.nx, it.c.ny) : 0);
+    // a move followed by a fusion with points runs inside the fusion's passes
+    it.fuse_move = moved && fuse ? 1 : 0;
+    tab->off[kBMove][i + 1] =
+        tab->off[kBMove][i] + (moved && !fuse ? move_units(it.c.nx, it.c.ny) : 0);
     tab->off[kBChunk][i + 1] = tab->off[kBChunk][i] + (fuse ? it.B : 0);
     tab->off[kBTile][i + 1] = tab->off[kBTile][i] + (fuse ? it.T : 0);
     tab->off[kBSetup][i + 1] =

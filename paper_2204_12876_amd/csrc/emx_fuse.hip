@@ -558,7 +558,8 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk_b(const Batch* bt) {
   const int64_t total = bt->off[kBChunk][bt->n];
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int i = batch_item(bt, kBChunk, w);
-    chunk_body<KeyT>(bt->items[i], w - bt->off[kBChunk][i]);
+    if (bt->items[i].fuse_move) chunk_body<KeyT, true>(bt->items[i], w - bt->off[kBChunk][i]);
+    else chunk_body<KeyT, false>(bt->items[i], w - bt->off[kBChunk][i]);
     __syncthreads();
   }
 }
