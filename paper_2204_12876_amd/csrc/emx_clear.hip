@@ -212,6 +212,7 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
   for (int k = ka; k <= kb; k += kUnroll) {
     int cell[kUnroll];
     float qz[kUnroll];
+    float m[kUnroll];
     bool cand[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -227,9 +228,13 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
       const int ix = (int)(qx * inv_r);
       const int iy = (int)(qy * inv_r);
       cell[u] = iy * nx + ix;
-      const float m = kRec ? cm[(iy >> bl) * bx + (ix >> bl)] : INFINITY;
-      cand[u] = (k + u <= kb) && (qz[u] < m) && cell[u] != end_cell;
+      // every slot's block maximum is loaded before any is used, so the
+      // loads of the kUnroll samples are in flight together
+      m[u] = kRec ? cm[(uint32_t)((iy >> bl) * bx + (ix >> bl))] : INFINITY;
     }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      cand[u] = (k + u <= kb) & (qz[u] < m[u]) & (cell[u] != end_cell);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (!cand[u]) continue;
