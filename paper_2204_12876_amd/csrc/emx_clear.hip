@@ -180,8 +180,7 @@ __device__ __forceinline__ void test_cell(const Item& it, const Ray& r, int c, f
 // bound layer, a cell without an estimate holds NaN in place of the height
 // (no other record does), which sends the sample to its bound.
 __device__ __forceinline__ void test_cell_rec(const Item& it, const Ray& r, int c, float qz,
-                                              float an2dd) {
-  const float4 k = it.L.clr[c];
+                                              float an2dd, const float4 k) {
   if (isnan(k.x)) {
     atomic_min_f32(it.L.ub + c, qz);
     return;
@@ -235,10 +234,17 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
       cand[u] = (k + u <= kb) & (qz[u] < m[u]) & (cell[u] != end_cell);
+    // the candidates' records, all requested before any is tested
+    float4 rec[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      rec[u] = make_float4(-INFINITY, 0.0f, 0.0f, 0.0f);
+      if (kRec && cand[u]) rec[u] = it.L.clr[cell[u]];
+    }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (!cand[u]) continue;
-      if (kRec) test_cell_rec(it, r, cell[u], qz[u], an2dd);
+      if (kRec) test_cell_rec(it, r, cell[u], qz[u], an2dd, rec[u]);
       else test_cell(it, r, cell[u], qz[u], an2dd);
     }
   }
