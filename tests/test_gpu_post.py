@@ -262,3 +262,35 @@ def test_filters_reject_bad_arguments(dev):
     with pytest.raises(EmxError):
         m.overlap_clear((0, 0, 0), -1.0, 0.5)
     m.close()
+
+
+def test_features_are_deterministic(dev):
+    """Every feature gives the same bits on a second run of the same inputs
+    (the upper bound and inpainting use integer atomics, drift a fixed-order
+    float64 sum)."""
+    from paper_2204_12876_amd import smooth
+    _say("feature determinism")
+    d = synth.cfg0(n_frames=2)
+    params = dict(d["params"], upper_bound=1, wall_min_count=3, time_variance=0.001)
+    outs = []
+    for _ in range(2):
+        m = _map(params, dev)
+        w = torch.from_numpy(synth.trav_weights()).to(dev)
+        res = []
+        for k, f in enumerate(d["frames"]):
+            xyz = _dev(dev, *f.numpy())
+            mean, cnt = m.compensate_drift(*xyz, f.pose, f.t_ms, 0.0)
+            m.move_fuse_points(0.04 * k, -0.04 * k, *xyz, f.pose, f.t_ms)
+            m.clear_visibility(*xyz, f.pose, f.t_ms + 600)
+            m.normals_traversability(w)
+            m.overlap_clear((0.0, 0.0, 0.2), 0.8, 0.3)
+            filled = m.inpaint_min()
+            res += [mean.cpu(), cnt.cpu(), m.export_state().cpu(), m.upper_bound().cpu().clone(),
+                    filled.cpu(), smooth(filled, "gaussian", 5, 1.0).cpu(),
+                    smooth(filled, "median", 3).cpu()]
+        torch.cuda.synchronize()
+        outs.append(res)
+        m.close()
+    for a, b in zip(*outs):
+        assert torch.equal(a.view(torch.uint8) if a.dtype != torch.uint8 else a,
+                           b.view(torch.uint8) if b.dtype != torch.uint8 else b)
