@@ -279,7 +279,8 @@ def plain_single_robot(args, dev):
         "config": {"workload": "plain single robot: 400x400 map at 0.04 m, 300k-point frames "
                                "(dome LiDAR + 4 depth frustums), full pipeline per frame",
                    "map_cells": C, "points_per_frame": args.points, "frames": K,
-                   "mode": "per-frame plain calls, frames submitted back to back"},
+                   "mode": "per-frame plain calls (move_fuse_points, clear_visibility, "
+                           "normals_traversability), frames submitted back to back"},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3),
                        "max": float(lat.max() * 1e3),
