@@ -60,3 +60,50 @@ def test_init_map_argument_checks_need_no_gpu(L):
                           ctypes.byref(h)) == _emx.EMX_EINVAL          # misaligned
     assert L.emx_fuse_points(None, None, None, 0, None, None, None) == _emx.EMX_EINVAL
     assert L.emx_layer(None, 0, ctypes.byref(h)) == _emx.EMX_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [
+    ("time_variance", -1e-3), ("time_variance", float("nan")), ("wall_min_count", -1),
+    ("upper_bound", 2), ("upper_bound", -1),
+])
+def test_bad_extension_params_rejected(L, field, value):
+    d = dict(nx=64, ny=64, resolution=0.04)
+    d[field] = value
+    p = _emx.make_params(d)
+    assert _emx.params_check(p) == _emx.EMX_EINVAL
+    assert _emx.state_bytes(p) == 0 and _emx.inpaint_scratch_bytes(p) == 0
+
+
+def test_extension_sizes(L):
+    C = 64 * 48
+    base = _emx.make_params(dict(nx=64, ny=48, resolution=0.04))
+    ub = _emx.make_params(dict(nx=64, ny=48, resolution=0.04, upper_bound=1))
+    # the bound layer: one float per cell in each of the two buffer sets
+    assert _emx.state_bytes(ub) - _emx.state_bytes(base) >= 2 * 4 * C
+    wall = _emx.make_params(dict(nx=64, ny=48, resolution=0.04, wall_min_count=3))
+    # fusion's part grows by the per-cell counts (the buffer is the larger of
+    # fusion's and clearing's needs)
+    assert _emx.scratch_bytes(wall, 5000) >= _emx.scratch_bytes(base, 5000)
+    assert _emx.inpaint_scratch_bytes(base) >= 8 * C
+    assert _emx.drift_scratch_bytes(-1) == 0
+    assert _emx.drift_scratch_bytes(0) > 0
+    assert _emx.drift_scratch_bytes(300000) >= 293 * 12
+
+
+def test_next_row_calls_check_arguments_without_a_gpu(L):
+    none = ctypes.c_void_p()
+    assert L.emx_overlap_clear(None, 0.0, 0.0, 0.0, 1.0, 0.5, None, None) == _emx.EMX_EINVAL
+    assert L.emx_inpaint_min(None, None, None, 0, None) == _emx.EMX_EINVAL
+    assert L.emx_compensate_drift(None, None, 0.0, None, 0, None, None, None) == _emx.EMX_EINVAL
+    assert L.emx_move_fuse_points(None, 0.0, 0.0, None, None, 0, None, None, None) \
+        == _emx.EMX_EINVAL
+    assert L.emx_normals_traversability(None, None, None) == _emx.EMX_EINVAL
+    # smoothing validates every argument on the host
+    d_in, d_out = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 24)
+    bad = [(None, d_out, 8, 8, 0, 3, 0.0), (d_in, d_out, 8, 8, 3, 3, 0.0),
+           (d_in, d_out, 8, 8, 0, 4, 0.0), (d_in, d_out, 8, 8, 2, 7, 0.0),
+           (d_in, d_out, 8, 8, 1, 3, 0.0), (d_in, d_out, 8, 8, 0, 33, 0.0),
+           (d_in, d_out, 4, 8, 0, 9, 0.0), (d_in, d_in, 8, 8, 0, 3, 0.0),
+           (d_in, ctypes.c_void_p((1 << 20) + 64), 8, 8, 0, 3, 0.0)]
+    for args in bad:
+        assert _emx.lib().emx_smooth(*args, none) == _emx.EMX_EINVAL, args
