@@ -166,8 +166,10 @@ class ElevationMap:
               or not out.is_contiguous() or out.device != self.device):
             raise ValueError("out must be a contiguous float32 [ny, nx] tensor on the device")
         need = _emx.inpaint_scratch_bytes(self.p)
-        s = aligned_empty(need, self.device)
-        _emx.inpaint_min(self.handle, out.data_ptr(), s.data_ptr(), need, _stream(self.device))
+        if getattr(self, "_inpaint_scratch", None) is None:
+            self._inpaint_scratch = aligned_empty(need, self.device)
+        _emx.inpaint_min(self.handle, out.data_ptr(), self._inpaint_scratch.data_ptr(), need,
+                         _stream(self.device))
         return out
 
     def upper_bound(self) -> torch.Tensor:
