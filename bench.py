@@ -100,7 +100,7 @@ def kernel_alg_bytes(name: str, n: int, C: int, touched: float, updated: float,
         cell changes), also every layer read and written once (2 x 29 B);
       clearing: setup reads the points and h, t_upd, valid per cell for the
         block maxima (9 B); the march reads each cell's h, v, t_upd, valid and
-        normal once (25 B); apply reads the marks and writes the output mask;
+        normal once (25 B) and resets the removed cells in place;
       normals: h, valid in (5 B), three components out (12 B);
       traversability: h, valid in, one float out (9 B);
       normals and traversability in one pass: h, valid in, four floats out
@@ -111,7 +111,6 @@ def kernel_alg_bytes(name: str, n: int, C: int, touched: float, updated: float,
         "k_fuse_tile": 21 * updated + 58 * C * moved,
         "k_clear_setup": 12 * n + 9 * C,
         "k_clear_march": 25 * C,
-        "k_clear_apply": 2 * C,
         "k_normals": 17 * C,
         "k_trav": 9 * C,
         "k_normals_trav": 21 * C,
@@ -121,7 +120,7 @@ def kernel_alg_bytes(name: str, n: int, C: int, touched: float, updated: float,
 
 KERNEL_SOURCE = {"k_fuse_chunk": "emx_fuse.hip", "k_fuse_tile": "emx_fuse.hip",
                  "k_clear_setup": "emx_clear.hip", "k_clear_march": "emx_clear.hip",
-                 "k_clear_apply": "emx_clear.hip", "k_move": "emx_cells.hip",
+                 "k_move": "emx_cells.hip",
                  "k_normals": "emx_cells.hip", "k_trav": "emx_cells.hip",
                  "k_normals_trav": "emx_cells.hip",
                  "k_fill_prior": "emx_cells.hip"}

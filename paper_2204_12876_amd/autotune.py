@@ -28,7 +28,6 @@ SPACE = {
     "grid_setup": [512, 1024, 2048, 4096, 8192, 65536],
     "grid_march": [1024, 2048, 4096, 8192, 16384],
     "grid_move": [256, 512, 1024, 2048, 8192, 65536],
-    "grid_apply": [256, 512, 1024, 2048, 8192, 65536],
     "grid_cells": [256, 512, 1024, 2048, 8192, 65536],
     "seg": [16, 32, 64, 128],
 }

@@ -257,6 +257,7 @@ emx_status emx_init_map(const emx_params* params, double cx, double cy, int64_t 
   m->sets[0].clr = clr;
   m->sets[1].clr = clr;
   m->cur = 0;
+  m->ctr_sel = 0;
   m->ctl = (uint32_t*)(m->state + 2 * m->set_bytes + clr_bytes(*params));
   m->march_grid = persistent_grid(kMarchPerCU);
   hipError_t e = launch_fill_prior(m->c, m->sets[0], m->ctl, kCtlWords, (hipStream_t)stream);
@@ -385,12 +386,15 @@ emx_status emx_clear_visibility(emx_map* m, const emx_frame* f, void* d_scratch,
     clear_scratch_layout(f->n, kDefaultSeg, (char*)d_scratch, &it.cq);
   }
   it.cq.ray_item = nullptr;
-  it.cq.counter = m->ctl;
+  it.cq.counter = m->ctl + m->ctr_sel * kCtrWords;
+  it.cq.counter_next = m->ctl + (1 - m->ctr_sel) * kCtrWords;
   it.cq.seg = kDefaultSeg;
   it.out_cleared = d_out_cleared;
   it.stages = kStageClear;
-  hipError_t e = launch_clear(it, m->march_grid, (hipStream_t)stream);
+  bool ran = false;
+  hipError_t e = launch_clear(it, m->march_grid, (hipStream_t)stream, &ran);
   if (e != hipSuccess) return hip_fail(e, "clear_visibility");
+  if (ran) m->ctr_sel = 1 - m->ctr_sel;
   return EMX_OK;
 }
 

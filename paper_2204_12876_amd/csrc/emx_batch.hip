@@ -38,7 +38,6 @@ struct Tuning {
   int grid_tile = 512;
   int grid_setup = 2048;
   int grid_march = 2048;
-  int grid_apply = 1024;
   int grid_cells = 1024;
   int seg = kDefaultSeg;
   int graph = 1;
@@ -64,11 +63,11 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct GraphKey {
   void* scratch;
   int key64;
-  int grid[7];
+  int grid[6];
 
   bool operator==(const GraphKey& o) const {
     if (scratch != o.scratch || key64 != o.key64) return false;
-    for (int i = 0; i < 7; ++i)
+    for (int i = 0; i < 6; ++i)
       if (grid[i] != o.grid[i]) return false;
     return true;
   }
@@ -147,12 +146,13 @@ size_t batch_layout(const emx_batch_item* items, int32_t n, int seg, char* base,
     if (tab) tab->items[i].ray_base = rays;
     if (items[i].stages & EMX_STAGE_CLEAR) rays += np;
   }
-  ClearQueue cq;
+  ClearQueue cq = {};
   const size_t c = clear_scratch_layout(rays, seg, base ? base + off : nullptr, &cq);
   if (tab && base)
     for (int32_t i = 0; i < n; ++i) {
       tab->items[i].cq = cq;
       tab->items[i].cq.counter = (uint32_t*)(base + kCounterOffset);
+      tab->items[i].cq.counter_next = nullptr;  // zeroed by the batch's first launch
     }
   return off + c;
 }
@@ -174,14 +174,13 @@ emx_status emx_batch_create(const char* tuning_json, emx_batch** out) {
     json_int(tuning_json, "grid_tile", &b->tune.grid_tile);
     json_int(tuning_json, "grid_setup", &b->tune.grid_setup);
     json_int(tuning_json, "grid_march", &b->tune.grid_march);
-    json_int(tuning_json, "grid_apply", &b->tune.grid_apply);
     json_int(tuning_json, "grid_cells", &b->tune.grid_cells);
     json_int(tuning_json, "seg", &b->tune.seg);
     json_int(tuning_json, "graph", &b->tune.graph);
   }
   const Tuning& t = b->tune;
   const int grids[] = {t.grid_move, t.grid_chunk, t.grid_tile, t.grid_setup,
-                       t.grid_march, t.grid_apply, t.grid_cells};
+                       t.grid_march, t.grid_cells};
   for (int g : grids)
     if (g < 1 || g > 65536) {
       delete b;
@@ -236,10 +235,10 @@ emx_status emx_batch_tuning(const emx_batch* b, char* buf, size_t len) {
   const Tuning& t = b->tune;
   const int w = snprintf(buf, len,
                          "{\"grid_move\": %d, \"grid_chunk\": %d, \"grid_tile\": %d, "
-                         "\"grid_setup\": %d, \"grid_march\": %d, \"grid_apply\": %d, "
+                         "\"grid_setup\": %d, \"grid_march\": %d, "
                          "\"grid_cells\": %d, \"seg\": %d, \"graph\": %d}",
                          t.grid_move, t.grid_chunk, t.grid_tile, t.grid_setup, t.grid_march,
-                         t.grid_apply, t.grid_cells, t.seg, t.graph);
+                         t.grid_cells, t.seg, t.graph);
   if (w < 0 || (size_t)w >= len) return fail(EMX_ENOMEM, "buffer too small");
   return EMX_OK;
 }
@@ -347,7 +346,6 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
     it.cq.seg = b->tune.seg;
     if (it.stages & EMX_STAGE_CLEAR) clear_rays += it.n;
     const uint32_t st = it.stages;
-    const int64_t C = (int64_t)it.c.nx * it.c.ny;
     const bool moved = (st & EMX_STAGE_MOVE) && (it.sx != 0 || it.sy != 0);
     const bool fuse = (st & EMX_STAGE_FUSE) && it.n > 0;
     const bool clear = (st & EMX_STAGE_CLEAR) != 0;
@@ -358,8 +356,8 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
     tab->off[kBChunk][i + 1] = tab->off[kBChunk][i] + (fuse ? it.B : 0);
     tab->off[kBTile][i + 1] = tab->off[kBTile][i] + (fuse ? it.T : 0);
     tab->off[kBSetup][i + 1] =
-        tab->off[kBSetup][i] + (clear && it.n > 0 ? clear_setup_units(it.n, it.nprep) : 0);
-    tab->off[kBApply][i + 1] = tab->off[kBApply][i] + (clear ? clear_apply_units(C) : 0);
+        tab->off[kBSetup][i] +
+        (clear ? clear_setup_units(it.n, it.nprep, it.out_cleared != nullptr) : 0);
     tab->off[kBCells][i + 1] =
         tab->off[kBCells][i] +
         ((st & (EMX_STAGE_NORMALS | EMX_STAGE_TRAV)) ? cells_units(it.c.nx, it.c.ny) : 0);
@@ -379,8 +377,7 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
   key.grid[2] = cap(t.grid_tile, tab->off[kBTile][n]);
   key.grid[3] = cap(t.grid_setup, tab->off[kBSetup][n]);
   key.grid[4] = cap(t.grid_march, (2 * clear_rays + 255) / 256);
-  key.grid[5] = cap(t.grid_apply, tab->off[kBApply][n]);
-  key.grid[6] = cap(t.grid_cells, tab->off[kBCells][n]);
+  key.grid[5] = cap(t.grid_cells, tab->off[kBCells][n]);
 
   // ---- enqueue: the table upload, then a cached graph or the same launches
   hipStream_t st = (hipStream_t)stream;
@@ -391,8 +388,8 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
     hipError_t r = launch_move_batch(d_tab, key.grid[0], q);
     if (r == hipSuccess) r = launch_fuse_batch(d_tab, key64, key.grid[1], key.grid[2], q);
     if (r == hipSuccess)
-      r = launch_clear_batch(d_tab, key.grid[3], key.grid[4], key.grid[5], q);
-    if (r == hipSuccess) r = launch_cells_batch(d_tab, key.grid[6], q);
+      r = launch_clear_batch(d_tab, key.grid[3], key.grid[4], q);
+    if (r == hipSuccess) r = launch_cells_batch(d_tab, key.grid[5], q);
     return r;
   };
   if (t.graph) {

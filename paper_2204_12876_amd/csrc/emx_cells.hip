@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kNTf) void k_normals_trav(Item it) {
 // The batch's first launch: also zeroes the clearing queue counters, which
 // the later setup launch increments.
 __global__ __launch_bounds__(kNTf) void k_move_b(const Batch* bt) {
-  if (blockIdx.x == 0 && threadIdx.x < kSubQ)
+  if (blockIdx.x == 0 && threadIdx.x <= kSubQ)  // the sub-queues' and the overflow counter
     bt->items[0].cq.counter[threadIdx.x * kCtrStride] = 0u;
   const int64_t total = bt->off[kBMove][bt->n];
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {

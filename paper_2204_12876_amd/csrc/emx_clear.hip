@@ -21,19 +21,24 @@
 //       - the range is cut into segments of `seg` samples.  Each workgroup
 //         reserves its segments with one integer atomic, in one of kSubQ
 //         sub-queues, so no counter is contended.  A ray that would overflow
-//         its bounded sub-queue is marched in place instead.
+//         its bounded sub-queue goes whole to an overflow list (one entry per
+//         ray at most, so the list cannot overflow).
+//   - Block 0 zeroes the counter set of the next plain call, and the block
+//     role zeroes the caller's removed-cell mask.
 // march: a persistent grid drains the queue, one segment per thread.
 //   - A sample at height q.z >= the block maximum passes above every cell that
 //     could be removed, since removal needs h > q.z.  It is skipped without
 //     reading the cell: exact pruning.
 //   - Other samples read their cell's clearing record (and the normal's z
 //     only if the height test passes).
-//   - Marks are idempotent byte stores, so the queue order never shows in the
-//     result.
-//   - The state is only read, so every ray sees the state as it was when the
-//     call started.
-// apply: resets marked cells to the prior, reports and clears the marks, and
-// rewinds the queue counters for the next call.
+//   - A sample that removes its cell resets the cell to the prior on the spot
+//     (and flags it in the caller's mask).  The march reads only the setup's
+//     records and the normals, never the heights, variances or validity it
+//     resets, so every ray still sees the state as it was when the call
+//     started.  Resets are idempotent stores of the same values, so the queue
+//     order never shows in the result.
+//   - The overflow list's rays are marched after the queue, whole.
+// There is no separate pass to apply the removals.
 //
 // Upper bound layer (Sec. II-H), on maps that keep one: a sample in a cell
 // without an estimate lowers the cell's bound to the sample height, by an
@@ -151,32 +156,18 @@ __device__ __forceinline__ bool clearable(const Item& it, int64_t c) {
          !isnan(it.L.nz[c]);
 }
 
-// The full removal test of sample q (height qz) in cell c, from the layers.
-__device__ __forceinline__ void test_cell(const Item& it, const Ray& r, int c, float qz,
-                                          float an2dd) {
-  // one round trip: every field the test may need
-  const uint8_t vc = it.L.valid[c];
-  const int32_t tc = it.L.t[c];
-  const float hc = it.L.h[c];
-  const float varc = it.L.v[c];
-  const float nxc = it.L.nx[c];
-  const float nyc = it.L.ny[c];
-  const float nzc = it.L.nz[c];
-  const float hd = hc - qz;
-  if (!vc) {  // no estimate: the sample bounds the ground from above
-    if (it.L.ub) atomic_min_f32(it.L.ub + c, qz);
-    return;
-  }
-  if (!(((int64_t)it.t_now - (int64_t)tc) > (int64_t)it.c.tau) || isnan(nzc)) return;
-  if (!(hd > 0.0f) || !((hd * hd) > varc)) return;
-  const float dot = (r.dx * nxc + r.dy * nyc) + r.dz * nzc;
-  if ((dot * dot) > an2dd) it.L.mark[c] = 1;
+// Removal of cell c: back to the prior, invalid; flagged in the caller's mask.
+__device__ __forceinline__ void clear_cell(const Item& it, int c) {
+  it.L.h[c] = it.c.h_init;
+  it.L.v[c] = it.c.v_init;
+  it.L.valid[c] = 0;
+  if (it.out_cleared) it.out_cleared[c] = 1;
 }
 
-// The same test from the cell's clearing record, written by the setup: one
-// 16-byte load instead of seven, and the normal's z only when the height test
-// passes.  A cell no ray may clear holds -inf, which fails hd > 0 for every
-// finite sample height, so the decision is the same.  On maps with an upper
+// The removal test of sample q (height qz) in cell c, from the cell's
+// clearing record, written by the setup: one 16-byte load instead of seven,
+// and the normal's z only when the height test passes.  A cell no ray may
+// clear holds -inf, which fails hd > 0 for every finite sample height.  On maps with an upper
 // bound layer, a cell without an estimate holds NaN in place of the height
 // (no other record does), which sends the sample to its bound.
 __device__ __forceinline__ void test_cell_rec(const Item& it, const Ray& r, int c, float qz,
@@ -188,19 +179,15 @@ __device__ __forceinline__ void test_cell_rec(const Item& it, const Ray& r, int 
   const float hd = k.x - qz;
   if (!(hd > 0.0f) || !((hd * hd) > k.y)) return;
   const float dot = (r.dx * k.z + r.dy * k.w) + r.dz * it.L.nz[c];
-  if ((dot * dot) > an2dd) it.L.mark[c] = 1;
+  if ((dot * dot) > an2dd) clear_cell(it, c);
 }
 
 constexpr int kUnroll = 8;
 
-// Test samples k in [ka, kb] of ray r against the map.  With kRec, cm holds
-// the block maxima and the cells' clearing records are read; without, every
-// sample is tested against the layers (same result, no pruning), for use
-// while the setup is still writing maxima and records.
-// kUnroll samples at a time: their cells and block maxima are found without
-// branches, so the block-maximum loads issue together.  The march is bound by
-// instruction issue, so the per-sample work is kept to the sample itself.
-template <bool kRec>
+// Test samples k in [ka, kb] of ray r against the map; cm holds the block
+// maxima.  kUnroll samples at a time: their cells and block maxima are found
+// without branches, so the block-maximum loads issue together.  The per-sample
+// work is kept to the sample itself.
 __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka, int kb,
                                             int end_cell, const float* cm) {
   const float an2dd = it.c.an2 * ((r.dx * r.dx + r.dy * r.dy) + r.dz * r.dz);
@@ -229,7 +216,7 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
       cell[u] = iy * nx + ix;
       // every slot's block maximum is loaded before any is used, so the
       // loads of the kUnroll samples are in flight together
-      m[u] = kRec ? cm[(uint32_t)((iy >> bl) * bx + (ix >> bl))] : INFINITY;
+      m[u] = cm[(uint32_t)((iy >> bl) * bx + (ix >> bl))];
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
@@ -239,13 +226,12 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       rec[u] = make_float4(-INFINITY, 0.0f, 0.0f, 0.0f);
-      if (kRec && cand[u]) rec[u] = it.L.clr[cell[u]];
+      if (cand[u]) rec[u] = it.L.clr[cell[u]];
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (!cand[u]) continue;
-      if (kRec) test_cell_rec(it, r, cell[u], qz[u], an2dd, rec[u]);
-      else test_cell(it, r, cell[u], qz[u], an2dd);
+      test_cell_rec(it, r, cell[u], qz[u], an2dd, rec[u]);
     }
   }
 }
@@ -253,6 +239,9 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
 // Setup work unit `unit` of item `it`; `qsel` picks the sub-queue.
 __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
   const int lane = threadIdx.x & 63;
+  // the next plain call's queue counters start from zero
+  if (unit == 0 && it.cq.counter_next && threadIdx.x <= kSubQ)
+    it.cq.counter_next[threadIdx.x * kCtrStride] = 0u;
   if (unit < it.nprep) {
     // ---- block role: each wave takes it.bpw (1 or 4) blocks of 8 x 8 cells,
     // one cell of each per lane, so their loads are in flight together
@@ -268,6 +257,7 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
       const int iy = ((b / it.bx) << it.bl) + (lane >> it.bl);
       inside[j] = j < it.bpw && b < it.nb && ix < it.c.nx && iy < it.c.ny;
       c[j] = inside[j] ? (int64_t)iy * it.c.nx + ix : 0;
+      if (inside[j] && it.out_cleared) it.out_cleared[c[j]] = 0;  // the march sets removals
       ok[j] = inside[j] && clearable(it, c[j]);
       h[j] = inside[j] ? it.L.h[c[j]] : 0.0f;
       v[j] = ok[j] ? h[j] : -INFINITY;
@@ -351,10 +341,15 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
       q[first + sgi] = make_uint2((uint32_t)gray, ((uint32_t)ka << 8) | (uint32_t)cnt);
     }
   } else {
-    // sub-queue full: leave empty entries in any reserved slots and march
-    // here, unpruned (the block maxima are still being written by this launch)
+    // sub-queue full: leave empty entries in any reserved slots; the whole
+    // ray goes to the overflow list, marched after the queue
     for (int64_t e = first; e < first + nseg && e < cq.qcap; ++e) q[e] = make_uint2(0u, 0u);
-    march_range<false>(it, r, k0, k1, end_cell, nullptr);
+    const int64_t gray = it.ray_base + i;
+    cq.ray[gray] = make_float4(r.dx, r.dy, r.dz, r.Kf);
+    cq.ray_end[gray] = end_cell;
+    if (cq.ray_item) cq.ray_item[gray] = it.index;
+    const uint32_t o = atomicAdd(cq.counter + kOverCtr, 1u);
+    cq.over[o] = make_uint4((uint32_t)gray, (uint32_t)k0, (uint32_t)k1, 0u);
   }
 }
 
@@ -385,12 +380,10 @@ __device__ __forceinline__ uint2 queue_entry(const ClearQueue& cq, const int64_t
   return cq.queue[(int64_t)lo * cq.qcap + (g - s_qoff[lo])];
 }
 
-__device__ __forceinline__ void march_entry(const Item& it, const ClearQueue& cq, uint2 e,
-                                            const float* cm) {
-  const int cnt = (int)(e.y & 255u);
-  if (cnt == 0) return;
-  const int ka = (int)(e.y >> 8);
-  const float4 d = cq.ray[e.x];
+// Samples [ka, kb] of queued ray g.
+__device__ __forceinline__ void march_ray(const Item& it, const ClearQueue& cq, uint32_t g,
+                                          int ka, int kb, const float* cm) {
+  const float4 d = cq.ray[g];
   Ray r;
   r.ox = it.P.t[0];
   r.oy = it.P.t[1];
@@ -400,50 +393,15 @@ __device__ __forceinline__ void march_entry(const Item& it, const ClearQueue& cq
   r.dz = d.z;
   r.Kf = d.w;
   r.rK = 1.0 / (double)d.w;
-  march_range<true>(it, r, ka, ka + cnt - 1, cq.ray_end[e.x], cm);
+  march_range(it, r, ka, kb, cq.ray_end[g], cm);
 }
 
-// Apply: 16 cells per thread, one 16-byte load of marks; a cell is reset
-// only where its mark is set (rare).
-constexpr int kApplyPer = 16;
-constexpr int kApplyCells = kNTc * kApplyPer;
-
-__device__ __forceinline__ void apply_cell(const Item& it, int64_t i, uint8_t m) {
-  if (m) {
-    it.L.h[i] = it.c.h_init;
-    it.L.v[i] = it.c.v_init;
-    it.L.valid[i] = 0;
-    it.L.mark[i] = 0;
-  }
-}
-
-__device__ __forceinline__ void apply_body(const Item& it, int64_t unit) {
-  if (unit == 0 && threadIdx.x < kSubQ) it.cq.counter[threadIdx.x * kCtrStride] = 0u;
-  const int64_t C = (int64_t)it.c.nx * it.c.ny;
-  const int64_t i0 = unit * kApplyCells + (int64_t)threadIdx.x * kApplyPer;
-  if (i0 >= C) return;
-  uint8_t* out = it.out_cleared;
-  if (i0 + kApplyPer <= C) {
-    // the mark layer is 256-byte aligned and i0 a multiple of 16
-    const uint4 q = *reinterpret_cast<const uint4*>(it.L.mark + i0);
-    if (out) {
-      if (((uintptr_t)(out + i0) & 15u) == 0) {
-        *reinterpret_cast<uint4*>(out + i0) = q;
-      } else {
-        for (int j = 0; j < kApplyPer; ++j) out[i0 + j] = it.L.mark[i0 + j];
-      }
-    }
-    if ((q.x | q.y | q.z | q.w) == 0u) return;
-    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-    for (int j = 0; j < kApplyPer; ++j) apply_cell(it, i0 + j, (uint8_t)(w[j >> 2] >> (8 * (j & 3))));
-    return;
-  }
-  for (int64_t i = i0; i < C; ++i) {  // the ragged end of the map
-    const uint8_t m = it.L.mark[i];
-    if (out) out[i] = m;
-    apply_cell(it, i, m);
-  }
+__device__ __forceinline__ void march_entry(const Item& it, const ClearQueue& cq, uint2 e,
+                                            const float* cm) {
+  const int cnt = (int)(e.y & 255u);
+  if (cnt == 0) return;
+  const int ka = (int)(e.y >> 8);
+  march_ray(it, cq, e.x, ka, ka + cnt - 1, cm);
 }
 
 // ---------------------------------------------------------------- launches
@@ -461,9 +419,15 @@ __global__ __launch_bounds__(kNTc) void k_clear_march(Item it) {
   for (int64_t g = (int64_t)blockIdx.x * kNTc + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * kNTc)
     march_entry(it, it.cq, queue_entry(it.cq, s_qoff, g), it.L.cmax);
+  // then the rays that overflowed their sub-queue, whole
+  const uint32_t nover = it.cq.counter[kOverCtr];
+  for (int64_t g = (int64_t)blockIdx.x * kNTc + threadIdx.x; g < nover;
+       g += (int64_t)gridDim.x * kNTc) {
+    const uint4 o = it.cq.over[g];
+    march_ray(it, it.cq, o.x, (int)o.y, (int)o.z, it.L.cmax);
+  }
 }
 
-__global__ __launch_bounds__(kNTc) void k_clear_apply(Item it) { apply_body(it, blockIdx.x); }
 
 __global__ __launch_bounds__(kNTc) void k_clear_setup_b(const Batch* bt) {
   const int64_t total = bt->off[kBSetup][bt->n];
@@ -489,13 +453,12 @@ __global__ __launch_bounds__(kNTc) void k_clear_march_b(const Batch* bt) {
     const Item& it = bt->items[cq.ray_item[e.x]];
     march_entry(it, cq, e, it.L.cmax);
   }
-}
-
-__global__ __launch_bounds__(kNTc) void k_clear_apply_b(const Batch* bt) {
-  const int64_t total = bt->off[kBApply][bt->n];
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-    const int i = batch_item(bt, kBApply, w);
-    apply_body(bt->items[i], w - bt->off[kBApply][i]);
+  const uint32_t nover = cq.counter[kOverCtr];
+  for (int64_t g = (int64_t)blockIdx.x * kNTc + threadIdx.x; g < nover;
+       g += (int64_t)gridDim.x * kNTc) {
+    const uint4 o = cq.over[g];
+    const Item& it = bt->items[cq.ray_item[o.x]];
+    march_ray(it, cq, o.x, (int)o.y, (int)o.z, it.L.cmax);
   }
 }
 
@@ -506,7 +469,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Room for kQueueSamplesPerRay samples per ray on average plus two partial
 // segments per ray (a ray's range rarely ends on a segment boundary), and
 // slack for uneven sub-queue fill.  A full sub-queue is not an error: its
-// rays are marched in place by the setup, unpruned.
+// rays go to the overflow list (room for every ray) and are marched whole.
 int64_t clear_queue_cap(int64_t max_points, int seg) {
   const int64_t segs = (max_points * kQueueSamplesPerRay + seg - 1) / seg + 2 * max_points;
   return (segs + segs / 8 + kSubQ - 1) / kSubQ;
@@ -524,60 +487,53 @@ size_t clear_scratch_layout(int64_t max_points, int seg, char* base, ClearQueue*
   off = align256(off + n * sizeof(int32_t));
   const size_t o_q = off;
   off = align256(off + (size_t)kSubQ * qcap * sizeof(uint2));
+  const size_t o_over = off;
+  off = align256(off + n * sizeof(uint4));
   if (out && base) {
     out->ray = (float4*)(base + o_ray);
     out->ray_end = (int32_t*)(base + o_end);
     out->ray_item = (int32_t*)(base + o_item);
     out->queue = (uint2*)(base + o_q);
+    out->over = (uint4*)(base + o_over);
     out->qcap = (int64_t)qcap;
     out->seg = seg;
   }
   return off;
 }
 
-hipError_t launch_clear(const Item& it, int march_grid, hipStream_t stream) {
-  const int64_t cells = (int64_t)it.c.nx * it.c.ny;
-  if (it.n > 0) {
-    const unsigned nray = (unsigned)((it.n + kNTc - 1) / kNTc);
-    {
-      TimedLaunch tl("k_clear_setup", stream);
-      hipLaunchKernelGGL(k_clear_setup, dim3((unsigned)it.nprep + nray), dim3(kNTc), 0, stream,
-                         it);
-    }
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    {
-      TimedLaunch tl("k_clear_march", stream);
-      hipLaunchKernelGGL(k_clear_march, dim3((unsigned)march_grid), dim3(kNTc), 0, stream, it);
-    }
-    err = hipGetLastError();
-    if (err != hipSuccess) return err;
+hipError_t launch_clear(const Item& it, int march_grid, hipStream_t stream, bool* ran) {
+  *ran = false;
+  // with no rays the setup still zeroes the caller's mask (block role only)
+  if (it.n <= 0 && !it.out_cleared) return hipSuccess;
+  const unsigned nray = it.n > 0 ? (unsigned)((it.n + kNTc - 1) / kNTc) : 0u;
+  {
+    TimedLaunch tl("k_clear_setup", stream);
+    hipLaunchKernelGGL(k_clear_setup, dim3((unsigned)it.nprep + nray), dim3(kNTc), 0, stream, it);
   }
-  TimedLaunch tl("k_clear_apply", stream);
-  hipLaunchKernelGGL(k_clear_apply, dim3((unsigned)clear_apply_units(cells)), dim3(kNTc), 0,
-                     stream, it);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  *ran = true;
+  if (it.n <= 0) return hipSuccess;
+  TimedLaunch tl("k_clear_march", stream);
+  hipLaunchKernelGGL(k_clear_march, dim3((unsigned)march_grid), dim3(kNTc), 0, stream, it);
   return hipGetLastError();
 }
 
-int clear_setup_units(int64_t n, int nprep) {
-  return n > 0 ? nprep + (int)((n + kNTc - 1) / kNTc) : 0;
+int clear_setup_units(int64_t n, int nprep, bool mask) {
+  return n > 0 ? nprep + (int)((n + kNTc - 1) / kNTc) : (mask ? nprep : 0);
 }
 int clear_blocks_per_wave(int nb) { return nb >= 4096 ? kMaxBlocksPerWave : 1; }
 int clear_block_units(int nb) {
   const int per = (kNTc / 64) * clear_blocks_per_wave(nb);
   return (nb + per - 1) / per;
 }
-int64_t clear_apply_units(int64_t cells) { return (cells + kApplyCells - 1) / kApplyCells; }
 
 hipError_t launch_clear_batch(const Batch* d_batch, int grid_setup, int grid_march,
-                              int grid_apply, hipStream_t stream) {
+                              hipStream_t stream) {
   hipLaunchKernelGGL(k_clear_setup_b, dim3(grid_setup), dim3(kNTc), 0, stream, d_batch);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_clear_march_b, dim3(grid_march), dim3(kNTc), 0, stream, d_batch);
-  err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_clear_apply_b, dim3(grid_apply), dim3(kNTc), 0, stream, d_batch);
   return hipGetLastError();
 }
 

@@ -29,7 +29,8 @@ constexpr int kTileCells = kTile * kTile;
 // apart.
 constexpr int kSubQ = 64;
 constexpr int kCtrStride = 32;
-constexpr int kCtrWords = kSubQ * kCtrStride;
+constexpr int kOverCtr = kSubQ * kCtrStride;          // the overflow list's counter
+constexpr int kCtrWords = (kSubQ + 1) * kCtrStride;   // one set of queue counters
 
 // One buffer set of map layers, row-major [ny][nx].
 struct Layers {
@@ -99,7 +100,11 @@ struct ClearQueue {
   int32_t* ray_end;   // end point's cell or -1
   int32_t* ray_item;  // item of the ray (batched launches), or nullptr
   uint2* queue;       // kSubQ sub-queues of qcap (ray, k_start << 8 | count) entries
-  uint32_t* counter;  // kSubQ counters, kCtrStride apart; zero on entry
+  uint4* over;        // rays that did not fit their sub-queue: (ray, k0, k1, 0)
+  uint32_t* counter;  // kSubQ sub-queue counters and the overflow counter (at
+                      // kOverCtr), kCtrStride apart; zero on entry
+  uint32_t* counter_next;  // the next call's counter set, zeroed by this call's
+                           // setup (plain calls alternate two sets), or null
   int64_t qcap;       // entries per sub-queue
   int seg;            // samples per queued segment (1..255)
 };
@@ -144,7 +149,7 @@ struct Item {
 // Batched launches: a device-resident table of items and, per stage, the
 // prefix of work units over the items.
 constexpr int kMaxItems = 64;
-enum BatchStage { kBMove = 0, kBChunk, kBTile, kBSetup, kBApply, kBCells, kBNum };
+enum BatchStage { kBMove = 0, kBChunk, kBTile, kBSetup, kBCells, kBNum };
 
 // Only the header and the first n items are uploaded for a batch of n.
 struct Batch {

@@ -8,9 +8,10 @@
 
 namespace emx {
 
-// Per-map control words after the two buffer sets: the clearing sub-queue
-// counters of the plain calls.
-constexpr int kCtlWords = kCtrWords;
+// Per-map control words after the two buffer sets: two sets of clearing
+// queue counters, used by alternate plain calls (each call's setup zeroes the
+// other set for the next call).
+constexpr int kCtlWords = 2 * kCtrWords;
 
 // Default clearing segment length (samples per queued segment) and march
 // workgroups per compute unit, from a sweep of both on MI355X.
@@ -41,6 +42,7 @@ struct emx_map {
   int cur;
   emx::Layers sets[2];
   uint32_t* ctl;
+  int ctr_sel;  // the counter set the next clear_visibility uses
   int march_grid;
 };
 

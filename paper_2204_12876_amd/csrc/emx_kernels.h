@@ -42,15 +42,17 @@ hipError_t launch_fuse_batch(const Batch* d_batch, bool key64, int grid_chunk, i
 // ---------------------------------------------------------------- clearing
 int64_t clear_queue_cap(int64_t max_points, int seg);
 size_t clear_scratch_layout(int64_t max_points, int seg, char* base, ClearQueue* out);
-int clear_setup_units(int64_t n, int nprep);
+// Setup workgroups: block role, then one per 256 rays; with no rays, the
+// block role alone if a removed-cell mask must be zeroed.
+int clear_setup_units(int64_t n, int nprep, bool mask);
 // Blocks per wave and workgroups of the setup's block role for nb pruning blocks.
 int clear_blocks_per_wave(int nb);
 int clear_block_units(int nb);
-int64_t clear_apply_units(int64_t cells);
-// The item's queue counters must be zero on entry; the call leaves them zero.
-hipError_t launch_clear(const Item& it, int march_grid, hipStream_t stream);
+// The item's queue counters must be zero on entry; the setup zeroes
+// it.cq.counter_next (if set) for the next call.  *ran: the setup was launched.
+hipError_t launch_clear(const Item& it, int march_grid, hipStream_t stream, bool* ran);
 hipError_t launch_clear_batch(const Batch* d_batch, int grid_setup, int grid_march,
-                              int grid_apply, hipStream_t stream);
+                              hipStream_t stream);
 
 // --------------------------------------------------------------- per cell
 int64_t move_units(int nx, int ny);

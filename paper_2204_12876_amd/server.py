@@ -299,7 +299,7 @@ class GpuExecutor:
     #     the host for milliseconds, and varying batch shapes would keep
     #     capturing new graphs while frames wait.
     DEFAULT_TUNING = {"grid_move": 65536, "grid_chunk": 65536, "grid_tile": 65536,
-                      "grid_setup": 65536, "grid_apply": 65536, "grid_cells": 65536,
+                      "grid_setup": 65536, "grid_cells": 65536,
                       "graph": 0}
 
     def __init__(self, largest_params: dict, lanes: int = 2, max_items: int = 64,
