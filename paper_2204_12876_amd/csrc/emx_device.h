@@ -20,10 +20,14 @@ namespace emx {
 // Points per fusion chunk.  This fixes the float32 summation order of the fused
 // sums, so it is a constant of the library, not a tunable.
 constexpr int kChunk = 1024;
-// Map tiles of 32x32 cells own the per-cell merge.
-constexpr int kTileLog = 5;
-constexpr int kTile = 1 << kTileLog;
-constexpr int kTileCells = kTile * kTile;
+// Map tiles of 32 x 16 cells own the per-cell merge (pass 2 runs one thread
+// per cell of a tile; a 400 x 400 map has 338 tiles, more than the chip's
+// compute units).
+constexpr int kTileLogX = 5;
+constexpr int kTileLogY = 4;
+constexpr int kTileW = 1 << kTileLogX;
+constexpr int kTileH = 1 << kTileLogY;
+constexpr int kTileCells = kTileW * kTileH;
 
 // Clearing queue: kSubQ sub-queues, each with its own counter kCtrStride words
 // apart.

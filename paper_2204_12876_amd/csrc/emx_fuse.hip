@@ -32,7 +32,7 @@ namespace {
 constexpr int kNT1 = kChunk / 2;          // pass-1 threads: two keys each
 constexpr int kPBits = 10;                // point index within the chunk
 static_assert((1 << kPBits) == kChunk, "the key's point field spans one chunk");
-constexpr int kSegBits = 2 * kTileLog;    // local cell within the tile
+constexpr int kSegBits = kTileLogX + kTileLogY;  // local cell within the tile
 // 32-bit keys hold (tile, local, point) while tile * kTileCells < 2^21.
 constexpr int64_t kMaxCells32 = (int64_t)1 << (32 - kPBits);
 
@@ -182,8 +182,9 @@ __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
         const float w = 1.0f / e.sp2;
         s_w[p] = w;
         s_wz[p] = w * e.zm;
-        const uint32_t tile = (uint32_t)((iy >> kTileLog) * it.tiles_x + (ix >> kTileLog));
-        const uint32_t local = (uint32_t)(((iy & (kTile - 1)) << kTileLog) | (ix & (kTile - 1)));
+        const uint32_t tile = (uint32_t)((iy >> kTileLogY) * it.tiles_x + (ix >> kTileLogX));
+        const uint32_t local =
+            (uint32_t)(((iy & (kTileH - 1)) << kTileLogX) | (ix & (kTileW - 1)));
         const KeyT seg = ((KeyT)tile << kSegBits) | (KeyT)local;
         key[j] = (seg << kPBits) | (KeyT)p;
         ++nmine;
@@ -325,9 +326,9 @@ __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
 }
 
 // ------------------------------------------------------------------ pass 2
-constexpr int kNT2 = 1024;                 // pass-2 threads: one per cell of the tile
+constexpr int kNT2 = kTileCells;           // pass-2 threads: one per cell of the tile
 static_assert(kNT2 == kTileCells, "pass 2 gives each thread one cell of the tile");
-constexpr int kCap = 8192;                 // partials staged per group
+constexpr int kCap = 8 * kNT2;             // partials staged per group
 constexpr int kPer = kCap / kNT2;          // partials each thread loads per group
 constexpr int kGroupChunks = 256;          // chunks per group
 constexpr int kMaskWords = kGroupChunks / 32;
@@ -352,8 +353,8 @@ __device__ __forceinline__ void tile_body(const Item& it, int t) {
   bool hit = false;
   const int tx = t % it.tiles_x;
   const int ty = t / it.tiles_x;
-  const int ix = (tx << kTileLog) + (l & (kTile - 1));
-  const int iy = (ty << kTileLog) + (l >> kTileLog);
+  const int ix = (tx << kTileLogX) + (l & (kTileW - 1));
+  const int iy = (ty << kTileLogY) + (l >> kTileLogX);
   const int64_t cell = (int64_t)iy * it.c.nx + ix;
   // a fused move: every cell of the tile takes its moved-in values first (the
   // same thread updates it below, so the update sees them)
@@ -577,8 +578,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-int tiles_x_of(int nx) { return (nx + kTile - 1) >> kTileLog; }
-int tiles_y_of(int ny) { return (ny + kTile - 1) >> kTileLog; }
+int tiles_x_of(int nx) { return (nx + kTileW - 1) >> kTileLogX; }
+int tiles_y_of(int ny) { return (ny + kTileH - 1) >> kTileLogY; }
 bool fuse_needs_key64(int T) { return (int64_t)T * kTileCells > kMaxCells32; }
 
 size_t fuse_scratch_layout(int64_t max_points, int T, int64_t count_cells, char* base,
