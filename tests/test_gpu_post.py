@@ -294,3 +294,46 @@ def test_features_are_deterministic(dev):
     for a, b in zip(*outs):
         assert torch.equal(a.view(torch.uint8) if a.dtype != torch.uint8 else a,
                            b.view(torch.uint8) if b.dtype != torch.uint8 else b)
+
+
+@pytest.mark.parametrize("ub", [0, 1])
+def test_clearing_overflow_list(dev, ub):
+    """Rays far longer than the queue's average budget (about 450 samples
+    each against 128): whole workgroups of rays overflow their sub-queue and
+    are marched from the overflow list.  Marks, state and bound as the oracle."""
+    _say("clearing overflow", ub)
+    rng = np.random.default_rng(77 + ub)
+    params = dict(nx=1000, ny=1000, resolution=0.01, noise_alpha=0.01, gate_k=2.0,
+                  min_range=0.05, ray_step=0.01, clear_normal_alpha=0.05, clear_min_age_ms=10,
+                  upper_bound=ub)
+    p = O.Params.from_dict(params)
+    m = _map(params, dev)
+    st = random_state(p, rng, valid_frac=0.6)
+    st.h[:] = rng.uniform(-0.9, 0.2, st.h.shape).astype(F32)
+    load_state(m, st)
+    n = 2000
+    ang = rng.uniform(0, 2 * np.pi, n)
+    rad = rng.uniform(3.5, 4.9, n)
+    xs = (rad * np.cos(ang)).astype(F32)
+    ys = (rad * np.sin(ang)).astype(F32)
+    zs = rng.uniform(-1.9, -1.2, n).astype(F32)
+    pose = _pose((0.0, 0.0, 1.0))
+    ub0 = np.full((p.ny, p.nx), np.inf, F32)
+    new_ub, cleared = _clear_with_bound(m, p, st, ub0, xs, ys, zs, pose, 1000, dev) if ub else \
+        (None, None)
+    if not ub:
+        out = torch.full((p.nx * p.ny,), 9, dtype=torch.uint8, device=dev)
+        m.clear_visibility(*_dev(dev, xs, ys, zs), pose, 1000, out_cleared=out)
+        torch.cuda.synchronize()
+        marks = O.clear_visibility(p, st, xs, ys, zs, pose, 1000)
+        assert np.array_equal(out.cpu().numpy().reshape(p.ny, p.nx).astype(bool), marks)
+        cleared = int(marks.sum())
+    else:
+        marks = O.clear_visibility(p, st, xs, ys, zs, pose, 1000)
+    g = m.state_numpy()
+    exp = O.apply_clear(p, st, marks)
+    for k in ("h", "v", "valid", "t_upd"):
+        assert np.array_equal(g[k], getattr(exp, k)), k
+    assert cleared > 50
+    _say(f"overflow clearing: {cleared} cells removed")
+    m.close()
