@@ -366,8 +366,9 @@ typedef struct {
 /* Create a batch executor.  tuning_json: NULL, or a flat JSON object whose
  * optional integer keys are the persistent grid sizes in workgroups
  * ("grid_move", "grid_chunk", "grid_tile", "grid_setup", "grid_march",
- * "grid_apply", "grid_cells"), the clearing segment length "seg" (1..255)
- * and "graph" (0 runs the launches directly instead of a cached graph).
+ * "grid_cells"), the clearing segment length "seg" (1..255) and "graph" (0
+ * runs the launches directly instead of a cached graph).  Other keys are
+ * ignored.
  * The executor allocates two pinned host tables and a capture stream. */
 emx_status emx_batch_create(const char* tuning_json, emx_batch** out);
 emx_status emx_batch_destroy(emx_batch* batch); /* waits for its last batch */
