@@ -393,8 +393,10 @@ emx_status emx_clear_visibility(emx_map* m, const emx_frame* f, void* d_scratch,
   it.stages = kStageClear;
   bool ran = false;
   hipError_t e = launch_clear(it, m->march_grid, (hipStream_t)stream, &ran);
-  if (e != hipSuccess) return hip_fail(e, "clear_visibility");
+  // once the setup ran, this call's counter set is spent and the other one
+  // is being zeroed: switch, whatever happened after
   if (ran) m->ctr_sel = 1 - m->ctr_sel;
+  if (e != hipSuccess) return hip_fail(e, "clear_visibility");
   return EMX_OK;
 }
 
