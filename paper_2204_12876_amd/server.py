@@ -362,14 +362,14 @@ class GpuExecutor:
         self.maps.pop(robot).close()
 
     def launch(self, lane: int, requests, offsets, batch_id):
+        if self.single_plain and len(requests) == 1:
+            self._launch_plain(lane, requests[0], offsets[0])
+            return
         st = self.streams[lane]
         base = self.pool.data_ptr()
         items = (_emx.BatchItem * len(requests))()
         wptr = self.weights.data_ptr() if self.weights is not None else None
         stages = _emx.STAGE_ALL if self.weights is not None else _emx.STAGE_ALL & ~_emx.STAGE_TRAV
-        if self.single_plain and len(requests) == 1:
-            self._launch_plain(lane, requests[0], offsets[0])
-            return
         with torch.cuda.stream(st):
             for k, (r, off) in enumerate(zip(requests, offsets)):
                 n = r.n
