@@ -161,8 +161,9 @@ def test_batch_equals_plain_calls_with_graph_replays(dev):
 
 @pytest.mark.parametrize("tuning", [
     '{"graph": 0}',
+    # every key at an odd small value; unknown keys are ignored
     '{"grid_move": 1, "grid_chunk": 3, "grid_tile": 5, "grid_setup": 7, "grid_march": 9, '
-    '"grid_apply": 2, "grid_cells": 1, "seg": 7}',
+    '"grid_cells": 1, "seg": 7, "no_such_key": 2}',
     '{"grid_chunk": 4096, "grid_tile": 4096, "grid_march": 8192, "seg": 128, "graph": 1}',
 ])
 def test_batch_tuning_does_not_change_results(dev, tuning):
