@@ -67,6 +67,35 @@ MUTANTS = [
      "iy = np.where(iy > ny - 1, 2 * (ny - 1) - iy, iy)", "iy = np.where(iy > ny - 1, 2 * ny - 1 - iy, iy)"),
     ("Gaussian with sigma, not sigma squared", "filters.py",
      "w = np.exp(-(i * i) / (2.0 * s * s))", "w = np.exp(-(i * i) / (2.0 * s))"),
+    ("gate boundary exclusive", "elevation.py",
+     'accept = inmap & ((e * e) <= (c["k2"] * (v0 + sp2)))',
+     'accept = inmap & ((e * e) < (c["k2"] * (v0 + sp2)))'),
+    ("fused height from the x row", "elevation.py",
+     "zm64 = R[2, 0] * x64 + R[2, 1] * y64 + R[2, 2] * z64 + t[2]",
+     "zm64 = R[0, 0] * x64 + R[2, 1] * y64 + R[2, 2] * z64 + t[2]"),
+    ("ray step count from |dx| + |dy|", "elevation.py",
+     "m = np.maximum(np.abs(dx), np.abs(dy))", "m = np.abs(dx) + np.abs(dy)"),
+    ("ray samples from k = 0", "elevation.py",
+     "k = np.arange(len(rep)) - np.repeat(starts, nsamp) + 1",
+     "k = np.arange(len(rep)) - np.repeat(starts, nsamp)"),
+    ("upper bound takes the maximum", "elevation.py",
+     "np.minimum.at(out, cs[sel], qz[sel])", "np.maximum.at(out, cs[sel], qz[sel])"),
+    ("overlap threshold inclusive", "elevation.py",
+     "far = np.abs(st.h - rz) > thr", "far = np.abs(st.h - rz) >= thr"),
+    ("normal window without its corners", "elevation.py",
+     "acc &= v[1 + dy:ny - 1 + dy, 1 + dx:nx - 1 + dx]",
+     "acc &= v[1 + dy:ny - 1 + dy, 1 + dx:nx - 1 + dx] if dx * dy == 0 else True"),
+    ("normal z not normalised", "elevation.py",
+     "out[2, 1:-1, 1:-1] = np.where(inner, 1.0 / nrm, np.nan)",
+     "out[2, 1:-1, 1:-1] = np.where(inner, 1.0, np.nan)"),
+    ("inpainting over 8 neighbours", "filters.py",
+     "steps = ((0, 1), (0, -1), (1, 0), (-1, 0))",
+     "steps = ((0, 1), (0, -1), (1, 0), (-1, 0), (1, 1), (1, -1), (-1, 1), (-1, -1))"),
+    ("box blur over one row", "filters.py",
+     "return _windows(x, ksize).mean(axis=(2, 3))",
+     "return _windows(x, ksize)[:, :, ksize // 2, :].mean(axis=2)"),
+    ("median by mean", "filters.py",
+     "out = np.median(w, axis=2)", "out = np.mean(w, axis=2)"),
 ]
 
 
