@@ -98,11 +98,15 @@ class Params:
     noise_alpha: float = 1e-4
     gate_k: float = 3.0
     min_range: float = 0.05
-    ray_step: float = 0.04
+    ray_step: float = None         # clearing ray step; None takes the resolution
     clear_normal_alpha: float = 0.3
     clear_min_age_ms: int = 500
     time_variance: float = 0.0     # sigma_t^2 added per fusion to cells it leaves alone
     wall_min_count: int = 0        # wall/edge rule threshold; 0 turns the rule off
+
+    def __post_init__(self):
+        if self.ray_step is None:
+            self.ray_step = self.resolution
 
     @classmethod
     def from_dict(cls, d: dict) -> "Params":
@@ -499,15 +503,15 @@ def move_layer(p: Params, st: MapState, layer: np.ndarray, cx: float, cy: float,
                fill) -> np.ndarray:
     """One extra layer through the robot-centric move of ``move_map``: cells
     that stay keep their value, cells that enter take ``fill``."""
-    ngx = int(math.floor(cx / p.resolution))
-    ngy = int(math.floor(cy / p.resolution))
-    sx, sy = ngx - st.cgx, ngy - st.cgy
+    shift_x = int(math.floor(cx / p.resolution)) - st.cgx
+    shift_y = int(math.floor(cy / p.resolution)) - st.cgy
     out = np.full_like(layer, fill)
     ny, nx = p.ny, p.nx
-    x0, x1 = max(0, -sx), min(nx, nx - sx)
-    y0, y1 = max(0, -sy), min(ny, ny - sy)
+    # out local (ix, iy) <- layer local (ix + shift_x, iy + shift_y)
+    x0, x1 = max(0, -shift_x), min(nx, nx - shift_x)
+    y0, y1 = max(0, -shift_y), min(ny, ny - shift_y)
     if x0 < x1 and y0 < y1:
-        out[y0:y1, x0:x1] = layer[y0 + sy:y1 + sy, x0 + sx:x1 + sx]
+        out[y0:y1, x0:x1] = layer[y0 + shift_y:y1 + shift_y, x0 + shift_x:x1 + shift_x]
     return out
 
 

@@ -299,3 +299,50 @@ def test_move_far_resets_everything_and_composes():
     for x, y in zip(_layers(ab), _layers(direct)):
         np.testing.assert_array_equal(x[kept], y[kept])
     assert (direct.valid == 1).sum() == (8 - 3) * (8 - 1)
+
+
+# ---------------------------------------------------------------------- move_layer
+# move_layer carries one extra layer (the upper bound) through the robot-centric
+# move.  It is pinned by a per-cell brute force over the move's definition, by
+# shift and inverse shift, by a shift past the map side and by agreement with
+# move_map on the height layer.
+def _brute_move(layer, sx, sy, fill):
+    ny, nx = layer.shape
+    out = np.empty_like(layer)
+    for iy in range(ny):
+        for ix in range(nx):
+            jx, jy = ix + sx, iy + sy
+            inside = 0 <= jx < nx and 0 <= jy < ny
+            out[iy, ix] = layer[jy, jx] if inside else fill
+    return out
+
+
+@pytest.mark.parametrize("cx,cy", [(3 * 0.25 + 0.1, -2 * 0.25 + 0.1), (-1.3, 0.6), (0.0, 0.0),
+                                   (0.1, -3 * 0.25 + 0.01)])
+def test_move_layer_brute_force(cx, cy):
+    p = O.Params(nx=9, ny=7, resolution=0.25)
+    st = _rand_state(p, 3)
+    lay = np.random.default_rng(4).normal(size=(7, 9)).astype(F32)
+    sx = math.floor(cx / 0.25) - st.cgx
+    sy = math.floor(cy / 0.25) - st.cgy
+    out = O.move_layer(p, st, lay, cx, cy, np.inf)
+    np.testing.assert_array_equal(out, _brute_move(lay, sx, sy, np.inf))
+
+
+def test_move_layer_shift_back_far_and_move_map():
+    p = O.Params(nx=12, ny=10, resolution=0.25)
+    st = _rand_state(p, 5)
+    lay = np.random.default_rng(6).normal(size=(10, 12)).astype(F32)
+    a = O.move_layer(p, st, lay, 3 * 0.25 + 0.1, -2 * 0.25 + 0.1, np.inf)     # shift (3, -2)
+    st_a = O.move_map(p, st, 3 * 0.25 + 0.1, -2 * 0.25 + 0.1)
+    b = O.move_layer(p, st_a, a, 0.1, 0.1, np.inf)                           # and back
+    keep = (slice(0, 8), slice(3, 12))
+    np.testing.assert_array_equal(b[keep], lay[keep])
+    assert np.isinf(b[8:]).all() and np.isinf(b[:, :3]).all()
+    # a shift of at least the map side leaves only the fill
+    assert (O.move_layer(p, st, lay, 12 * 0.25 + 0.1, 0.1, -7.0) == F32(-7.0)).all()
+    assert (O.move_layer(p, st, lay, 0.1, -10 * 0.25 + 0.1, -7.0) == F32(-7.0)).all()
+    # the height layer with the prior as fill is move_map's height layer
+    for cx, cy in [(3 * 0.25 + 0.1, -2 * 0.25 + 0.1), (-0.9, 1.2), (5.0, 5.0)]:
+        np.testing.assert_array_equal(O.move_layer(p, st, st.h, cx, cy, F32(0.0)),
+                                      O.move_map(p, st, cx, cy).h)

@@ -55,7 +55,15 @@ MUTANTS = [
     ("traversability kernel flipped", "elevation.py",
      "act = act + w1[ch, dy + 1, dx + 1] * win", "act = act + w1[ch, 1 - dy, 1 - dx] * win"),
     ("move in the wrong direction", "elevation.py",
-     "sx, sy = ngx - st.cgx, ngy - st.cgy", "sx, sy = st.cgx - ngx, st.cgy - ngy", 2),
+     "sx, sy = ngx - st.cgx, ngy - st.cgy", "sx, sy = st.cgx - ngx, st.cgy - ngy"),
+    ("extra layer moved in the wrong direction", "elevation.py",
+     "shift_x = int(math.floor(cx / p.resolution)) - st.cgx",
+     "shift_x = st.cgx - int(math.floor(cx / p.resolution))"),
+    ("extra layer filled with zero", "elevation.py",
+     "out = np.full_like(layer, fill)", "out = np.zeros_like(layer)"),
+    ("extra layer rows and columns swapped", "elevation.py",
+     "out[y0:y1, x0:x1] = layer[y0 + shift_y:y1 + shift_y, x0 + shift_x:x1 + shift_x]",
+     "out[y0:y1, x0:x1] = layer[y0 + shift_x:y1 + shift_x, x0 + shift_y:x1 + shift_y]"),
     ("drift error sign", "elevation.py",
      'err = d["zm"][use].astype(F64) - st.h.reshape(-1)[cc[use]].astype(F64)',
      'err = st.h.reshape(-1)[cc[use]].astype(F64) - d["zm"][use].astype(F64)'),
