@@ -1,27 +1,36 @@
 """Benchmark of the elevation-map fusion hot path on one MI355X.
 
-Headline workload: one robot.
-  * A 400x400 map at 0.04 m (16 x 16 m).
-  * 300k-point frames: a 64-beam dome LiDAR plus four depth frustums.
-  * The frames follow a seeded smooth trajectory over a synthetic terrain.
-One step is one frame through the whole per-frame path, the ABI calls in
-order: move_fuse_points (the robot-centric move inside the fusion),
-clear_visibility, normals_traversability (the normals and the traversability
-filter in one pass).  Every frame is generated on the device before timing
-starts.
-  * value: the timed frames submitted back to back (inputs resident in HBM),
-    points per second of wall time between two device synchronisations.
-  * latency_ms: the same frames with the host waiting for each one
-    (submission to completion).
-  * roofline: the dominant kernel of the plain path, its per-launch duration
-    taken with events on its stream around each launch.
+Headline: the serving workload, continuous batching against per-frame plain
+launches (points fused per second and p99 update latency).
+  * 64 simulated robots; maps U{256..800}^2 at 0.04 m; frames of logU[50k, 500k]
+    points (a dome LiDAR plus four depth frustums) copied from pinned host
+    memory; the full per-frame path (move, fusion, visibility clearing,
+    normals, traversability); every map resident in device memory under a
+    32 GiB budget.
+  * One step serves one frame of every robot.  Robots are closed-loop
+    clients: each submits its next frame as soon as the previous one has
+    completed, so the server always holds every robot's next frame.  W steps
+    warm up, then K steps are timed between two device synchronisations.
+  * value: points per second through the server over the K steps.
+    latency_ms: per-frame update latency (submission to completion).
+    plain: the same K steps through the per-frame plain calls on one stream.
+  * sweep: the seeded Poisson arrival trace (20 Hz per robot; a warm-up
+    second and a measured window) replayed at x1, x2, x4, ... time
+    compression through both, until each stops keeping up.
+  * roofline: the dominant kernel of the headline's server run, from a second
+    pass of the K steps with every kernel bracketed by events on its stream.
 
-Also reported, each with its plain per-frame comparison:
+Sub-records, each with its plain comparison where one exists:
+  * single_robot: the 400x400 map with 300k-point frames through the plain
+    calls (per-kernel timings);
+  * features: the further per-map steps on the same map and frames;
   * batched: 16 maps of uneven sizes, one frame each, in one batched launch
-    (emx_pipeline_batch) against 16 per-frame plain pipelines;
-  * server: 64 robots sending frames by Poisson arrival at 20 Hz each into the
-    continuous-batching server, against the per-frame plain loop on the same
-    arrival trace; and both with every frame queued at once (saturated).
+    against 16 plain pipelines; warm, and cold with a rotation over copies
+    larger than the 256 MB last-level cache;
+  * stress: the 2000x2000 map with 4M-point LiDAR frames, plain, and batched
+    together with 8 400x400 maps;
+  * cpu_baseline: the oracle on a bounded sample of the headline workload, on
+    the host cores, one map per process; and on the 128x128 fusion case.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -44,35 +53,43 @@ METRIC = "points fused/sec and p99 update latency: batched server vs per-frame p
 HBM_PEAK_GBS = 8000.0
 STAGES = ("move_fuse_points", "clear_visibility", "normals_traversability")
 TUNING_FILE = os.path.join(ROOT, "paper_2204_12876_amd", "tuning_mi355x.json")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_400x400_300k.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+BUDGET_BYTES = 32 << 30
+SLO_S = 0.05          # one frame period at 20 Hz: a later update lags the robot by a frame
 
 
 def say(*a):
     print("#", *a, file=sys.stderr, flush=True)
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed steps of the headline (one frame of every robot per step)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--robots", type=int, default=64)
+    ap.add_argument("--lanes", type=int, default=2)
+    ap.add_argument("--sweep-warm", type=float, default=1.0)
+    ap.add_argument("--sweep-window", type=float, default=10.0)
+    ap.add_argument("--sweep-max", type=int, default=64, help="largest time compression")
+    ap.add_argument("--single-frames", type=int, default=30)
     ap.add_argument("--points", type=int, default=300000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=50)
-    ap.add_argument("--skip-batched", action="store_true")
-    ap.add_argument("--skip-features", action="store_true")
-    ap.add_argument("--skip-server", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=20)
-    ap.add_argument("--server-seconds", type=float, default=1.0)
-    ap.add_argument("--server-robots", type=int, default=64)
-    ap.add_argument("--server-lanes", type=int, default=2)
+    ap.add_argument("--stress-frames", type=int, default=4)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="oracle seconds per process in the CPU baseline")
+    ap.add_argument("--cpu-procs", type=int, default=0, help="0: min(16, host cores)")
+    for leg in ("sweep", "single", "features", "batched", "stress"):
+        ap.add_argument(f"--skip-{leg}", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default=None, help="batch tuning JSON (default: the tuned file)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy 256 MiB device to device once (a known-size kernel that "
                          "calibrates hardware byte counters)")
     ap.add_argument("--autotune", default=None, metavar="OUT",
                     help="tune the batched executor on the 16-map workload, write OUT, exit")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def cpu_model() -> str:
@@ -85,52 +102,45 @@ def cpu_model() -> str:
     return platform.processor()
 
 
-def frame_stats(cell: np.ndarray, acc: np.ndarray) -> dict:
-    return dict(touched=np.unique(cell[cell >= 0]).size,
-                updated=np.unique(cell[acc.astype(bool)]).size)
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else math.nan
 
 
-def kernel_alg_bytes(name: str, n: int, C: int, touched: float, updated: float,
-                     moved: float = 0.0) -> float:
-    """Bytes each kernel must move at the least, per launch.
-      fusion pass 1: the points (12 B) and the prior h, v of each distinct
-        in-map cell they hit (8 B);
-      fusion pass 2: prior h, v read and h, v, t_upd, valid written for each
+# ------------------------------------------------------------ algorithmic bytes
+def frame_bytes(n: float, C: float, touched: float, updated: float, moved: float) -> dict:
+    """Bytes each stage of one frame must move at the least, by kernel role.
+      fuse_chunk: the points (12 B) and the prior h, v of each distinct in-map
+        cell they hit (8 B);
+      fuse_tile: prior h, v read and h, v, t_upd, valid written for each
         updated cell (8 + 13 B); with the move folded in (a frame whose centre
         cell changes), also every layer read and written once (2 x 29 B);
-      clearing: setup reads the points and h, t_upd, valid per cell for the
-        block maxima (9 B); the march reads each cell's h, v, t_upd, valid and
-        normal once (25 B) and resets the removed cells in place;
-      normals: h, valid in (5 B), three components out (12 B);
-      traversability: h, valid in, one float out (9 B);
-      normals and traversability in one pass: h, valid in, four floats out
-        (21 B);
+      clear_setup: the points, and h, t_upd, valid per cell for the block
+        maxima (9 B); clear_march: each cell's h, v, t_upd, valid and normal
+        read once (25 B);
+      cells: normals and traversability from h, valid (5 B in, 16 B out);
       move: every layer read and written once (2 x 29 B)."""
-    return {
-        "k_fuse_chunk": 12 * n + 8 * touched,
-        "k_fuse_tile": 21 * updated + 58 * C * moved,
-        "k_clear_setup": 12 * n + 9 * C,
-        "k_clear_march": 25 * C,
-        "k_normals": 17 * C,
-        "k_trav": 9 * C,
-        "k_normals_trav": 21 * C,
-        "k_move": 58 * C,
-    }.get(name, 0.0)
+    return {"fuse_chunk": 12 * n + 8 * touched, "fuse_tile": 21 * updated + 58 * C * moved,
+            "clear_setup": 12 * n + 9 * C, "clear_march": 25 * C, "cells": 21 * C,
+            "move": 58 * C * moved}
 
 
-KERNEL_SOURCE = {"k_fuse_chunk": "emx_fuse.hip", "k_fuse_tile": "emx_fuse.hip",
-                 "k_clear_setup": "emx_clear.hip", "k_clear_march": "emx_clear.hip",
-                 "k_move": "emx_cells.hip",
-                 "k_normals": "emx_cells.hip", "k_trav": "emx_cells.hip",
-                 "k_normals_trav": "emx_cells.hip",
-                 "k_fill_prior": "emx_cells.hip"}
+PLAIN_KERNEL = {"fuse_chunk": "k_fuse_chunk", "fuse_tile": "k_fuse_tile",
+                "clear_setup": "k_clear_setup", "clear_march": "k_clear_march",
+                "cells": "k_normals_trav", "move": "k_move"}
+BATCH_KERNEL = {"fuse_chunk": "k_fuse_chunk_b", "fuse_tile": "k_fuse_tile_b",
+                "clear_setup": "k_clear_setup_b", "clear_march": "k_clear_march_b",
+                "cells": "k_cells_b", "move": "k_move_b"}
+KERNEL_SOURCE = {"fuse": "emx_fuse.hip", "clear": "emx_clear.hip", "cells": "emx_cells.hip",
+                 "move": "emx_cells.hip"}
 
 
 def kernel_source_hash(kernel: str) -> str:
     """Hash of the source file holding ``kernel`` and the headers it includes."""
+    role = kernel[2:].split("_")[0]
+    src = KERNEL_SOURCE.get(role, "emx_cells.hip")
     d = os.path.join(ROOT, "paper_2204_12876_amd", "csrc")
     h = hashlib.sha256()
-    for f in (KERNEL_SOURCE[kernel], "emx_device.h", "emx_kernels.h"):
+    for f in (src, "emx_device.h", "emx_kernels.h"):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -154,6 +164,31 @@ def measured_traffic(kernel: str):
         return None
 
 
+def kernel_table(kt: dict, alg: dict) -> dict:
+    """Per kernel: launches, average duration, and with ``alg`` (total
+    algorithmic bytes over the same launches) bytes per launch and GB/s."""
+    out = {}
+    for name, (cnt, tot_ms) in kt.items():
+        e = {"launches": cnt, "avg_us": tot_ms / cnt * 1e3, "total_ms": tot_ms}
+        if name in alg and tot_ms > 0:
+            e["alg_bytes_per_launch"] = alg[name] / cnt
+            e["alg_GBps"] = alg[name] / (tot_ms * 1e-3) / 1e9
+        out[name] = e
+    return out
+
+
+def roofline(kernels: dict) -> dict:
+    """The roofline object of the kernel with the largest total time among
+    those with algorithmic bytes."""
+    cand = [k for k in kernels if "alg_GBps" in kernels[k]]
+    dom = max(cand, key=lambda k: kernels[k]["total_ms"])
+    d = kernels[dom]
+    traffic = measured_traffic(dom)
+    return {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": d["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+            "alg_bytes_per_launch": d["alg_bytes_per_launch"], "avg_launch_us": d["avg_us"]}
+
+
 def load_tuning(args):
     if args.tuning:
         return args.tuning
@@ -163,14 +198,261 @@ def load_tuning(args):
     return None
 
 
+# ---------------------------------------------------------------- serving
+def serving_context(args, dev):
+    """The robots' frames (one per robot, re-sent from its pose; the map centre
+    alternates by one cell so that every frame also moves the map), pinned on
+    the host, and per-robot frame statistics for the algorithmic bytes."""
+    import torch
+
+    import synth
+    from paper_2204_12876_amd import ElevationMap
+
+    t_gen = time.perf_counter()
+    d = synth.cfg3(device=dev, n_robots=args.robots, n_frames=1)
+    torch.cuda.synchronize()
+    items = d["items"]
+    say(f"generated {len(items)} robot frames in {time.perf_counter() - t_gen:.1f} s")
+    w = torch.from_numpy(synth.trav_weights()).to(dev)
+    host, stats = [], []
+    for it in items:
+        f = it["frames"][0]
+        xyz = torch.empty((3, f.n), dtype=torch.float32, pin_memory=True)
+        xyz[0].copy_(f.x)
+        xyz[1].copy_(f.y)
+        xyz[2].copy_(f.z)
+        host.append((xyz, f.pose, it["centers"][0]))
+        m = ElevationMap(it["params"], *it["centers"][0], 0, device=dev)
+        cell = torch.empty(f.n, dtype=torch.int32, device=dev)
+        acc = torch.empty(f.n, dtype=torch.uint8, device=dev)
+        m.fuse_points(f.x.contiguous(), f.y.contiguous(), f.z.contiguous(), f.pose, 100,
+                      out_cell=cell, out_accept=acc)
+        c = cell.cpu().numpy()
+        a = acc.cpu().numpy().astype(bool)
+        m.close()
+        C = it["params"]["nx"] * it["params"]["ny"]
+        stats.append(dict(n=f.n, C=C, touched=np.unique(c[c >= 0]).size,
+                          updated=np.unique(c[a]).size))
+    largest = max((it["params"] for it in items), key=lambda p: p["nx"] * p["ny"])
+    return dict(items=items, host=host, stats=stats, weights=w, largest=largest,
+                data=d)
+
+
+def _make_request(ctx, k, j, arrival=0.0, t_off=0):
+    """Robot k's j-th frame: its one ray-cast frame re-sent from the same pose,
+    with the map centre alternating by one cell; frame times increase with j
+    (and with ``t_off`` between replays on the same maps)."""
+    from paper_2204_12876_amd.server import Request
+    xyz, pose, c = ctx["host"][k]
+    r = ctx["items"][k]["params"]["resolution"]
+    cx = c[0] + (r if j % 2 else 0.0)
+    return Request(robot=k, xyz=xyz, pose=pose, t_ms=t_off + 100 * (j + 1), center=(cx, c[1]),
+                   arrival=float(arrival))
+
+
+def _executor(args, ctx, dev, tuning=None):
+    from paper_2204_12876_amd.server import GpuExecutor, Server
+    ex = GpuExecutor(ctx["largest"], lanes=args.lanes, max_items=64,
+                     max_batch_points=8_000_000, pool_points=24_000_000,
+                     weights=ctx["weights"], tuning=tuning, device=dev)
+    srv = Server(ex, BUDGET_BYTES)
+    for k, it in enumerate(ctx["items"]):
+        srv.add_map(k, it["params"], *ctx["host"][k][2])
+    return ex, srv
+
+
+def _plain_maps(ctx, dev):
+    from paper_2204_12876_amd import ElevationMap
+    return {k: ElevationMap(it["params"], *ctx["host"][k][2], 0, device=dev)
+            for k, it in enumerate(ctx["items"])}
+
+
+def serving_headline(args, dev, ctx):
+    """Closed-loop saturation: K steps (one frame of every robot per step)
+    through the server, then through the per-frame plain calls."""
+    import torch
+
+    from paper_2204_12876_amd import _emx
+    from paper_2204_12876_amd.server import run_closed_loop, run_plain_closed_loop
+
+    K, W = args.steps, args.warmup
+    robots = list(range(len(ctx["items"])))
+    mk = lambda k, j: _make_request(ctx, k, j)        # noqa: E731
+    mx = max(h[0].shape[1] for h in ctx["host"])
+
+    # ---- server: W warm-up steps, then K timed steps between synchronisations
+    ex, srv = _executor(args, ctx, dev)
+    run_closed_loop(srv, mk, robots, max(W, 1))
+    srv.completed.clear()
+    srv.batch_sizes.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reqs = run_closed_loop(srv, lambda k, j: mk(k, W + j), robots, K)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pts = sum(r.n for r in reqs)
+    lat = np.array([r.latency for r in reqs])
+    batches = list(srv.batch_sizes)
+    say(f"server closed loop: {pts / wall / 1e9:.2f} G points/s, p99 "
+        f"{pct(lat, 99) * 1e3:.2f} ms, mean batch {np.mean(batches):.1f}")
+
+    # ---- per-kernel timing: the same K steps again, every kernel bracketed by
+    # events on its stream; algorithmic bytes summed over the frames each
+    # launch served
+    _emx.timing_begin()
+    treqs = run_closed_loop(srv, lambda k, j: mk(k, W + K + j), robots, K)
+    kt = _emx.timing_end()
+    alg = {}
+    for r in treqs:
+        s = ctx["stats"][r.robot]
+        names = BATCH_KERNEL if r.batch_items > 1 else PLAIN_KERNEL
+        for role, b in frame_bytes(s["n"], s["C"], s["touched"], s["updated"], 1.0).items():
+            if role == "move":
+                continue                     # every frame fuses: the move runs inside
+            alg[names[role]] = alg.get(names[role], 0.0) + b
+    kernels = kernel_table(kt, alg)
+    roof = roofline(kernels)
+    b_stats = ex.graph_stats()
+    for m in list(ex.maps):
+        ex.drop_map(m)
+
+    # ---- plain: the same steps through the per-frame calls on one stream
+    maps = _plain_maps(ctx, dev)
+    run_plain_closed_loop(maps, mk, robots, max(W, 1), ctx["weights"], device=dev, max_points=mx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    preqs = run_plain_closed_loop(maps, lambda k, j: mk(k, W + j), robots, K, ctx["weights"],
+                                  device=dev, max_points=mx)
+    torch.cuda.synchronize()
+    pwall = time.perf_counter() - t0
+    plat = np.array([r.latency for r in preqs])
+    for m in maps.values():
+        m.close()
+    say(f"plain closed loop: {pts / pwall / 1e9:.2f} G points/s, p99 {pct(plat, 99) * 1e3:.2f} ms")
+    return {
+        "value": pts / wall,
+        "ms_per_step": wall / K * 1e3,
+        "maps_per_s": len(reqs) / wall,
+        "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
+                       "max": float(lat.max() * 1e3),
+                       "note": "submission to completion; closed-loop clients"},
+        "server": {"mean_batch_items": float(np.mean(batches)), "batches": len(batches),
+                   "lanes": args.lanes, "batched_calls_and_graph_captures": list(b_stats),
+                   "hbm_budget_bytes": BUDGET_BYTES, "hbm_reserved_bytes": srv.budget.used},
+        "plain": {"points_per_s": pts / pwall, "ms_per_step": pwall / K * 1e3,
+                  "p50_ms": pct(plat, 50) * 1e3, "p99_ms": pct(plat, 99) * 1e3,
+                  "mode": "per-frame plain calls (move_fuse_points, clear_visibility, "
+                          "normals_traversability) on one stream, frames in turn"},
+        "speedup_vs_plain": pwall / wall,
+        "points_per_step": pts / K,
+        "kernels": kernels,
+        "roofline": roof,
+    }
+
+
+def poisson_trace(ctx, seconds: float, seed: int = 12876 + 3):
+    """Seeded Poisson arrivals (each robot at its rate) over ``seconds``:
+    (robot, frame index, arrival time) sorted by time."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, it in enumerate(ctx["items"]):
+        gaps = rng.exponential(1.0 / it["rate_hz"], int(seconds * it["rate_hz"] * 3) + 8)
+        times = np.cumsum(gaps)
+        for j, t in enumerate(times[times < seconds]):
+            out.append((k, j, float(t)))
+    out.sort(key=lambda e: e[2])
+    return out
+
+
+def window_summary(reqs, t_from: float, t_to: float) -> dict:
+    """Requests arriving in [t_from, t_to) (compressed time): latency
+    percentiles, and delivered points/s = their points over the time from
+    t_from until the last of them completed."""
+    sel = [r for r in reqs if t_from <= r.arrival < t_to]
+    lat = np.array([r.latency for r in sel])
+    pts = sum(r.n for r in sel)
+    end = max(r.done for r in sel)
+    return dict(frames=len(sel), points=int(pts), offered_points_per_s=pts / (t_to - t_from),
+                points_per_s=pts / (end - t_from), p50_ms=pct(lat, 50) * 1e3,
+                p99_ms=pct(lat, 99) * 1e3, max_ms=float(lat.max() * 1e3))
+
+
+def serving_sweep(args, dev, ctx):
+    """The Poisson trace replayed at x1, x2, x4, ... through the server and the
+    plain loop.  A system stops at the first level where it no longer keeps
+    up: delivered points/s under 95% of offered, or p99 above one frame period
+    (50 ms)."""
+    from paper_2204_12876_amd.server import run_plain_trace, run_trace
+
+    warm, win = args.sweep_warm, args.sweep_window
+    base = poisson_trace(ctx, warm + win)
+    offered = sum(ctx["stats"][k]["n"] for k, _, t in base if t >= warm) / win
+    mx = max(h[0].shape[1] for h in ctx["host"])
+    levels = []
+    c = 1
+    while c <= args.sweep_max:
+        levels.append(c)
+        c *= 2
+    ex, srv = _executor(args, ctx, dev)
+    maps = _plain_maps(ctx, dev)
+    out = {"trace": f"Poisson, 20 Hz per robot, {warm:g} s warm-up + {win:g} s window at x1; "
+                    f"{len(base)} frames; offered {offered / 1e6:.0f} M points/s at x1",
+           "slo_ms": SLO_S * 1e3, "levels": []}
+    alive = {"server": True, "plain": True}
+    for li, c in enumerate(levels):
+        ent = {"compression": c}
+        for name in ("server", "plain"):
+            if not alive[name]:
+                continue
+            # frame times keep increasing from one replay to the next on the same maps
+            t_off = (li + 1) * 10_000_000
+            reqs = [_make_request(ctx, k, j, t / c, t_off) for k, j, t in base]
+            for i, r in enumerate(reqs):
+                r.seq = i
+            if name == "server":
+                srv.completed.clear()
+                srv.batch_sizes.clear()
+                run_trace(srv, reqs, timeout_s=300)
+            else:
+                run_plain_trace(maps, reqs, ctx["weights"], device=dev, max_points=mx)
+            s = window_summary(reqs, warm / c, (warm + win) / c)
+            if name == "server":
+                s["mean_batch_items"] = float(np.mean([r.batch_items for r in reqs
+                                                       if r.arrival >= warm / c]))
+            keeps_up = s["points_per_s"] >= 0.95 * s["offered_points_per_s"] and \
+                s["p99_ms"] <= SLO_S * 1e3
+            s["keeps_up"] = bool(keeps_up)
+            ent[name] = s
+            alive[name] = keeps_up
+            say(f"sweep x{c} {name}: {s['points_per_s'] / 1e9:.2f} G points/s of "
+                f"{s['offered_points_per_s'] / 1e9:.2f}, p50 {s['p50_ms']:.2f} "
+                f"p99 {s['p99_ms']:.2f} ms" + (f", batch {s['mean_batch_items']:.1f}"
+                                              if name == "server" else ""))
+        out["levels"].append(ent)
+        if not alive["server"] and not alive["plain"]:
+            break
+    for m in list(ex.maps):
+        ex.drop_map(m)
+    for m in maps.values():
+        m.close()
+    for name in ("server", "plain"):
+        ok = [e[name] for e in out["levels"] if name in e and e[name]["keeps_up"]]
+        out[f"{name}_sustained_points_per_s"] = max((s["points_per_s"] for s in ok), default=0.0)
+    return out
+
+
 # ------------------------------------------------------------- plain, one robot
-def plain_single_robot(args, dev):
+def single_robot(args, dev):
+    """The 400x400 map with 300k-point frames along a trajectory, through the
+    plain calls: frames back to back, then with the host waiting, then with
+    every kernel timed by events."""
     import torch
 
     import synth
     from paper_2204_12876_amd import ElevationMap, _emx
 
-    K, W = args.steps, args.warmup
+    K = args.single_frames
+    W = 5
     t_gen = time.perf_counter()
     d = synth.cfg1(n_frames=W + K, device=dev, n_points=args.points)
     torch.cuda.synchronize()
@@ -208,9 +490,7 @@ def plain_single_robot(args, dev):
         torch.cuda.synchronize()
         return m
 
-    # ---- timed: frames back to back, inputs resident; wall clock between syncs
     m = fresh()
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for j in range(K):
         run(m, W + j)
@@ -218,9 +498,8 @@ def plain_single_robot(args, dev):
     wall = time.perf_counter() - t0
     m.close()
     n_pts = sum(frames[W + j][0].numel() for j in range(K))
-    say(f"plain back to back: {wall / K * 1e3:.3f} ms/frame")
+    say(f"single robot back to back: {wall / K * 1e3:.3f} ms/frame")
 
-    # ---- latency: the host waits for every frame; events per stage
     m = fresh()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)]
            for _ in range(K)]
@@ -234,85 +513,57 @@ def plain_single_robot(args, dev):
                 for i, name in enumerate(STAGES)}
     m.close()
 
-    # ---- per-kernel durations: the frames back to back again, each kernel
-    # bracketed by events on its stream
+    # frame statistics for the algorithmic bytes (untimed), then the kernels
+    m = fresh()
+    cell = torch.empty(args.points, dtype=torch.int32, device=dev)
+    acc = torch.empty(args.points, dtype=torch.uint8, device=dev)
+    r = params["resolution"]
+    cell_of = [(math.floor(cx / r), math.floor(cy / r)) for cx, cy in centers]
+    alg = {}
+    for j in range(K):
+        run(m, W + j, cell=cell, acc=acc)
+        n = frames[W + j][0].numel()
+        c = cell[:n].cpu().numpy()
+        a = acc[:n].cpu().numpy().astype(bool)
+        moved = float(cell_of[W + j] != cell_of[W + j - 1])
+        for role, b in frame_bytes(n, C, np.unique(c[c >= 0]).size, np.unique(c[a]).size,
+                                   moved).items():
+            if role != "move":
+                alg[PLAIN_KERNEL[role]] = alg.get(PLAIN_KERNEL[role], 0.0) + b
+    m.close()
     m = fresh()
     _emx.timing_begin()
     for j in range(K):
         run(m, W + j)
     kt = _emx.timing_end()
     m.close()
-
-    # ---- frame statistics for the algorithmic bytes (untimed)
-    m = fresh()
-    cell = torch.empty(args.points, dtype=torch.int32, device=dev)
-    acc = torch.empty(args.points, dtype=torch.uint8, device=dev)
-    stats = []
-    for j in range(K):
-        run(m, W + j, cell=cell, acc=acc)
-        n = frames[W + j][0].numel()
-        stats.append(frame_stats(cell[:n].cpu().numpy(), acc[:n].cpu().numpy()))
-    m.close()
-    touched = float(np.mean([s["touched"] for s in stats]))
-    updated = float(np.mean([s["updated"] for s in stats]))
-    n_mean = n_pts / K
-    # the share of timed frames whose centre cell changes (the move is folded
-    # into fusion pass 2 for those)
-    r = params["resolution"]
-    cell_of = [(math.floor(cx / r), math.floor(cy / r)) for cx, cy in centers]
-    moved = float(np.mean([cell_of[W + j] != cell_of[W + j - 1] for j in range(K)]))
-    kernels = {}
-    for name, (cnt, tot_ms) in kt.items():
-        avg_us = tot_ms / cnt * 1e3
-        ab = kernel_alg_bytes(name, n_mean, C, touched, updated, moved)
-        kernels[name] = {"launches": cnt, "avg_us": avg_us, "alg_bytes": ab,
-                         "alg_GBps": ab / (avg_us * 1e-6) / 1e9 if avg_us > 0 else None}
-    dom = max((k for k in kernels if k != "k_fill_prior"),
-              key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
-    dk = kernels[dom]
-    traffic = measured_traffic(dom)
-
-    out = {
-        "value": n_pts / wall,
-        "ms_per_step": wall / K * 1e3,
-        "config": {"workload": "plain single robot: 400x400 map at 0.04 m, 300k-point frames "
-                               "(dome LiDAR + 4 depth frustums), full pipeline per frame",
-                   "map_cells": C, "points_per_frame": args.points, "frames": K,
-                   "mode": "per-frame plain calls (move_fuse_points, clear_visibility, "
-                           "normals_traversability), frames submitted back to back"},
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3),
-                       "max": float(lat.max() * 1e3),
-                       "note": "host waits for each frame before the next"},
+    kernels = kernel_table(kt, alg)
+    return {
+        "workload": "one robot: 400x400 map at 0.04 m, 300k-point frames (dome LiDAR + 4 depth "
+                    "frustums) along a trajectory, full path per frame through the plain calls",
+        "frames": K, "points_per_s": n_pts / wall, "ms_per_frame": wall / K * 1e3,
         "maps_per_s": K / wall,
-        "stage_ms": stage_ms,
-        "kernels": kernels,
-        "cells_touched": touched, "cells_updated": updated, "frames_moved": moved,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"],
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dk["alg_GBps"] / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_us": dk["avg_us"]},
-    }
-    return out, dict(frames=frames, centers=centers, params=params)
+        "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
+                       "note": "host waits for each frame"},
+        "stage_ms": stage_ms, "kernels": kernels, "roofline": roofline(kernels),
+    }, dict(frames=frames, centers=centers, params=params)
 
 
 # --------------------------------------------------- optional per-map features
 def features(args, dev, ctx):
-    """The features beyond the base path, on the same workload and frames: a
-    map with time variance, the wall/edge rule and the upper bound layer on,
-    run through the extended per-frame sequence (move, drift compensation,
-    fusion, clearing with the bound, normals, traversability, overlap
-    clearance, inpainting).  Each feature is then timed per kernel over the
-    frames; algorithmic bytes per call are stated in ``FEATURE_BYTES``."""
+    """The features beyond the base path on the single-robot map and frames:
+    time variance, the wall/edge rule and the upper bound layer on, through the
+    extended per-frame sequence (move, drift compensation, fusion, clearing
+    with the bound, normals, traversability, overlap clearance, inpainting).
+    Each feature is then timed per kernel over the frames."""
     import torch
 
     import synth
     from paper_2204_12876_amd import ElevationMap, _emx, smooth
 
     frames, centers, params = ctx["frames"], ctx["centers"], ctx["params"]
-    W = min(args.warmup, len(frames) // 2)
-    K = min(args.steps, len(frames) - W, 20)
+    W = min(5, len(frames) // 2)
+    K = min(20, len(frames) - W)
     C = params["nx"] * params["ny"]
     pe = dict(params, time_variance=1e-4, wall_min_count=8, upper_bound=1)
     w = torch.from_numpy(synth.trav_weights()).to(dev)
@@ -356,8 +607,7 @@ def features(args, dev, ctx):
         _emx.timing_begin()
         for j in range(reps):
             fn(j)
-        kt = _emx.timing_end()
-        return {k: v for k, v in kt.items()}
+        return _emx.timing_end()
 
     x0 = frames[W]
     ops = {
@@ -374,7 +624,7 @@ def features(args, dev, ctx):
         "smooth_gaussian_5": (lambda j: smooth(filled, "gaussian", 5, 1.0), 8 * C),
         "smooth_median_5": (lambda j: smooth(filled, "median", 5), 8 * C),
     }
-    out = {"workload": "the plain workload's map and frames with time_variance, "
+    out = {"workload": "the single-robot map and frames with time_variance, "
                        "wall_min_count=8 and upper_bound on",
            "extended_ms_per_frame": wall / K * 1e3, "frames": K}
     for name, (fn, ab) in ops.items():
@@ -387,211 +637,331 @@ def features(args, dev, ctx):
             gbps = ab / (per_call_us * 1e-6) / 1e9
             ent.update(alg_bytes=ab, alg_GBps=gbps, frac_hbm=gbps / HBM_PEAK_GBS)
         out[name] = ent
-    # the feature kernels inside the extended fusion: counts and time variance
     fk = out["wall_rule_and_time_variance_fusion"]["kernels"]
-    extra = {k: fk[k] for k in ("k_zero_u32", "k_fuse_count", "k_time_variance") if k in fk}
     ab = {"k_zero_u32": 4 * C, "k_fuse_count": 12 * n_mean + 8 * touched,
           "k_time_variance": 2 * C + 8 * valid}
-    for k, e in extra.items():
-        e["alg_bytes"] = ab[k]
-        e["alg_GBps"] = ab[k] / (e["avg_us"] * 1e-6) / 1e9
+    for k in ("k_zero_u32", "k_fuse_count", "k_time_variance"):
+        if k in fk:
+            fk[k]["alg_bytes"] = ab[k]
+            fk[k]["alg_GBps"] = ab[k] / (fk[k]["avg_us"] * 1e-6) / 1e9
     m.close()
     return out
 
 
-# ------------------------------------------------------------ batched, 16 maps
-def batched_maps(args, dev, tuning):
+# ------------------------------------------------------------ batched, many maps
+def batch_vs_plain(args, dev, tuning, specs, label: str, reps: int, cold_copies: int = 0):
+    """Maps of ``specs`` (params, centre, frame) through one emx_pipeline_batch
+    per step against their plain per-frame pipelines; warm (the same maps and
+    frames every step) and, with ``cold_copies``, rotating over that many copies
+    of every map and frame."""
     import torch
 
-    import synth
-    from paper_2204_12876_amd import BatchEntry, ElevationMap, PipelineBatch
+    from paper_2204_12876_amd import BatchEntry, ElevationMap, PipelineBatch, _emx
 
-    t_gen = time.perf_counter()
-    d = synth.cfg2(device=dev)
-    torch.cuda.synchronize()
-    items = d["items"]
-    pts = sum(it["frames"][0].n for it in items)
-    say(f"generated 16 maps / {pts} points in {time.perf_counter() - t_gen:.1f} s")
-    w = torch.from_numpy(synth.trav_weights()).to(dev)
-    fr = [(it["frames"][0].x.contiguous(), it["frames"][0].y.contiguous(),
-           it["frames"][0].z.contiguous(), it["frames"][0].pose) for it in items]
-    R = args.batched_reps
+    w = torch.from_numpy(__import__("synth").trav_weights()).to(dev)
     stream = torch.cuda.current_stream(dev)
+    pts = sum(f[0].numel() for _, _, f in specs)
+    C = sum(p["nx"] * p["ny"] for p, _, _ in specs)
 
     def maps():
-        return [ElevationMap(it["params"], 0.0, 0.0, 0, device=dev) for it in items]
+        return [ElevationMap(p, c[0], c[1], 0, device=dev) for p, c, _ in specs]
 
-    # batched
-    mb = maps()
+    def frames_copy():
+        return [(f[0].clone(), f[1].clone(), f[2].clone(), f[3]) for _, _, f in specs]
+
+    def centre(c, rep, p):       # the centre alternates by one cell: every step moves
+        return (c[0] + (p["resolution"] if rep % 2 else 0.0), c[1])
+
     pb = PipelineBatch(tuning, device=dev)
+    copies = [(maps(), frames_copy()) for _ in range(max(1, cold_copies))]
 
-    def batch(rep):
-        pb.run([BatchEntry(m, x, y, z, pose, 100 * rep, center=(0.0, 0.0), weights=w)
-                for m, (x, y, z, pose) in zip(mb, fr)])
+    def batch(rep, copy=0):
+        mb, fr = copies[copy]
+        pb.run([BatchEntry(m, x, y, z, pose, 100 * (rep + 1), center=centre(c, rep, p), weights=w)
+                for m, (x, y, z, pose), (p, c, _) in zip(mb, fr, specs)])
 
-    for rep in range(3):
-        batch(rep)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for rep in range(3, 3 + R):
-        batch(rep)
-    torch.cuda.synchronize()
-    t_b = (time.perf_counter() - t0) / R
+    def timed(fn, r):
+        for rep in range(3):
+            fn(rep)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for rep in range(3, 3 + r):
+            fn(rep)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / r
+
+    t_b = timed(batch, reps)
     lat_b = []
-    for rep in range(3 + R, 3 + 2 * R):
+    for rep in range(3 + reps, 3 + 2 * reps):
         s = time.perf_counter()
         batch(rep)
         stream.synchronize()
         lat_b.append(time.perf_counter() - s)
+    t_cold = None
+    if cold_copies > 1:
+        t_cold = timed(lambda rep: batch(rep, rep % cold_copies), reps)
+    # per-kernel timing of the batched launches (direct, every kernel bracketed)
+    pbd = PipelineBatch(json.dumps(dict(json.loads(tuning) if tuning else {}, graph=0)),
+                        device=dev)
+    mb, fr = copies[0]
+    _emx.timing_begin()
+    for rep in range(reps):
+        pbd.run([BatchEntry(m, x, y, z, pose, 100 * (rep + 1), center=centre(c, rep, p),
+                            weights=w) for m, (x, y, z, pose), (p, c, _) in zip(mb, fr, specs)])
+    kt = _emx.timing_end()
+    pbd.close()
 
-    # 16 per-frame plain pipelines
     mp = maps()
-    scratch = max((m.scratch(f[0].numel()) for m, f in zip(mp, fr)), key=lambda t: t.numel())
+    fr0 = copies[0][1]
+    scratch = max((m.scratch(f[0].numel()) for m, f in zip(mp, fr0)), key=lambda t: t.numel())
 
     def plain(rep):
-        for m, (x, y, z, pose) in zip(mp, fr):
-            m.move_fuse_points(0.0, 0.0, x, y, z, pose, 100 * rep, scratch=scratch)
-            m.clear_visibility(x, y, z, pose, 100 * rep, scratch=scratch)
+        for m, (x, y, z, pose), (p, c, _) in zip(mp, fr0, specs):
+            m.move_fuse_points(*centre(c, rep, p), x, y, z, pose, 100 * (rep + 1),
+                               scratch=scratch)
+            m.clear_visibility(x, y, z, pose, 100 * (rep + 1), scratch=scratch)
             m.normals_traversability(w)
 
-    for rep in range(3):
-        plain(rep)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for rep in range(3, 3 + R):
-        plain(rep)
-    torch.cuda.synchronize()
-    t_p = (time.perf_counter() - t0) / R
+    t_p = timed(plain, reps)
     lat_p = []
-    for rep in range(3 + R, 3 + 2 * R):
+    for rep in range(3 + reps, 3 + 2 * reps):
         s = time.perf_counter()
         plain(rep)
         stream.synchronize()
         lat_p.append(time.perf_counter() - s)
-    # identical results, as the batched path promises
-    same = all(torch.equal(a.export_state(), b.export_state()) for a, b in zip(mb, mp))
-    for m in mb + mp:
+    # the batch promises the plain calls' bits: fresh maps through three steps
+    # each way
+    ma, mb2 = maps(), maps()
+    for rep in range(3):
+        pb.run([BatchEntry(m, x, y, z, pose, 100 * (rep + 1), center=centre(c, rep, p),
+                           weights=w) for m, (x, y, z, pose), (p, c, _) in zip(ma, fr0, specs)])
+        for m, (x, y, z, pose), (p, c, _) in zip(mb2, fr0, specs):
+            m.move_fuse_points(*centre(c, rep, p), x, y, z, pose, 100 * (rep + 1),
+                               scratch=scratch)
+            m.clear_visibility(x, y, z, pose, 100 * (rep + 1), scratch=scratch)
+            m.normals_traversability(w)
+    same = all(torch.equal(a.export_state(), b.export_state()) for a, b in zip(ma, mb2))
+    for m in ma + mb2:
+        m.close()
+    for mb_, _ in copies:
+        for m in mb_:
+            m.close()
+    for m in mp:
         m.close()
     pb.close()
-    say(f"batched {t_b * 1e3:.3f} ms vs plain {t_p * 1e3:.3f} ms per 16 maps")
-    return {
-        "workload": "16 maps, sides U{200..1000} at 0.02-0.1 m, one frame each of "
-                    "logU[20k, 1M] points, full pipeline",
-        "points_per_batch": int(pts),
-        "batched": {"ms": t_b * 1e3, "points_per_s": pts / t_b, "maps_per_s": 16 / t_b,
-                    "p50_ms": float(np.percentile(lat_b, 50) * 1e3),
-                    "p99_ms": float(np.percentile(lat_b, 99) * 1e3)},
-        "plain": {"ms": t_p * 1e3, "points_per_s": pts / t_p, "maps_per_s": 16 / t_p,
-                  "p50_ms": float(np.percentile(lat_p, 50) * 1e3),
-                  "p99_ms": float(np.percentile(lat_p, 99) * 1e3)},
+    say(f"{label}: batched {t_b * 1e3:.3f} ms vs plain {t_p * 1e3:.3f} ms per step")
+    n = len(specs)
+    out = {
+        "points_per_step": int(pts), "cells": int(C), "maps": n,
+        "batched": {"ms": t_b * 1e3, "points_per_s": pts / t_b, "maps_per_s": n / t_b,
+                    "p50_ms": pct(lat_b, 50) * 1e3, "p99_ms": pct(lat_b, 99) * 1e3},
+        "plain": {"ms": t_p * 1e3, "points_per_s": pts / t_p, "maps_per_s": n / t_p,
+                  "p50_ms": pct(lat_p, 50) * 1e3, "p99_ms": pct(lat_p, 99) * 1e3},
         "speedup": t_p / t_b,
-        "results_identical": bool(same),
-        "tuning": pb_tuning_text(tuning),
+        "batched_kernels": {k: {"launches": c_, "avg_us": tot / c_ * 1e3}
+                            for k, (c_, tot) in kt.items()},
+        "tuning": json.loads(tuning) if tuning else "library defaults",
     }
+    out["results_identical"] = bool(same)
+    if t_cold is not None:
+        out["batched_cold"] = {"ms": t_cold * 1e3, "points_per_s": pts / t_cold,
+                               "copies": cold_copies,
+                               "note": "each step takes the next copy of every map and frame; "
+                                       "the copies together exceed the 256 MB last-level cache"}
+    return out
 
 
-def pb_tuning_text(tuning):
-    return json.loads(tuning) if tuning else "library defaults"
-
-
-# -------------------------------------------------------------- server, 64 robots
-def serving(args, dev, tuning):
+def batched_maps(args, dev, tuning):
     import torch
 
     import synth
-    from paper_2204_12876_amd import ElevationMap
-    from paper_2204_12876_amd.server import (GpuExecutor, Request, Server, latency_summary,
-                                             run_plain_trace, run_trace)
-
     t_gen = time.perf_counter()
-    d = synth.cfg3(device=dev, n_robots=args.server_robots, n_frames=1)
+    d = synth.cfg2(device=dev)
     torch.cuda.synchronize()
-    items = d["items"]
-    say(f"generated {len(items)} robot frames in {time.perf_counter() - t_gen:.1f} s")
-    w = torch.from_numpy(synth.trav_weights()).to(dev)
-    host = []
-    for it in items:
+    specs = []
+    for it in d["items"]:
         f = it["frames"][0]
-        xyz = torch.empty((3, f.n), dtype=torch.float32, pin_memory=True)
-        xyz[0].copy_(f.x)
-        xyz[1].copy_(f.y)
-        xyz[2].copy_(f.z)
-        host.append((xyz, f.pose, it["centers"][0]))
-    largest = max((it["params"] for it in items), key=lambda p: p["nx"] * p["ny"])
-    rng = np.random.default_rng(12876 + 3)
+        specs.append((it["params"], (0.0, 0.0), (f.x.contiguous(), f.y.contiguous(),
+                                                 f.z.contiguous(), f.pose)))
+    say(f"generated 16 maps / {sum(f[0].numel() for _, _, f in specs)} points in "
+        f"{time.perf_counter() - t_gen:.1f} s")
+    # every copy holds the maps' state (two buffer sets, about 60 B per cell)
+    # and the frames; four copies pass 256 MB several times over
+    out = batch_vs_plain(args, dev, tuning, specs, "16 maps", args.batched_reps, cold_copies=4)
+    out["workload"] = ("16 maps, sides U{200..1000} at 0.02-0.1 m, one frame each of "
+                       "logU[20k, 1M] points, full path")
+    return out
 
-    def trace(seconds, saturated_frames=0):
-        reqs, seq = [], 0
-        for k, it in enumerate(items):
-            xyz, pose, c = host[k]
-            if saturated_frames:
-                times = np.zeros(saturated_frames)
-            else:
-                gaps = rng.exponential(1.0 / it["rate_hz"], int(seconds * it["rate_hz"] * 3) + 8)
-                times = np.cumsum(gaps)
-                times = times[times < seconds]
-            for j, t in enumerate(times):
-                # the robot re-observes from its pose; the centre alternates by one cell
-                cx = c[0] + (it["params"]["resolution"] if j % 2 else 0.0)
-                reqs.append(Request(robot=k, xyz=xyz, pose=pose, t_ms=100 * (j + 1),
-                                    center=(cx, c[1]), arrival=float(t), seq=seq))
-                seq += 1
-        return reqs
 
-    budget = 32 << 30
+def stress(args, dev, tuning, single_ctx):
+    """The 2000x2000 map with 4M-point LiDAR frames: plain per frame along its
+    trajectory, and batched together with 8 400x400 maps (300k-point frames of
+    the single-robot workload)."""
+    import torch
 
-    def run_server(reqs, warm):
-        ex = GpuExecutor(largest, lanes=args.server_lanes, max_items=64,
-                         max_batch_points=8_000_000, pool_points=24_000_000, weights=w,
-                         device=dev)
-        srv = Server(ex, budget)
-        for k, it in enumerate(items):
-            srv.add_map(k, it["params"], *host[k][2])
-        run_trace(srv, warm)  # a short trace of the same kind: graph captures, clocks
-        srv.completed.clear()
-        srv.batch_sizes.clear()
-        b0, c0 = ex.graph_stats()
-        run_trace(srv, reqs, timeout_s=120)
-        b1, c1 = ex.graph_stats()
-        s = latency_summary(reqs)
-        s["mean_batch_items"] = float(np.mean(srv.batch_sizes))
-        s["batches"] = len(srv.batch_sizes)
-        s["batched_calls"] = b1 - b0
-        s["graph_captures_in_trace"] = c1 - c0
-        s["hbm_budget_bytes"] = budget
-        s["hbm_reserved_bytes"] = srv.budget.used
-        return s
+    import synth
+    from paper_2204_12876_amd import ElevationMap, _emx
 
-    def run_plain(reqs):
-        maps = {k: ElevationMap(it["params"], *host[k][2], 0, device=dev)
-                for k, it in enumerate(items)}
-        mx = max(h[0].shape[1] for h in host)
-        run_plain_trace(maps, trace(0, saturated_frames=1), w, device=dev, max_points=mx)
-        run_plain_trace(maps, reqs, w, device=dev, max_points=mx)
-        for m in maps.values():
-            m.close()
-        return latency_summary(reqs)
+    S = max(2, args.stress_frames)
+    t_gen = time.perf_counter()
+    d = synth.cfg4(n_frames=S, device=dev)
+    torch.cuda.synchronize()
+    say(f"generated {S} stress frames in {time.perf_counter() - t_gen:.1f} s")
+    frames = [(f.x.contiguous(), f.y.contiguous(), f.z.contiguous(), f.pose, f.t_ms)
+              for f in d["frames"]]
+    centers = d["centers"]
+    params = d["params"]
+    C = params["nx"] * params["ny"]
+    w = torch.from_numpy(synth.trav_weights()).to(dev)
+    m = ElevationMap(params, *centers[0], 0, device=dev)
+    scratch = m.scratch(max(f[0].numel() for f in frames))
+    n_steps = 2 * S
 
-    poisson = trace(args.server_seconds)
-    offered = sum(r.n for r in poisson) / args.server_seconds
-    say(f"server trace: {len(poisson)} frames, offered {offered / 1e6:.0f} M points/s")
-    srv_p = run_server(poisson, trace(0.3))
-    say(f"server p50 {srv_p['p50_ms']:.3f} p99 {srv_p['p99_ms']:.3f} ms")
-    pln_p = run_plain(_fresh(poisson))
-    say(f"plain  p50 {pln_p['p50_ms']:.3f} p99 {pln_p['p99_ms']:.3f} ms")
-    sat = trace(0, saturated_frames=6)
-    srv_s = run_server(sat, trace(0, saturated_frames=2))
-    pln_s = run_plain(_fresh(sat))
-    say(f"saturated: server {srv_s['points_per_s'] / 1e9:.2f} vs plain "
-        f"{pln_s['points_per_s'] / 1e9:.2f} G points/s")
-    return {
-        "workload": f"{len(items)} robots, maps U{{256..800}}^2 at 0.04 m, frames "
-                    "logU[50k, 500k] points, Poisson arrivals at 20 Hz each, full pipeline, "
-                    "frames copied from pinned host memory, 32 GiB device budget",
-        "offered_points_per_s": offered,
-        "poisson": {"server": srv_p, "plain": pln_p},
-        "saturated": {"frames_per_robot": 6, "server": srv_s, "plain": pln_s},
-    }
+    def run(k, t):
+        x, y, z, pose, _ = frames[k % S]
+        m.move_fuse_points(*centers[k % S], x, y, z, pose, t, scratch=scratch)
+        m.clear_visibility(x, y, z, pose, t, scratch=scratch)
+        m.normals_traversability(w)
+
+    run(0, 100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, n_steps + 1):
+        run(k, 100 * (k + 1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pts = sum(frames[k % S][0].numel() for k in range(1, n_steps + 1))
+    _emx.timing_begin()
+    for k in range(n_steps + 1, 2 * n_steps + 1):
+        run(k, 100 * (k + 1))
+    kt = _emx.timing_end()
+    m.close()
+    say(f"stress plain: {wall / n_steps * 1e3:.2f} ms/frame")
+    out = {"workload": "2000x2000 map at 0.02 m, 4M-point frames from a 128-beam LiDAR "
+                       "(30 m, 10% outliers, 500 boxes), full path per frame",
+           "plain": {"frames": n_steps, "distinct_frames": S, "ms_per_frame": wall / n_steps * 1e3,
+                     "points_per_s": pts / wall,
+                     "kernels": {k: {"launches": c, "avg_us": tot / c * 1e3}
+                                 for k, (c, tot) in kt.items()}}}
+    # batched with 8 smaller maps
+    specs = [(params, centers[0], frames[0][:4])]
+    sf, sc, sp = single_ctx["frames"], single_ctx["centers"], single_ctx["params"]
+    for k in range(8):
+        specs.append((sp, sc[k], sf[k][:4]))
+    b = batch_vs_plain(args, dev, tuning, specs, "stress batch", max(3, args.batched_reps // 4))
+    b["workload"] = ("the 2000x2000 map with one 4M-point frame and 8 400x400 maps with one "
+                     "300k-point frame each, one batched launch per step")
+    out["batched"] = b
+    return out
+
+
+# ------------------------------------------------------------------- CPU oracle
+def _oracle_worker(job):
+    """One process: the oracle's full per-frame path on its maps' frames,
+    frame after frame in turn, until ``seconds`` of oracle time have passed."""
+    import oracle as O
+    frames, weights, seconds = job
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    t_cpu, pts, nfr = 0.0, 0, 0
+    states = {}
+    while t_cpu < seconds:
+        for (key, params, centre, xs, ys, zs, pose) in frames:
+            p = O.Params.from_dict(params)
+            st = states.get(key)
+            if st is None:
+                st = O.init_map(p, centre[0], centre[1], 0)
+            t = 100 * (nfr + 1)
+            s = time.perf_counter()
+            st = O.move_map(p, st, centre[0] + (p.resolution if nfr % 2 else 0.0), centre[1])
+            r = O.fuse(p, st, xs, ys, zs, pose, t)
+            st = r.state
+            mk = O.clear_visibility(p, st, xs, ys, zs, pose, t)
+            st = O.apply_clear(p, st, mk)
+            st.nrm[:] = O.compute_normals(p, st.h, st.valid).astype(np.float32)
+            T, _ = O.traversability(st.h, st.valid, weights)
+            st.trav[:] = T.astype(np.float32)
+            t_cpu += time.perf_counter() - s
+            states[key] = st
+            pts += xs.size
+            nfr += 1
+            if t_cpu >= seconds:
+                break
+    return pts, t_cpu, nfr
+
+
+def _cfg0_worker(job):
+    """The oracle's fusion on the 128x128 case, 20 repetitions."""
+    import oracle as O
+    import synth
+    reps = job
+    d = synth.cfg0()
+    p = O.Params.from_dict(d["params"])
+    f = d["frames"][0]
+    xs, ys, zs = f.numpy()
+    ts = []
+    for _ in range(reps):
+        st = O.init_map(p, 0.0, 0.0, 0)
+        s = time.perf_counter()
+        O.fuse(p, st, xs, ys, zs, f.pose, f.t_ms)
+        ts.append(time.perf_counter() - s)
+    return xs.size, ts
+
+
+def cpu_pool(args):
+    """Worker processes for the oracle baseline, started before the GPU is
+    touched (each is a fresh interpreter)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    procs = args.cpu_procs or min(16, os.cpu_count() or 1)
+    # one thread per worker: the variables are read when each interpreter starts
+    keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                           "MKL_NUM_THREADS")}
+    for k in keep:
+        os.environ[k] = "1"
+    pool = ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn"))
+    # a worker starts per task submitted while none is idle: start them all now
+    list(pool.map(time.sleep, [0.5] * procs))
+    for k, v in keep.items():
+        if v is None:
+            os.environ.pop(k)
+        else:
+            os.environ[k] = v
+    return pool, procs
+
+
+def cpu_baseline(args, ctx, pool, procs):
+    """The oracle (float64 NumPy, one thread per process) on the headline
+    workload: the robots' frames spread over ``procs`` processes, one map per
+    process at a time, each running for about ``cpu_seconds``; then one
+    process alone.  Also the 128x128 fusion case, 20 repetitions."""
+    import synth
+    jobs = [[] for _ in range(procs)]
+    for k, it in enumerate(ctx["items"]):
+        xyz, pose, c = ctx["host"][k]
+        a = xyz.numpy()
+        jobs[k % procs].append((k, it["params"], c, a[0].copy(), a[1].copy(), a[2].copy(),
+                                np.asarray(pose)))
+    wts = synth.trav_weights()
+    t0 = time.perf_counter()
+    res = list(pool.map(_oracle_worker, [(j, wts, args.cpu_seconds) for j in jobs if j]))
+    wall = time.perf_counter() - t0
+    pts = sum(r[0] for r in res)
+    nfr = sum(r[2] for r in res)
+    one = pool.submit(_oracle_worker, (jobs[0], wts, args.cpu_seconds)).result()
+    cfg0 = pool.submit(_cfg0_worker, 20).result()
+    n0, ts0 = cfg0
+    used = len([j for j in jobs if j])
+    return {"value": pts / wall, "unit": "points/s", "cores": used, "kind": "oracle",
+            "sample": f"the serving workload's robot frames (full path: move, fusion, clearing, "
+                      f"normals, traversability), {used} processes of one thread each, each "
+                      f"on its robots' maps in turn for about {args.cpu_seconds:g} s: {nfr} "
+                      f"frames, {pts / 1e6:.1f} M points in {wall:.1f} s wall; {cpu_model()}, "
+                      f"{os.cpu_count()} host threads visible",
+            "single_core": {"value": one[0] / one[1], "frames": one[2],
+                            "seconds": one[1], "cores": 1},
+            "fusion_128x128_20k": {"points_per_s": n0 / float(np.median(ts0)),
+                                   "median_ms": float(np.median(ts0) * 1e3), "reps": len(ts0),
+                                   "cores": 1}}
 
 
 def autotune_batched(dev, out_path):
@@ -628,51 +998,15 @@ def autotune_batched(dev, out_path):
     print(json.dumps(out), flush=True)
 
 
-def _fresh(reqs):
-    """Copies of requests with their timing fields reset."""
-    from paper_2204_12876_amd.server import Request
-    return [Request(robot=r.robot, xyz=r.xyz, pose=r.pose, t_ms=r.t_ms, center=r.center,
-                    arrival=r.arrival, seq=r.seq) for r in reqs]
-
-
-# ------------------------------------------------------------------- CPU oracle
-def cpu_baseline(args, ctx):
-    import oracle as O
-    import synth
-    params, frames, centers = ctx["params"], ctx["frames"], ctx["centers"]
-    p = O.Params.from_dict(params)
-    nfr = max(1, args.cpu_frames)
-    st = O.init_map(p, centers[0][0], centers[0][1], 0)
-    wts = synth.trav_weights()
-    t_cpu, pts = 0.0, 0
-    host = [(frames[k][0].cpu().numpy(), frames[k][1].cpu().numpy(),
-             frames[k][2].cpu().numpy()) for k in range(nfr)]
-    for k in range(nfr):
-        xs, ys, zs = host[k]
-        pose, t = frames[k][3], frames[k][4]
-        s = time.perf_counter()
-        st = O.move_map(p, st, *centers[k])
-        r = O.fuse(p, st, xs, ys, zs, pose, t)
-        st = r.state
-        mk = O.clear_visibility(p, st, xs, ys, zs, pose, t)
-        st = O.apply_clear(p, st, mk)
-        st.nrm[:] = O.compute_normals(p, st.h, st.valid).astype(np.float32)
-        T, _ = O.traversability(st.h, st.valid, wts)
-        st.trav[:] = T.astype(np.float32)
-        t_cpu += time.perf_counter() - s
-        pts += xs.size
-    return {"value": pts / t_cpu, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {nfr} frames of the same workload, full pipeline, "
-                      f"{t_cpu:.1f} s on one thread; {cpu_model()}, "
-                      f"{os.cpu_count()} host threads visible"}
-
-
-def main():
-    args = parse()
+def main(argv=None):
+    args = parse(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every map and frame "
               "of this workload fits one MI355X.", file=sys.stderr)
         sys.exit(2)
+    pool = procs = None
+    if not args.no_cpu_baseline and not args.autotune:
+        pool, procs = cpu_pool(args)        # the workers start before the GPU is touched
     import torch
     dev = torch.device("cuda:0")
     if args.autotune:
@@ -687,30 +1021,47 @@ def main():
         torch.cuda.synchronize()
         say("calibration copy: 268435456 bytes read, 268435456 bytes written")
         del src, dst
-    plain, ctx = plain_single_robot(args, dev)
+    ctx = serving_context(args, dev)
+    head = serving_headline(args, dev, ctx)
     out = {
         "metric": METRIC,
-        "value": plain.pop("value"),
+        "value": head.pop("value"),
         "unit": "points/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": plain.pop("ms_per_step"),
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        "config": {"workload": f"serving: {len(ctx['items'])} robots, maps U{{256..800}}^2 at "
+                               "0.04 m, frames logU[50k, 500k] points (dome LiDAR + 4 depth "
+                               "frustums) from pinned host memory, full path per frame, "
+                               "continuous-batching server under a 32 GiB device budget",
+                   "robots": len(ctx["items"]), "frames_per_step": len(ctx["items"]),
+                   "lanes": args.lanes,
+                   "mode": "closed-loop clients: each robot submits its next frame when the "
+                           "previous one completes"},
     }
-    out.update(plain)
+    out.update(head)
+    if not args.skip_sweep:
+        out["sweep"] = serving_sweep(args, dev, ctx)
+    single_ctx = None
+    if not args.skip_single or not args.skip_features or not args.skip_stress:
+        single, single_ctx = single_robot(args, dev)
+        if not args.skip_single:
+            out["single_robot"] = single
     if not args.skip_features:
-        out["features"] = features(args, dev, ctx)
+        out["features"] = features(args, dev, single_ctx)
     if not args.skip_batched:
         out["batched"] = batched_maps(args, dev, tuning)
-    if not args.skip_server:
-        out["server"] = serving(args, dev, tuning)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args, ctx)
+    if not args.skip_stress:
+        out["stress"] = stress(args, dev, tuning, single_ctx)
+    if pool is not None:
+        out["cpu_baseline"] = cpu_baseline(args, ctx, pool, procs)
+        pool.shutdown()
     print(json.dumps(out), flush=True)
 
 

@@ -410,9 +410,10 @@ emx_status emx_pipeline_batch(emx_batch* batch, const emx_batch_item* items, int
                               void* d_scratch, size_t scratch_bytes, void* stream);
 
 /* ---------------------------------------------------------------- timing
- * Per-kernel timing of the plain calls, for profiling.  Between begin and
- * end, each kernel launched by a plain call is bracketed by two timing
- * events on its own stream; batched calls are not timed.  end waits for the
+ * Per-kernel timing, for profiling.  Between begin and end, each kernel the
+ * library launches directly (plain calls, and batches run with "graph": 0) is
+ * bracketed by two timing events on its own stream; launches captured into a
+ * graph are not timed.  Batched kernels carry the suffix "_b".  end waits for the
  * recorded events and writes a JSON object to buf (len bytes):
  *   {"<kernel>": [launches, total_ms], ...}
  * in order of first launch, then forgets them: a second end without a new

@@ -280,12 +280,18 @@ hipError_t launch_normals_trav(const Item& it, hipStream_t stream) {
 }
 
 hipError_t launch_move_batch(const Batch* d_batch, int grid, hipStream_t stream) {
-  hipLaunchKernelGGL(k_move_b, dim3(grid), dim3(kNTf), 0, stream, d_batch);
+  {
+    TimedLaunch tl("k_move_b", stream);
+    hipLaunchKernelGGL(k_move_b, dim3(grid), dim3(kNTf), 0, stream, d_batch);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_cells_batch(const Batch* d_batch, int grid, hipStream_t stream) {
-  hipLaunchKernelGGL(k_cells_b, dim3(grid), dim3(kNTf), 0, stream, d_batch);
+  {
+    TimedLaunch tl("k_cells_b", stream);
+    hipLaunchKernelGGL(k_cells_b, dim3(grid), dim3(kNTf), 0, stream, d_batch);
+  }
   return hipGetLastError();
 }
 

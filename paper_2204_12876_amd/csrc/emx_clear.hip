@@ -530,10 +530,16 @@ int clear_block_units(int nb) {
 
 hipError_t launch_clear_batch(const Batch* d_batch, int grid_setup, int grid_march,
                               hipStream_t stream) {
-  hipLaunchKernelGGL(k_clear_setup_b, dim3(grid_setup), dim3(kNTc), 0, stream, d_batch);
+  {
+    TimedLaunch tl("k_clear_setup_b", stream);
+    hipLaunchKernelGGL(k_clear_setup_b, dim3(grid_setup), dim3(kNTc), 0, stream, d_batch);
+  }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_clear_march_b, dim3(grid_march), dim3(kNTc), 0, stream, d_batch);
+  {
+    TimedLaunch tl("k_clear_march_b", stream);
+    hipLaunchKernelGGL(k_clear_march_b, dim3(grid_march), dim3(kNTc), 0, stream, d_batch);
+  }
   return hipGetLastError();
 }
 

@@ -653,15 +653,21 @@ hipError_t launch_fuse(const Item& it, hipStream_t stream) {
 
 hipError_t launch_fuse_batch(const Batch* d_batch, bool key64, int grid_chunk, int grid_tile,
                              hipStream_t stream) {
-  if (key64)
-    hipLaunchKernelGGL(k_fuse_chunk_b<uint64_t>, dim3(grid_chunk), dim3(kNT1), 0, stream,
-                       d_batch);
-  else
-    hipLaunchKernelGGL(k_fuse_chunk_b<uint32_t>, dim3(grid_chunk), dim3(kNT1), 0, stream,
-                       d_batch);
+  {
+    TimedLaunch tl("k_fuse_chunk_b", stream);
+    if (key64)
+      hipLaunchKernelGGL(k_fuse_chunk_b<uint64_t>, dim3(grid_chunk), dim3(kNT1), 0, stream,
+                         d_batch);
+    else
+      hipLaunchKernelGGL(k_fuse_chunk_b<uint32_t>, dim3(grid_chunk), dim3(kNT1), 0, stream,
+                         d_batch);
+  }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_fuse_tile_b, dim3(grid_tile), dim3(kNT2), 0, stream, d_batch);
+  {
+    TimedLaunch tl("k_fuse_tile_b", stream);
+    hipLaunchKernelGGL(k_fuse_tile_b, dim3(grid_tile), dim3(kNT2), 0, stream, d_batch);
+  }
   return hipGetLastError();
 }
 

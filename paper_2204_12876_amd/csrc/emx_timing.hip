@@ -1,10 +1,10 @@
-// Optional per-kernel timing of the plain calls.
+// Optional per-kernel timing.
 //
-// While timing is on, every kernel a plain call launches is bracketed by two
-// timing events recorded on the kernel's own stream.  emx_timing_end waits for
-// them and reports, per kernel, the number of launches and the summed
-// duration.  Batched launches are not timed (they may be captured into a
-// graph).  Timing is meant for one host thread driving the library.
+// While timing is on, every kernel the library launches directly is bracketed
+// by two timing events recorded on the kernel's own stream.  emx_timing_end
+// waits for them and reports, per kernel, the number of launches and the
+// summed duration.  Launches into a stream that is being captured into a graph
+// are not timed.  Timing is meant for one host thread driving the library.
 #include <stdio.h>
 #include <string.h>
 
@@ -43,6 +43,8 @@ hipEvent_t take_event() {
 TimedLaunch::TimedLaunch(const char* name, hipStream_t s) : stream_(s), idx_(-1) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   Mark m{name, take_event(), take_event()};
   if (!m.a || !m.b || hipEventRecord(m.a, s) != hipSuccess) {
     if (m.a) g_free.push_back(m.a);

@@ -36,7 +36,8 @@ import torch
 from . import _emx
 
 __all__ = ["AdmissionError", "HbmBudget", "Request", "Server", "GpuExecutor", "FramePool",
-           "run_trace", "run_plain_trace", "latency_summary"]
+           "run_trace", "run_closed_loop", "run_plain_trace", "run_plain_closed_loop",
+           "latency_summary"]
 
 
 class AdmissionError(RuntimeError):
@@ -439,6 +440,42 @@ def run_trace(server: Server, requests: List[Request], timeout_s: float = 120.0)
     return reqs
 
 
+def run_closed_loop(server: Server, make_request, robots, frames_per_robot: int,
+                    timeout_s: float = 120.0) -> List[Request]:
+    """Closed-loop clients: every robot submits its first frame at once and
+    each later frame as soon as its previous one has completed, so the server
+    always has every robot's next frame in hand.  ``make_request(robot, j)``
+    returns the robot's j-th frame; its arrival is set to the submission time.
+    Returns the requests in submission order."""
+    if hasattr(server.ex, "start_clock"):
+        server.ex.start_clock()
+    nxt = {k: 0 for k in robots}
+    out: List[Request] = []
+
+    def submit(k):
+        r = make_request(k, nxt[k])
+        r.arrival = server.ex.now()
+        r.seq = len(out)
+        nxt[k] += 1
+        server.submit(r)
+        out.append(r)
+
+    for k in robots:
+        submit(k)
+    seen = len(server.completed)
+    t_end = server.ex.now() + timeout_s
+    while len(out) < frames_per_robot * len(nxt) or not server.idle():
+        server.poll()
+        while seen < len(server.completed):
+            r = server.completed[seen]
+            seen += 1
+            if nxt[r.robot] < frames_per_robot:
+                submit(r.robot)
+        if server.ex.now() > t_end:
+            raise TimeoutError("closed loop did not finish")
+    return out
+
+
 def run_plain_trace(maps: dict, requests: List[Request], weights: torch.Tensor, device=None,
                     max_points: int = 1_000_000):
     """The per-frame baseline: each frame, at its arrival, is copied to the
@@ -477,6 +514,53 @@ def run_plain_trace(maps: dict, requests: List[Request], weights: torch.Tensor, 
     torch.cuda.synchronize(device)
     for r, e in ends:
         r.done = t0e.elapsed_time(e) / 1e3
+    return reqs
+
+
+def run_plain_closed_loop(maps: dict, make_request, robots, frames_per_robot: int,
+                          weights: torch.Tensor, device=None,
+                          max_points: int = 1_000_000) -> List[Request]:
+    """The per-frame baseline under closed-loop clients: the robots' frames in
+    turn, first frames first, each copied to the device and run through the
+    plain calls on one stream.  A robot's next frame arrives when its previous
+    one completes; on one stream in this order that is always before its turn,
+    so the host never waits.  Arrival and completion times are read from
+    events recorded on the stream."""
+    from . import aligned_empty
+    device = torch.device(device if device is not None else "cuda")
+    st = torch.cuda.current_stream(device)
+    stage = aligned_empty(12 * max_points, device).view(torch.float32)
+    need = max(_emx.scratch_bytes(m.p, max_points) for m in maps.values())
+    scratch = aligned_empty(need, device)
+    torch.cuda.synchronize(device)
+    t0e = torch.cuda.Event(enable_timing=True)
+    t0e.record(st)
+    reqs, ends = [], []
+    for j in range(frames_per_robot):
+        for k in robots:
+            r = make_request(k, j)
+            r.seq = len(reqs)
+            m = maps[k]
+            n = r.n
+            stage[:3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
+            x, y, z = stage[:n], stage[n:2 * n], stage[2 * n:3 * n]
+            m.move_fuse_points(*r.center, x, y, z, r.pose, r.t_ms, scratch=scratch)
+            m.clear_visibility(x, y, z, r.pose, r.t_ms, scratch=scratch)
+            if weights is not None:
+                m.normals_traversability(weights)
+            else:
+                m.compute_normals()
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(st)
+            reqs.append(r)
+            ends.append(e)
+    torch.cuda.synchronize(device)
+    last = {}
+    for r, e in zip(reqs, ends):
+        r.done = t0e.elapsed_time(e) / 1e3
+        r.arrival = last.get(r.robot, 0.0)
+        r.launch = r.arrival
+        last[r.robot] = r.done
     return reqs
 
 

@@ -13,3 +13,102 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+# --------------------------------------------------------------------------
+# the host-side parts of bench.py that run after the GPU legs, on stubs
+# --------------------------------------------------------------------------
+import math  # noqa: E402
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_driver_arguments_parse():
+    a = bench.parse(["--gpus", "1", "--steps", "20", "--warmup", "5"])
+    assert (a.gpus, a.steps, a.warmup) == (1, 20, 5)
+    d = bench.parse([])
+    assert d.steps >= 1 and d.warmup >= 1 and d.gpus == 1
+
+
+def _stub_ctx(n_robots=3, n=1500):
+    """A serving context in bench.py's layout: small maps and pinned-free host
+    frames (the CPU baseline reads them as numpy)."""
+    rng = np.random.default_rng(1)
+    items, host = [], []
+    for k in range(n_robots):
+        params = dict(nx=24 + 4 * k, ny=20, resolution=0.1, noise_alpha=1e-4, gate_k=3.0,
+                      min_range=0.05, ray_step=0.1, clear_normal_alpha=0.3,
+                      clear_min_age_ms=500)
+        xs = rng.uniform(0.2, 1.0, n).astype(np.float32)
+        ys = rng.uniform(-0.8, 0.8, n).astype(np.float32)
+        zs = (-0.5 + 0.01 * rng.normal(size=n)).astype(np.float32)
+        P = np.zeros((3, 4))
+        P[:, :3] = np.eye(3)
+        P[:, 3] = (0.0, 0.0, 0.5)
+        items.append(dict(params=params, rate_hz=20.0))
+        host.append((torch.from_numpy(np.stack([xs, ys, zs])), P, (0.0, 0.0)))
+    return dict(items=items, host=host,
+                stats=[dict(n=n, C=p["params"]["nx"] * 20, touched=10, updated=9) for p in items])
+
+
+def test_cpu_baseline_runs_on_a_stub_workload():
+    args = bench.parse(["--steps", "20", "--warmup", "5", "--cpu-seconds", "0.3",
+                        "--cpu-procs", "2"])
+    pool, procs = bench.cpu_pool(args)
+    try:
+        out = bench.cpu_baseline(args, _stub_ctx(), pool, procs)
+    finally:
+        pool.shutdown()
+    assert out["kind"] == "oracle" and out["unit"] == "points/s"
+    assert out["cores"] == 2 and out["value"] > 0
+    assert out["single_core"]["cores"] == 1 and out["single_core"]["value"] > 0
+    assert out["fusion_128x128_20k"]["reps"] == 20
+    assert "processes" in out["sample"]
+
+
+class _R:
+    def __init__(self, arrival, done, n, robot=0):
+        self.arrival, self.done, self.n, self.robot = arrival, done, n, robot
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+def test_window_summary_counts_only_the_window():
+    reqs = [_R(0.5, 0.6, 10), _R(1.0, 1.01, 100), _R(1.5, 1.52, 100), _R(2.0, 2.5, 999)]
+    s = bench.window_summary(reqs, 1.0, 2.0)
+    assert s["frames"] == 2 and s["points"] == 200
+    assert math.isclose(s["offered_points_per_s"], 200.0)
+    assert math.isclose(s["points_per_s"], 200 / 0.52)
+    assert math.isclose(s["p99_ms"], 1e3 * (0.01 + 0.99 * 0.01), rel_tol=1e-9)
+
+
+def test_poisson_trace_is_seeded_and_sorted():
+    ctx = _stub_ctx()
+    a = bench.poisson_trace(ctx, 2.0)
+    b = bench.poisson_trace(ctx, 2.0)
+    assert a == b and len(a) > 60
+    assert all(x[2] <= y[2] for x, y in zip(a, a[1:]))
+    assert all(0 <= t < 2.0 for _, _, t in a)
+    # per robot, frame indices count up in time order
+    for k in range(3):
+        js = [j for r, j, _ in a if r == k]
+        assert js == list(range(len(js)))
+
+
+def test_roofline_takes_the_kernel_with_the_most_time():
+    kt = {"k_a": [10, 1.0], "k_b": [5, 3.0], "k_c": [1, 9.0]}
+    alg = {"k_a": 1e9, "k_b": 6e9}
+    k = bench.kernel_table(kt, alg)
+    r = bench.roofline(k)
+    assert r["kernel"] == "k_b"                   # k_c has no algorithmic bytes
+    assert math.isclose(r["achieved"], 6e9 / 3e-3 / 1e9)
+    assert math.isclose(r["frac"], r["achieved"] / 8000.0)
+    assert math.isclose(r["alg_bytes_per_launch"], 6e9 / 5)
+    fb = bench.frame_bytes(100, 50, 7, 5, 1.0)
+    assert fb["fuse_chunk"] == 1200 + 56 and fb["fuse_tile"] == 105 + 58 * 50

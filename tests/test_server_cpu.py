@@ -213,3 +213,32 @@ def test_oldest_frames_go_first():
     srv.poll()
     second = sorted(r.robot for r in srv.lanes[0].requests)
     assert second == [0, 1]           # robot 0's second frame, then the next oldest
+
+
+class _AutoClock(SimExecutor):
+    """The simulated clock jumps to the next batch end whenever it is read."""
+
+    def now(self):
+        nxt = [f for f in self.finish if f is not None]
+        if nxt:
+            self.t = max(self.t, min(nxt))
+        return self.t
+
+
+def test_closed_loop_clients_resubmit_on_completion():
+    from paper_2204_12876_amd.server import run_closed_loop
+    ex = _AutoClock(lanes=2, max_items=8, max_batch_points=100_000, pool_points=150_000,
+                    a=3e-4, b=4e-9)
+    srv = Server(ex, 1 << 40)
+    robots = list(range(12))
+    for k in robots:
+        srv.add_map(k, dict(nx=32, ny=32))
+    reqs = run_closed_loop(srv, lambda k, j: _req(k, j, 1000 + 100 * k, 0.0), robots, 5)
+    assert len(reqs) == len(srv.completed) == 60
+    for k in robots:
+        mine = [r for r in reqs if r.robot == k]
+        assert [r.t_ms for r in mine] == list(range(5))
+        # each later frame is submitted only once the previous one has completed
+        assert all(b.arrival >= a.done for a, b in zip(mine, mine[1:]))
+    assert all(r.done >= r.launch >= r.arrival for r in reqs)
+    assert max(srv.batch_sizes) > 1
