@@ -3,10 +3,10 @@
 Headline: the serving workload, continuous batching against per-frame plain
 launches (points fused per second and p99 update latency).
   * 64 simulated robots; maps U{256..800}^2 at 0.04 m; frames of logU[50k, 500k]
-    points (a dome LiDAR plus four depth frustums) copied from pinned host
-    memory; the full per-frame path (move, fusion, visibility clearing,
-    normals, traversability); every map resident in device memory under a
-    32 GiB budget.
+    points (a dome LiDAR plus four depth frustums) already in device memory
+    when the timed region starts; the full per-frame path (move, fusion,
+    visibility clearing, normals, traversability); every map resident in
+    device memory under a 32 GiB budget.
   * One step serves one frame of every robot.  Robots are closed-loop
     clients: each submits its next frame as soon as the previous one has
     completed, so the server always holds every robot's next frame.  W steps
@@ -19,6 +19,8 @@ launches (points fused per second and p99 update latency).
     compression through both, until each stops keeping up.
   * roofline: the dominant kernel of the headline's server run, from a second
     pass of the K steps with every kernel bracketed by events on its stream.
+  * pcie_inclusive: the same closed loop with every frame copied from pinned
+    host memory inside the timed region (server and plain).
 
 Sub-records, each with its plain comparison where one exists:
   * single_robot: the 400x400 map with 300k-point frames through the plain
@@ -80,7 +82,7 @@ def parse(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="oracle seconds per process in the CPU baseline")
     ap.add_argument("--cpu-procs", type=int, default=0, help="0: min(16, host cores)")
-    for leg in ("sweep", "single", "features", "batched", "stress"):
+    for leg in ("pcie", "sweep", "single", "features", "batched", "stress"):
         ap.add_argument(f"--skip-{leg}", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default=None, help="batch tuning JSON (default: the tuned file)")
@@ -202,7 +204,8 @@ def load_tuning(args):
 def serving_context(args, dev):
     """The robots' frames (one per robot, re-sent from its pose; the map centre
     alternates by one cell so that every frame also moves the map), pinned on
-    the host, and per-robot frame statistics for the algorithmic bytes."""
+    the host and resident on the device, and per-robot frame statistics for
+    the algorithmic bytes."""
     import torch
 
     import synth
@@ -214,7 +217,7 @@ def serving_context(args, dev):
     items = d["items"]
     say(f"generated {len(items)} robot frames in {time.perf_counter() - t_gen:.1f} s")
     w = torch.from_numpy(synth.trav_weights()).to(dev)
-    host, stats = [], []
+    host, device, stats = [], [], []
     for it in items:
         f = it["frames"][0]
         xyz = torch.empty((3, f.n), dtype=torch.float32, pin_memory=True)
@@ -222,6 +225,7 @@ def serving_context(args, dev):
         xyz[1].copy_(f.y)
         xyz[2].copy_(f.z)
         host.append((xyz, f.pose, it["centers"][0]))
+        device.append(xyz.to(dev))
         m = ElevationMap(it["params"], *it["centers"][0], 0, device=dev)
         cell = torch.empty(f.n, dtype=torch.int32, device=dev)
         acc = torch.empty(f.n, dtype=torch.uint8, device=dev)
@@ -234,16 +238,20 @@ def serving_context(args, dev):
         stats.append(dict(n=f.n, C=C, touched=np.unique(c[c >= 0]).size,
                           updated=np.unique(c[a]).size))
     largest = max((it["params"] for it in items), key=lambda p: p["nx"] * p["ny"])
-    return dict(items=items, host=host, stats=stats, weights=w, largest=largest,
-                data=d)
+    return dict(items=items, host=host, device=device, stats=stats, weights=w,
+                largest=largest, data=d)
 
 
-def _make_request(ctx, k, j, arrival=0.0, t_off=0):
+def _make_request(ctx, k, j, arrival=0.0, t_off=0, resident=True):
     """Robot k's j-th frame: its one ray-cast frame re-sent from the same pose,
     with the map centre alternating by one cell; frame times increase with j
-    (and with ``t_off`` between replays on the same maps)."""
+    (and with ``t_off`` between replays on the same maps).  ``resident``: the
+    points are already in device memory, else they come from pinned host
+    memory and each run copies them to the device."""
     from paper_2204_12876_amd.server import Request
     xyz, pose, c = ctx["host"][k]
+    if resident:
+        xyz = ctx["device"][k]
     r = ctx["items"][k]["params"]["resolution"]
     cx = c[0] + (r if j % 2 else 0.0)
     return Request(robot=k, xyz=xyz, pose=pose, t_ms=t_off + 100 * (j + 1), center=(cx, c[1]),
@@ -267,9 +275,11 @@ def _plain_maps(ctx, dev):
             for k, it in enumerate(ctx["items"])}
 
 
-def serving_headline(args, dev, ctx):
+def serving_headline(args, dev, ctx, resident=True, kernel_timing=True):
     """Closed-loop saturation: K steps (one frame of every robot per step)
-    through the server, then through the per-frame plain calls."""
+    through the server, then through the per-frame plain calls.  With
+    ``resident`` the frames are in device memory when the timed region
+    starts; without, every frame is copied from pinned host memory inside it."""
     import torch
 
     from paper_2204_12876_amd import _emx
@@ -277,7 +287,7 @@ def serving_headline(args, dev, ctx):
 
     K, W = args.steps, args.warmup
     robots = list(range(len(ctx["items"])))
-    mk = lambda k, j: _make_request(ctx, k, j)        # noqa: E731
+    mk = lambda k, j: _make_request(ctx, k, j, resident=resident)        # noqa: E731
     mx = max(h[0].shape[1] for h in ctx["host"])
 
     # ---- server: W warm-up steps, then K timed steps between synchronisations
@@ -293,25 +303,16 @@ def serving_headline(args, dev, ctx):
     pts = sum(r.n for r in reqs)
     lat = np.array([r.latency for r in reqs])
     batches = list(srv.batch_sizes)
-    say(f"server closed loop: {pts / wall / 1e9:.2f} G points/s, p99 "
+    where = "resident" if resident else "from host"
+    say(f"server closed loop ({where}): {pts / wall / 1e9:.2f} G points/s, p99 "
         f"{pct(lat, 99) * 1e3:.2f} ms, mean batch {np.mean(batches):.1f}")
 
     # ---- per-kernel timing: the same K steps again, every kernel bracketed by
     # events on its stream; algorithmic bytes summed over the frames each
     # launch served
-    _emx.timing_begin()
-    treqs = run_closed_loop(srv, lambda k, j: mk(k, W + K + j), robots, K)
-    kt = _emx.timing_end()
-    alg = {}
-    for r in treqs:
-        s = ctx["stats"][r.robot]
-        names = BATCH_KERNEL if r.batch_items > 1 else PLAIN_KERNEL
-        for role, b in frame_bytes(s["n"], s["C"], s["touched"], s["updated"], 1.0).items():
-            if role == "move":
-                continue                     # every frame fuses: the move runs inside
-            alg[names[role]] = alg.get(names[role], 0.0) + b
-    kernels = kernel_table(kt, alg)
-    roof = roofline(kernels)
+    kernels = roof = None
+    if kernel_timing:
+        kernels, roof = _serving_kernels(ctx, srv, mk, robots, K, W)
     b_stats = ex.graph_stats()
     for m in list(ex.maps):
         ex.drop_map(m)
@@ -328,8 +329,9 @@ def serving_headline(args, dev, ctx):
     plat = np.array([r.latency for r in preqs])
     for m in maps.values():
         m.close()
-    say(f"plain closed loop: {pts / pwall / 1e9:.2f} G points/s, p99 {pct(plat, 99) * 1e3:.2f} ms")
-    return {
+    say(f"plain closed loop ({where}): {pts / pwall / 1e9:.2f} G points/s, p99 "
+        f"{pct(plat, 99) * 1e3:.2f} ms")
+    out = {
         "value": pts / wall,
         "ms_per_step": wall / K * 1e3,
         "maps_per_s": len(reqs) / wall,
@@ -345,9 +347,32 @@ def serving_headline(args, dev, ctx):
                           "normals_traversability) on one stream, frames in turn"},
         "speedup_vs_plain": pwall / wall,
         "points_per_step": pts / K,
-        "kernels": kernels,
-        "roofline": roof,
+        "frames": "resident in device memory before the timed region" if resident else
+                  "copied from pinned host memory inside the timed region",
     }
+    if kernel_timing:
+        out["kernels"] = kernels
+        out["roofline"] = roof
+    return out
+
+
+def _serving_kernels(ctx, srv, mk, robots, K, W):
+    """Per-kernel table and roofline of K more closed-loop steps."""
+    from paper_2204_12876_amd import _emx
+    from paper_2204_12876_amd.server import run_closed_loop
+    _emx.timing_begin()
+    treqs = run_closed_loop(srv, lambda k, j: mk(k, W + K + j), robots, K)
+    kt = _emx.timing_end()
+    alg = {}
+    for r in treqs:
+        s = ctx["stats"][r.robot]
+        names = BATCH_KERNEL if r.batch_items > 1 else PLAIN_KERNEL
+        for role, b in frame_bytes(s["n"], s["C"], s["touched"], s["updated"], 1.0).items():
+            if role == "move":
+                continue                     # every frame fuses: the move runs inside
+            alg[names[role]] = alg.get(names[role], 0.0) + b
+    kernels = kernel_table(kt, alg)
+    return kernels, roofline(kernels)
 
 
 def poisson_trace(ctx, seconds: float, seed: int = 12876 + 3):
@@ -1038,7 +1063,7 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": f"serving: {len(ctx['items'])} robots, maps U{{256..800}}^2 at "
                                "0.04 m, frames logU[50k, 500k] points (dome LiDAR + 4 depth "
-                               "frustums) from pinned host memory, full path per frame, "
+                               "frustums) resident in device memory, full path per frame, "
                                "continuous-batching server under a 32 GiB device budget",
                    "robots": len(ctx["items"]), "frames_per_step": len(ctx["items"]),
                    "lanes": args.lanes,
@@ -1046,6 +1071,9 @@ def main(argv=None):
                            "previous one completes"},
     }
     out.update(head)
+    if not args.skip_pcie:
+        out["pcie_inclusive"] = serving_headline(args, dev, ctx, resident=False,
+                                                 kernel_timing=False)
     if not args.skip_sweep:
         out["sweep"] = serving_sweep(args, dev, ctx)
     single_ctx = None

@@ -122,7 +122,10 @@ class FramePool:
 
 @dataclasses.dataclass
 class Request:
-    """One frame of one robot.  xyz: host float32 [3, n] (pinned for overlap)."""
+    """One frame of one robot.  xyz: float32 [3, n], either in host memory
+    (pinned for overlap; the server stages it on the device) or already in
+    device memory (used in place; it must stay unchanged until the frame
+    completes)."""
     robot: object
     xyz: torch.Tensor
     pose: np.ndarray
@@ -139,6 +142,11 @@ class Request:
     @property
     def n(self) -> int:
         return int(self.xyz.shape[1])
+
+    @property
+    def resident(self) -> bool:
+        """True if the points are already in device memory."""
+        return bool(self.xyz.is_cuda)
 
     def pose12(self):
         """The pose as 12 Python floats (row-major 3x4), computed once."""
@@ -211,7 +219,10 @@ class Server:
     def submit(self, req: Request):
         if req.robot not in self.maps:
             raise AdmissionError(f"robot {req.robot!r} has no admitted map")
-        if req.n > self.ex.max_batch_points or 3 * req.n > self.pool.capacity:
+        if req.resident and (req.xyz.dtype != torch.float32 or not req.xyz.is_contiguous()):
+            raise AdmissionError("a resident frame must be a contiguous float32 [3, n] tensor")
+        if req.n > self.ex.max_batch_points or (not req.resident
+                                                and 3 * req.n > self.pool.capacity):
             raise AdmissionError(f"frame of {req.n} points exceeds the staging limits")
         self.waiting[req.robot].append(req)
         self.ready.add(req.robot)
@@ -232,7 +243,8 @@ class Server:
                     self.inflight.discard(r.robot)
                     self.completed.append(r)
                 for off, size in ln.regions:
-                    self.pool.release(off, size)
+                    if off >= 0:
+                        self.pool.release(off, size)
                 ln.requests, ln.regions, ln.busy = [], [], False
 
     def _form(self) -> List[Request]:
@@ -262,6 +274,10 @@ class Server:
                 break
             regions, taken = [], []
             for r in reqs:
+                if r.resident:                    # no staging: used in place
+                    regions.append((-1, 0))
+                    taken.append(r)
+                    continue
                 off = self.pool.alloc(3 * r.n)
                 if off is None:
                     continue                      # waits for staging room
@@ -374,12 +390,16 @@ class GpuExecutor:
         with torch.cuda.stream(st):
             for k, (r, off) in enumerate(zip(requests, offsets)):
                 n = r.n
-                if n:
-                    self.pool[off:off + 3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
                 it = items[k]
                 it.map = self.maps[r.robot].handle
                 f = it.frame
-                f.x, f.y, f.z = base + 4 * off, base + 4 * (off + n), base + 4 * (off + 2 * n)
+                if off < 0:                           # resident [3, n] rows
+                    b = r.xyz.data_ptr()
+                    f.x, f.y, f.z = b, b + 4 * n, b + 8 * n
+                else:
+                    if n:
+                        self.pool[off:off + 3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
+                    f.x, f.y, f.z = base + 4 * off, base + 4 * (off + n), base + 4 * (off + 2 * n)
                 f.n = n
                 f.pose[:] = r.pose12()
                 f.t_ms = r.t_ms
@@ -397,11 +417,14 @@ class GpuExecutor:
         m = self.maps[r.robot]
         scratch = self.execs[lane].scratch_buffer()
         with torch.cuda.stream(st):
-            if n:
-                self.pool[off:off + 3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
-            x = self.pool[off:off + n]
-            y = self.pool[off + n:off + 2 * n]
-            z = self.pool[off + 2 * n:off + 3 * n]
+            if off < 0:
+                x, y, z = r.xyz[0], r.xyz[1], r.xyz[2]
+            else:
+                if n:
+                    self.pool[off:off + 3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
+                x = self.pool[off:off + n]
+                y = self.pool[off + n:off + 2 * n]
+                z = self.pool[off + 2 * n:off + 3 * n]
             m.move_fuse_points(*r.center, x, y, z, r.pose, r.t_ms, scratch=scratch)
             m.clear_visibility(x, y, z, r.pose, r.t_ms, scratch=scratch)
             if self.weights is not None:
@@ -476,10 +499,21 @@ def run_closed_loop(server: Server, make_request, robots, frames_per_robot: int,
     return out
 
 
+def _plain_points(r: Request, stage: torch.Tensor):
+    """The frame's x, y, z rows on the device: in place if resident, else
+    copied into the staging buffer on the current stream."""
+    if r.resident:
+        return r.xyz[0], r.xyz[1], r.xyz[2]
+    n = r.n
+    stage[:3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
+    return stage[:n], stage[n:2 * n], stage[2 * n:3 * n]
+
+
 def run_plain_trace(maps: dict, requests: List[Request], weights: torch.Tensor, device=None,
                     max_points: int = 1_000_000):
     """The per-frame baseline: each frame, at its arrival, is copied to the
-    device and run through the plain calls on one stream (no batching)."""
+    device (unless already resident) and run through the plain calls on one
+    stream (no batching)."""
     from . import aligned_empty
     device = torch.device(device if device is not None else "cuda")
     reqs = sorted(requests, key=lambda r: (r.arrival, r.seq))
@@ -498,9 +532,7 @@ def run_plain_trace(maps: dict, requests: List[Request], weights: torch.Tensor, 
         while time.perf_counter() - t0 < r.arrival:
             pass
         m = maps[r.robot]
-        n = r.n
-        stage[:3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
-        x, y, z = stage[:n], stage[n:2 * n], stage[2 * n:3 * n]
+        x, y, z = _plain_points(r, stage)
         r.launch = time.perf_counter() - t0
         m.move_fuse_points(*r.center, x, y, z, r.pose, r.t_ms, scratch=scratch)
         m.clear_visibility(x, y, z, r.pose, r.t_ms, scratch=scratch)
@@ -541,9 +573,7 @@ def run_plain_closed_loop(maps: dict, make_request, robots, frames_per_robot: in
             r = make_request(k, j)
             r.seq = len(reqs)
             m = maps[k]
-            n = r.n
-            stage[:3 * n].view(3, n).copy_(r.xyz, non_blocking=True)
-            x, y, z = stage[:n], stage[n:2 * n], stage[2 * n:3 * n]
+            x, y, z = _plain_points(r, stage)
             m.move_fuse_points(*r.center, x, y, z, r.pose, r.t_ms, scratch=scratch)
             m.clear_visibility(x, y, z, r.pose, r.t_ms, scratch=scratch)
             if weights is not None:
