@@ -36,7 +36,7 @@ listed with its reason in the design notes):
     using the cell prior at frame start.  Accept iff e*e <= k2*(v0 + sp2).
   * d is the Euclidean range in the sensor frame; the model is applied as
     sp2 = alpha_d * d^2.
-  * Rejected points leave their cell untouched.
+  * Rejected points leave their cell untouched (unless outlier_variance is set).
   * The first point of an empty cell is fused with the large-variance prior; it
     does not replace it.
   * In Eq. 3, sigma is the standard deviation.  The test is written as
@@ -58,8 +58,15 @@ listed with its reason in the design notes):
   * Time variance sigma_t^2 is added once per fusion to every valid cell the
     fusion does not update.
   * The wall/edge rule counts a frame's valid in-map points per cell before
-    any gate; in cells that hold an estimate and receive more than the
-    threshold, points below the estimate are ignored.
+    any gate (points of the exclusion area are not counted); in cells that
+    hold an estimate and receive more than the threshold, points below the
+    estimate are ignored.
+  * The exclusion area (Fig. 3 is missing from the text): around the sensor
+    origin, a point higher above it than the line b, rising at tan(theta_a)
+    from horizontal distance c on, at most d, is ignored by the fusion.
+  * The outlier check increases the variance (the amount is not given): each
+    cell that holds an estimate and gets at least one gate-rejected point has
+    sigma_o^2 added to its variance once per call, after the fusion.
   * Drift compensation averages z - h over valid in-map points in valid cells
     whose traversability exceeds a threshold, and adds the mean to every valid
     cell's height before fusion.
@@ -103,6 +110,12 @@ class Params:
     clear_min_age_ms: int = 500
     time_variance: float = 0.0     # sigma_t^2 added per fusion to cells it leaves alone
     wall_min_count: int = 0        # wall/edge rule threshold; 0 turns the rule off
+    excl_on: int = 0               # 1: the exclusion area (ramp) drops points above its line
+    excl_theta: float = 0.0        # theta_a, the ramp's angle (rad)
+    excl_b: float = 0.0            # height of the line above the sensor near it (m)
+    excl_c: float = 0.0            # horizontal distance at which the ramp starts (m)
+    excl_d: float = 0.0            # the line's maximum height above the sensor (m)
+    outlier_variance: float = 0.0  # sigma_o^2 added to a cell with gate-rejected points
 
     def __post_init__(self):
         if self.ray_step is None:
@@ -135,6 +148,13 @@ def f32_constants(p: Params) -> dict:
         h_init=F32(p.init_height),
         v_init=F32(p.init_variance),
         var_t=F32(p.time_variance),
+        # the ramp's slope: tan of the float32 angle in float64 (the C
+        # library's tan, through the math module), rounded once to float32
+        excl_slope=F32(math.tan(F64(F32(p.excl_theta)))),
+        excl_b=F32(p.excl_b),
+        excl_c=F32(p.excl_c),
+        excl_d=F32(p.excl_d),
+        var_o=F32(p.outlier_variance),
     )
 
 
@@ -204,8 +224,12 @@ def point_decisions(p: Params, st: MapState, xs, ys, zs, pose):
     Returns a dict with float32 arrays xm, ym, zm, d2, sp2 and the decisions:
       * valid: the coordinates are finite, d2 >= rmin^2 and sp2 is finite;
       * cell: iy*nx + ix for valid in-map points, else -1;
-      * accept: valid, in the map, and inside the Mahalanobis gate against the
-        cell's frame-start prior.
+      * excluded: in the map but above the exclusion area's line (only with
+        excl_on); such points are ignored by everything below;
+      * walled: ignored by the wall/edge rule;
+      * rejected: taken to the gate and outside it (outliers);
+      * accept: valid, in the map, not excluded or walled, and inside the
+        Mahalanobis gate against the cell's frame-start prior.
     """
     xs = np.asarray(xs, F32)
     ys = np.asarray(ys, F32)
@@ -223,19 +247,38 @@ def point_decisions(p: Params, st: MapState, xs, ys, zs, pose):
         cc = np.where(inmap, cell, 0)
         h0 = st.h.reshape(-1)[cc]
         v0 = st.v.reshape(-1)[cc]
+        # Exclusion area (Sec. II-C, Fig. 3; the figure is not in the text, so
+        # this is a stated reading).  Around the sensor origin o = t, with
+        # horizontal distance rho and height e_up above o, the line is
+        #   b              for rho <= c,
+        #   b + tan(theta_a) * (rho - c) beyond, up to at most d.
+        # A point above the line (e_up > line) is ignored: it is neither
+        # counted, gated nor fused.
+        excluded = np.zeros_like(inmap)
+        if p.excl_on:
+            dxr = xm - t[0]
+            dyr = ym - t[1]
+            rho = np.sqrt(dxr * dxr + dyr * dyr)
+            e_up = zm - t[2]
+            line = np.minimum(c["excl_b"] + c["excl_slope"] * np.maximum(rho - c["excl_c"], F32(0)),
+                              c["excl_d"])
+            excluded = inmap & (e_up > line)
+        kept = inmap & ~excluded
         e = zm - h0
-        accept = inmap & ((e * e) <= (c["k2"] * (v0 + sp2)))
+        inside = (e * e) <= (c["k2"] * (v0 + sp2))
         # Wall/edge rule (Sec. II-C): where more than wall_min_count of the
-        # frame's valid points fall into one cell that holds an estimate, the
+        # frame's kept points fall into one cell that holds an estimate, the
         # points below that estimate are ignored.  It acts before the gate.
-        walled = np.zeros_like(accept)
+        walled = np.zeros_like(inmap)
         if p.wall_min_count > 0:
-            count = np.bincount(cell[inmap], minlength=p.nx * p.ny)
+            count = np.bincount(cell[kept], minlength=p.nx * p.ny)
             crowded = (count[cc] > p.wall_min_count) & (st.valid.reshape(-1)[cc] != 0)
-            walled = inmap & crowded & (zm < h0)
-            accept = accept & ~walled
+            walled = kept & crowded & (zm < h0)
+        gated = kept & ~walled
+        accept = gated & inside
+        rejected = gated & ~inside
     return dict(xm=xm, ym=ym, zm=zm, d2=d2, sp2=sp2, valid=valid, cell=cell,
-                accept=accept, walled=walled, R=R, t=t)
+                accept=accept, walled=walled, excluded=excluded, rejected=rejected, R=R, t=t)
 
 
 @dataclasses.dataclass
@@ -301,7 +344,19 @@ def fuse(p: Params, st: MapState, xs, ys, zs, pose, t_ms: int) -> FuseResult:
         grow = ~upd & (st.valid.reshape(-1) != 0)
         v_keep = np.where(grow, v_keep + c32["var_t"], v_keep)
         v1 = np.where(grow, v_keep.astype(F64), v1)
-    new.v = np.where(upd, v1, v_keep).astype(F32).reshape(p.ny, p.nx)
+    v_out = np.where(upd, v1, v_keep).astype(F32)
+    # Outlier variance (Sec. II-C: the outlier check "increases the variance of
+    # the cell"; the amount is not given, so this is a stated reading): a cell
+    # that holds an estimate when the call starts and gets at least one
+    # gate-rejected point in the frame has sigma_o^2 added to its variance,
+    # once per call, after the fusion and the time variance (one float32
+    # addition).
+    if p.outlier_variance != 0.0:
+        hit = np.bincount(cell[d["rejected"]], minlength=C) > 0
+        inflate = hit & (st.valid.reshape(-1) != 0)
+        v_out = np.where(inflate, v_out + c32["var_o"], v_out)
+        v1 = np.where(inflate, v_out.astype(F64), v1)
+    new.v = v_out.reshape(p.ny, p.nx)
     new.valid = np.where(upd, 1, st.valid.reshape(-1)).astype(np.uint8).reshape(p.ny, p.nx)
     new.t_upd = np.where(upd, t_now, st.t_upd.reshape(-1)).astype(np.int32).reshape(p.ny, p.nx)
     shp = (p.ny, p.nx)

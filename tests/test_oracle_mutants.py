@@ -16,7 +16,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE_TESTS = ["test_oracle_fusion.py", "test_oracle_cells.py", "test_oracle_next.py",
-                "test_oracle_post.py"]
+                "test_oracle_post.py", "test_oracle_ramp.py"]
 
 # (name, file in oracle/, text, replacement[, times the text occurs])
 MUTANTS = [
@@ -37,7 +37,7 @@ MUTANTS = [
     ("time variance on updated cells too", "elevation.py",
      "grow = ~upd & (st.valid.reshape(-1) != 0)", "grow = st.valid.reshape(-1) != 0"),
     ("wall rule keeps points above", "elevation.py",
-     "walled = inmap & crowded & (zm < h0)", "walled = inmap & crowded & (zm > h0)"),
+     "walled = kept & crowded & (zm < h0)", "walled = kept & crowded & (zm > h0)"),
     ("ray end cell not skipped", "elevation.py",
      "keep = (cs >= 0) & (cs != end_cell[rep])", "keep = cs >= 0"),
     ("clearing ignores the variance", "elevation.py",
@@ -76,8 +76,8 @@ MUTANTS = [
     ("Gaussian with sigma, not sigma squared", "filters.py",
      "w = np.exp(-(i * i) / (2.0 * s * s))", "w = np.exp(-(i * i) / (2.0 * s))"),
     ("gate boundary exclusive", "elevation.py",
-     'accept = inmap & ((e * e) <= (c["k2"] * (v0 + sp2)))',
-     'accept = inmap & ((e * e) < (c["k2"] * (v0 + sp2)))'),
+     'inside = (e * e) <= (c["k2"] * (v0 + sp2))',
+     'inside = (e * e) < (c["k2"] * (v0 + sp2))'),
     ("fused height from the x row", "elevation.py",
      "zm64 = R[2, 0] * x64 + R[2, 1] * y64 + R[2, 2] * z64 + t[2]",
      "zm64 = R[0, 0] * x64 + R[2, 1] * y64 + R[2, 2] * z64 + t[2]"),
@@ -104,6 +104,27 @@ MUTANTS = [
      "return _windows(x, ksize)[:, :, ksize // 2, :].mean(axis=2)"),
     ("median by mean", "filters.py",
      "out = np.median(w, axis=2)", "out = np.mean(w, axis=2)"),
+    ("exclusion line inclusive", "elevation.py",
+     "excluded = inmap & (e_up > line)", "excluded = inmap & (e_up >= line)"),
+    ("ramp without its start", "elevation.py",
+     'np.maximum(rho - c["excl_c"], F32(0))', '(rho - c["excl_c"])'),
+    ("ramp without its cap", "elevation.py",
+     'c["excl_d"])', "F32(np.inf))"),
+    ("ramp distance in 3-D", "elevation.py",
+     "rho = np.sqrt(dxr * dxr + dyr * dyr)",
+     "rho = np.sqrt(dxr * dxr + dyr * dyr + (zm - t[2]) * (zm - t[2]))"),
+    ("ramp around the map corner", "elevation.py", "dxr = xm - t[0]", "dxr = xm"),
+    ("ramp points counted by the wall rule", "elevation.py",
+     "count = np.bincount(cell[kept], minlength=p.nx * p.ny)",
+     "count = np.bincount(cell[inmap], minlength=p.nx * p.ny)"),
+    ("outlier variance per rejected point", "elevation.py",
+     'v_out = np.where(inflate, v_out + c32["var_o"], v_out)',
+     'v_out = np.where(inflate, v_out + c32["var_o"] * np.bincount(cell[d["rejected"]], '
+     'minlength=C).astype(F32), v_out)'),
+    ("outlier variance on cells without an estimate", "elevation.py",
+     "inflate = hit & (st.valid.reshape(-1) != 0)", "inflate = hit"),
+    ("wall-rule points count as outliers", "elevation.py",
+     "rejected = gated & ~inside", "rejected = kept & ~inside"),
 ]
 
 
