@@ -210,6 +210,25 @@ emx_status emx_fuse_points(emx_map* map, const emx_frame* frame, void* d_scratch
                            size_t scratch_bytes, int32_t* d_out_cell,
                            uint8_t* d_out_accept, void* stream);
 
+/* emx_fuse_points without a scratch argument and without any allocation.
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ *   Scratch: a built-in device array of emx_noalloc_scratch_limit() bytes
+ *   (64 MiB), one per GPU, held from the first call on that GPU until the
+ *   process ends.  A frame whose fusion scratch on this map
+ *   (emx_scratch_bytes' fusion part) exceeds it is refused with EMX_ENOMEM and
+ *   nothing is enqueued: about 6M points on a 400x400 map.
+ *   Every call on one GPU shares that GPU's array.  Calls that overlap on one
+ *   GPU (on different streams, or from different threads without ordering)
+ *   race on it; calls in order on one stream do not.
+ *   Results are those of emx_fuse_points, bit for bit.  The call allocates
+ *   nothing on the device or through any library; its first call on a GPU
+ *   looks up the array's device address (hipGetSymbolAddress).
+ * Other arguments, checks and errors are as for emx_fuse_points. */
+size_t emx_noalloc_scratch_limit(void);
+emx_status emx_fuse_points_noalloc(emx_map* map, const emx_frame* frame, int32_t* d_out_cell,
+                                   uint8_t* d_out_accept, void* stream);
+
 /* emx_move_map(map, cx, cy) then emx_fuse_points(map, frame, ...), with the
  * results of the two calls bit for bit.  The move runs inside the fusion's
  * passes (the prior is read through the shift and each moved cell is written

@@ -106,6 +106,19 @@ class ElevationMap:
                          out_accept.data_ptr() if out_accept is not None else 0,
                          _stream(self.device))
 
+    def fuse_points_noalloc(self, x, y, z, pose, t_ms: int, out_cell: torch.Tensor = None,
+                            out_accept: torch.Tensor = None):
+        """fuse_points on the library's built-in scratch: allocates nothing."""
+        f, n = self._frame(x, y, z, pose, t_ms)
+        if out_cell is not None and (out_cell.dtype != torch.int32 or out_cell.numel() < n):
+            raise ValueError("out_cell must be int32 with n elements")
+        if out_accept is not None and (out_accept.dtype != torch.uint8 or out_accept.numel() < n):
+            raise ValueError("out_accept must be uint8 with n elements")
+        _emx.fuse_points_noalloc(self.handle, f,
+                                 out_cell.data_ptr() if out_cell is not None else 0,
+                                 out_accept.data_ptr() if out_accept is not None else 0,
+                                 _stream(self.device))
+
     def compensate_drift(self, x, y, z, pose, t_ms: int, trav_min: float,
                          scratch: torch.Tensor = None):
         """Shift the valid heights by the frame's mean error on flat ground

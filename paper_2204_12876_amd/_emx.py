@@ -72,6 +72,9 @@ _SIGS = {
     "emx_move_map": (c_int32, [c_void_p, c_double, c_double, c_void_p]),
     "emx_fuse_points": (c_int32, [c_void_p, POINTER(Frame), c_void_p, c_size_t, c_void_p,
                                   c_void_p, c_void_p]),
+    "emx_noalloc_scratch_limit": (c_size_t, []),
+    "emx_fuse_points_noalloc": (c_int32, [c_void_p, POINTER(Frame), c_void_p, c_void_p,
+                                          c_void_p]),
     "emx_move_fuse_points": (c_int32, [c_void_p, c_double, c_double, POINTER(Frame), c_void_p,
                                        c_size_t, c_void_p, c_void_p, c_void_p]),
     "emx_clear_visibility": (c_int32, [c_void_p, POINTER(Frame), c_void_p, c_size_t, c_void_p,
@@ -207,6 +210,15 @@ def fuse_points(h: int, f: Frame, d_scratch: int, nbytes: int, d_out_cell: int,
     check(lib().emx_fuse_points(c_void_p(h), byref(f), c_void_p(d_scratch), nbytes,
                                 c_void_p(d_out_cell or None), c_void_p(d_out_accept or None),
                                 c_void_p(stream)))
+
+
+def noalloc_scratch_limit() -> int:
+    return int(lib().emx_noalloc_scratch_limit())
+
+
+def fuse_points_noalloc(h: int, f: Frame, d_out_cell: int, d_out_accept: int, stream: int):
+    check(lib().emx_fuse_points_noalloc(c_void_p(h), byref(f), c_void_p(d_out_cell or None),
+                                        c_void_p(d_out_accept or None), c_void_p(stream)))
 
 
 SMOOTH_BOX, SMOOTH_GAUSSIAN, SMOOTH_MEDIAN = 0, 1, 2

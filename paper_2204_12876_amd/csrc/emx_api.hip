@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -360,6 +361,62 @@ emx_status emx_fuse_points(emx_map* m, const emx_frame* f, void* d_scratch, size
                            int32_t* d_out_cell, uint8_t* d_out_accept, void* stream) {
   return fuse_impl(m, f, false, 0.0, 0.0, d_scratch, scratch_bytes, d_out_cell, d_out_accept,
                    stream);
+}
+
+}  // extern "C"
+
+// Built-in fusion scratch for callers that cannot allocate.  Every GPU the
+// library runs on holds its own copy of this array until the process ends.
+// In host code the array's name is only a stand-in for the device address:
+// the address is looked up once per device and kept in g_noalloc_ptr.
+namespace {
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+constexpr int kNoallocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoallocMaxDevices] = {};
+
+// The current device's copy of the built-in scratch, looked up on first use.
+emx_status noalloc_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kNoallocMaxDevices)
+    return fail(EMX_EINVAL, "device %d is beyond the %d devices the built-in scratch serves", dev,
+                kNoallocMaxDevices);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(EMX_EHIP, "hipGetSymbolAddress(scratch) gave NULL");
+    g_noalloc_ptr[dev] = ptr;
+  }
+  *out = g_noalloc_ptr[dev];
+  return EMX_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t emx_noalloc_scratch_limit(void) { return kNoallocScratchBytes; }
+
+emx_status emx_fuse_points_noalloc(emx_map* m, const emx_frame* f, int32_t* d_out_cell,
+                                   uint8_t* d_out_accept, void* stream) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if ((s = check_frame(f)) != EMX_OK) return s;
+  const int64_t count_cells = m->p.wall_min_count > 0 ? (int64_t)m->p.nx * m->p.ny : 0;
+  const size_t need = fuse_scratch_layout(f->n, tiles_of(m->p), count_cells, nullptr, nullptr);
+  if (need > kNoallocScratchBytes)
+    return fail(EMX_ENOMEM,
+                "frame of %lld points needs %zu bytes of fusion scratch on this map; the "
+                "built-in scratch holds %zu",
+                (long long)f->n, need, kNoallocScratchBytes);
+  void* d_scratch = nullptr;
+  if ((s = noalloc_scratch(&d_scratch)) != EMX_OK) return s;
+  return fuse_impl(m, f, false, 0.0, 0.0, d_scratch, kNoallocScratchBytes, d_out_cell,
+                   d_out_accept, stream);
 }
 
 emx_status emx_move_fuse_points(emx_map* m, double cx, double cy, const emx_frame* f,
