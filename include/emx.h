@@ -89,6 +89,16 @@ typedef struct {
                              /* points below its height are ignored; >= 0, 0 off     */
   int32_t upper_bound;       /* 1: keep the upper bound layer (Sec. II-H), updated   */
                              /* by emx_clear_visibility; 0: no such layer            */
+  int32_t excl_on;           /* 1: exclusion area (Sec. II-C, Fig. 3): fusion ignores */
+                             /* points above the line below; 0 off                   */
+  float excl_theta;          /* theta_a, the line's angle, rad, in [0, pi/2)         */
+  float excl_b;              /* the line's height above the sensor near it, m        */
+  float excl_c;              /* horizontal distance where the line starts to rise, m */
+  float excl_d;              /* the line's greatest height above the sensor, m       */
+  float outlier_variance;    /* sigma_o^2 (Sec. II-C, the outlier check "increases   */
+                             /* the variance"): added once per fuse call to each     */
+                             /* cell that is valid when the call starts and gets a   */
+                             /* gate-rejected point; >= 0, 0 off                     */
 } emx_params;
 
 /* One point cloud in the sensor frame, structure of arrays. */
@@ -189,20 +199,33 @@ emx_status emx_move_map(emx_map* map, double cx, double cy, void* stream);
  *   Gate: e = zm - h0[cell]; accept iff e*e <= k2*(v0[cell] + sp2), with
  *   k2 = float32(gate_k^2).  h0 and v0 are the map's values when the call
  *   starts.
+ *   Exclusion area (excl_on = 1; the figure defining it is not in the text,
+ *   so this is the library's reading of theta_a, b, c, d): with the sensor
+ *   origin o = t32,
+ *     rho = sqrt((xm-o.x)*(xm-o.x) + (ym-o.y)*(ym-o.y));  e = zm - o.z
+ *     line = fminf(b + s*fmaxf(rho - c, 0), d),  s = float32(tan(theta_a))
+ *   an in-map point with e > line is ignored: not counted, gated or fused
+ *   (its cell is still reported in d_out_cell).
  *   Wall/edge rule (wall_min_count > 0): a cell that is valid when the call
- *   starts and receives more than wall_min_count of the frame's valid points
- *   ignores those with zm < h0, before the gate (they are not accepted).
+ *   starts and receives more than wall_min_count of the frame's valid,
+ *   not-ignored points ignores those with zm < h0, before the gate (they are
+ *   not accepted).
  * Per cell c with a non-empty accepted set A:
  *   W = 1/v0 + sum_A 1/sp2;  v = 1/W;  h = (h0/v0 + sum_A zm/sp2) * v
  *   valid = 1, t_upd = t_ms - t0.
  *   This equals Eq. 1 and 2 applied point by point, in exact arithmetic.
  *   The float32 sums are formed in a fixed order of the points.  That order
- *   depends only on the frame (chunks of 1024 points in index order: a
- *   segmented scan over a chunk's points sorted by cell and index, then chunk
+ *   depends only on the frame and the map's placement (chunks of 1024 points
+ *   in index order: within a chunk, a segmented scan over its accepted points
+ *   in order sums each run of consecutive points in one cell, and a second
+ *   one over the runs sorted by cell sums each cell's runs; then chunk
  *   partials in chunk order), so results are identical from run to run and
  *   across batching.
  * Cells with no accepted point are left bitwise unchanged, except that with
  * time_variance > 0 each valid one gets v = v + float32(time_variance).
+ * With outlier_variance > 0, each cell that is valid when the call starts and
+ * gets a point that reaches the gate and fails it gets, after the above,
+ * v = v + float32(outlier_variance), once per call.
  *   d_scratch:    >= emx_scratch_bytes(params, frame->n) bytes, 256-aligned.
  *   d_out_cell:   optional int32[n]: cell, or -1 (dropped or outside).
  *   d_out_accept: optional uint8[n]: 1 iff the point passed the gate. */
@@ -217,7 +240,7 @@ emx_status emx_fuse_points(emx_map* map, const emx_frame* frame, void* d_scratch
  *   (64 MiB), one per GPU, held from the first call on that GPU until the
  *   process ends.  A frame whose fusion scratch on this map
  *   (emx_scratch_bytes' fusion part) exceeds it is refused with EMX_ENOMEM and
- *   nothing is enqueued: about 6M points on a 400x400 map.
+ *   nothing is enqueued: about 5M points on a 400x400 map.
  *   Every call on one GPU shares that GPU's array.  Calls that overlap on one
  *   GPU (on different streams, or from different threads without ordering)
  *   race on it; calls in order on one stream do not.
@@ -230,11 +253,10 @@ emx_status emx_fuse_points_noalloc(emx_map* map, const emx_frame* frame, int32_t
                                    uint8_t* d_out_accept, void* stream);
 
 /* emx_move_map(map, cx, cy) then emx_fuse_points(map, frame, ...), with the
- * results of the two calls bit for bit.  The move runs inside the fusion's
- * passes (the prior is read through the shift and each moved cell is written
- * by the thread that updates it), which saves a pass over the map.  The pose
- * is taken relative to the moved map.  Arguments are as for the two calls;
- * everything is checked before anything is enqueued. */
+ * results of the two calls bit for bit, checked as one call: everything is
+ * checked before anything is enqueued, so a refused call moves nothing.  The
+ * pose is taken relative to the moved map.  Arguments are as for the two
+ * calls. */
 emx_status emx_move_fuse_points(emx_map* map, double cx, double cy, const emx_frame* frame,
                                 void* d_scratch, size_t scratch_bytes, int32_t* d_out_cell,
                                 uint8_t* d_out_accept, void* stream);

@@ -40,7 +40,9 @@ class Params(Structure):
                 ("gate_k", c_float), ("min_range", c_float), ("ray_step", c_float),
                 ("clear_normal_alpha", c_float), ("clear_min_age_ms", c_int32),
                 ("time_variance", c_float), ("wall_min_count", c_int32),
-                ("upper_bound", c_int32)]
+                ("upper_bound", c_int32), ("excl_on", c_int32), ("excl_theta", c_float),
+                ("excl_b", c_float), ("excl_c", c_float), ("excl_d", c_float),
+                ("outlier_variance", c_float)]
 
 
 class Frame(Structure):
@@ -158,6 +160,12 @@ def make_params(d: dict) -> Params:
     p.time_variance = float(d.get("time_variance", 0.0))
     p.wall_min_count = int(d.get("wall_min_count", 0))
     p.upper_bound = int(d.get("upper_bound", 0))
+    p.excl_on = int(d.get("excl_on", 0))
+    p.excl_theta = float(d.get("excl_theta", 0.0))
+    p.excl_b = float(d.get("excl_b", 0.0))
+    p.excl_c = float(d.get("excl_c", 0.0))
+    p.excl_d = float(d.get("excl_d", 0.0))
+    p.outlier_variance = float(d.get("outlier_variance", 0.0))
     return p
 
 

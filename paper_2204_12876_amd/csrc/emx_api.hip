@@ -63,6 +63,17 @@ emx_status check_params(const emx_params* p) {
   if (p->wall_min_count < 0) return fail(EMX_EINVAL, "wall_min_count must be >= 0");
   if (p->upper_bound != 0 && p->upper_bound != 1)
     return fail(EMX_EINVAL, "upper_bound must be 0 or 1");
+  if (p->excl_on != 0 && p->excl_on != 1) return fail(EMX_EINVAL, "excl_on must be 0 or 1");
+  if (p->excl_on) {
+    if (!isfinite(p->excl_theta) || p->excl_theta < 0.0f || p->excl_theta >= 1.5707963f)
+      return fail(EMX_EINVAL, "excl_theta must lie in [0, pi/2)");
+    if (!isfinite(p->excl_b) || !isfinite(p->excl_c) || !isfinite(p->excl_d))
+      return fail(EMX_EINVAL, "excl_b, excl_c, excl_d must be finite");
+    if (!isfinite((float)tan((double)p->excl_theta)))
+      return fail(EMX_EINVAL, "tan(excl_theta) overflows float32");
+  }
+  if (!isfinite(p->outlier_variance) || p->outlier_variance < 0.0f)
+    return fail(EMX_EINVAL, "outlier_variance must be >= 0");
   return EMX_OK;
 }
 
@@ -84,6 +95,12 @@ Consts make_consts(const emx_params& p) {
   c.tau = p.clear_min_age_ms;
   c.var_t = p.time_variance;
   c.wall = p.wall_min_count;
+  c.excl_on = p.excl_on;
+  c.excl_slope = p.excl_on ? (float)tan((double)p.excl_theta) : 0.0f;
+  c.excl_b = p.excl_b;
+  c.excl_c = p.excl_c;
+  c.excl_d = p.excl_d;
+  c.var_o = p.outlier_variance;
   return c;
 }
 
@@ -111,9 +128,11 @@ size_t set_layout(const emx_params& p, char* base, Layers* L) {
   return 7 * l4 + 2 * l1 + lb + (p.upper_bound ? l4 : 0);
 }
 
-size_t clr_bytes(const emx_params& p) { return align256((size_t)p.nx * (size_t)p.ny * 16); }
+size_t clr_bytes(const emx_params& p) { return align256((size_t)p.nx * (size_t)p.ny * 8); }
 
 int tiles_of(const emx_params& p) { return tiles_x_of(p.nx) * tiles_y_of(p.ny); }
+
+int64_t ctl_words(const emx_params& p) { return (int64_t)kCtlWords + tiles_of(p); }
 
 // A persistent grid of per_cu workgroups per compute unit of the current device.
 int persistent_grid(int per_cu) {
@@ -158,6 +177,7 @@ emx_status make_item(const emx_map* m, const emx_frame* f, Item* it) {
   it->nb = it->bx * it->by;
   it->bpw = clear_blocks_per_wave(it->nb);
   it->nprep = clear_block_units(it->nb);
+  it->fs.tcnt = m->ctl + kCtlWords;
   if (!f) return EMX_OK;
   for (int k = 0; k < 12; ++k)
     if (!isfinite(f->pose[k])) return fail(EMX_EINVAL, "pose has a non-finite entry");
@@ -207,8 +227,8 @@ emx_status emx_params_check(const emx_params* params) { return check_params(para
 
 size_t emx_state_bytes(const emx_params* params) {
   if (check_params(params) != EMX_OK) return 0;
-  return 2 * set_layout(*params, nullptr, nullptr) + clr_bytes(*params) +
-         kCtlWords * sizeof(uint32_t);
+  return align256(2 * set_layout(*params, nullptr, nullptr) + clr_bytes(*params) +
+                  ctl_words(*params) * sizeof(uint32_t));
 }
 
 size_t emx_scratch_bytes(const emx_params* params, int64_t max_points) {
@@ -254,14 +274,15 @@ emx_status emx_init_map(const emx_params* params, double cx, double cy, int64_t 
   m->set_bytes = set_layout(*params, nullptr, nullptr);
   set_layout(*params, m->state, &m->sets[0]);
   set_layout(*params, m->state + m->set_bytes, &m->sets[1]);
-  float4* clr = (float4*)(m->state + 2 * m->set_bytes);
+  float2* clr = (float2*)(m->state + 2 * m->set_bytes);
   m->sets[0].clr = clr;
   m->sets[1].clr = clr;
   m->cur = 0;
   m->ctr_sel = 0;
   m->ctl = (uint32_t*)(m->state + 2 * m->set_bytes + clr_bytes(*params));
   m->march_grid = persistent_grid(kMarchPerCU);
-  hipError_t e = launch_fill_prior(m->c, m->sets[0], m->ctl, kCtlWords, (hipStream_t)stream);
+  hipError_t e =
+      launch_fill_prior(m->c, m->sets[0], m->ctl, (int)ctl_words(*params), (hipStream_t)stream);
   if (e != hipSuccess) {
     delete m;
     return hip_fail(e, "init_map");
@@ -300,9 +321,7 @@ emx_status emx_move_map(emx_map* m, double cx, double cy, void* stream) {
 }
 
 // fuse_points, optionally preceded by the move to (cx, cy).  Every argument
-// is checked before anything is enqueued.  With a non-zero shift and points,
-// the move runs inside the fusion: pass 1 reads the prior through the shift
-// and pass 2 writes every moved cell before updating it.
+// is checked before anything is enqueued, so a refused call moves nothing.
 static emx_status fuse_impl(emx_map* m, const emx_frame* f, bool move, double cx, double cy,
                             void* d_scratch, size_t scratch_bytes, int32_t* d_out_cell,
                             uint8_t* d_out_accept, void* stream) {
@@ -326,7 +345,7 @@ static emx_status fuse_impl(emx_map* m, const emx_frame* f, bool move, double cx
   it.Lsrc = m->sets[m->cur];
   it.sx = sx;
   it.sy = sy;
-  const bool run = f->n > 0 || m->p.time_variance != 0.0f;
+  const bool run = f->n > 0 || m->p.time_variance != 0.0f;  // time variance: every call
   if (f->n > 0) {
     const int64_t count_cells = m->p.wall_min_count > 0 ? (int64_t)m->p.nx * m->p.ny : 0;
     const size_t need = fuse_scratch_layout(f->n, it.T, count_cells, nullptr, nullptr);
@@ -341,13 +360,8 @@ static emx_status fuse_impl(emx_map* m, const emx_frame* f, bool move, double cx
   it.out_accept = d_out_accept;
   it.stages = kStageFuse;
   hipError_t e = hipSuccess;
-  if (shift && f->n > 0) {
-    it.fuse_move = 1;
-    e = launch_fuse(it, (hipStream_t)stream);
-  } else {
-    if (shift) e = launch_move(it, (hipStream_t)stream);
-    if (e == hipSuccess && run) e = launch_fuse(it, (hipStream_t)stream);
-  }
+  if (shift) e = launch_move(it, (hipStream_t)stream);
+  if (e == hipSuccess && run) e = launch_fuse(it, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, move ? "move_fuse_points" : "fuse_points");
   if (shift) {
     m->cur = moved.cur;
@@ -442,7 +456,6 @@ emx_status emx_clear_visibility(emx_map* m, const emx_frame* f, void* d_scratch,
       return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
     clear_scratch_layout(f->n, kDefaultSeg, (char*)d_scratch, &it.cq);
   }
-  it.cq.ray_item = nullptr;
   it.cq.counter = m->ctl + m->ctr_sel * kCtrWords;
   it.cq.counter_next = m->ctl + (1 - m->ctr_sel) * kCtrWords;
   it.cq.seg = kDefaultSeg;

@@ -7,8 +7,10 @@
 // Then, on the caller's stream:
 //   - one copy of the table's header and its n items into the caller's
 //     scratch;
-//   - one graph of seven persistent launches: move, fusion pass 1, fusion
-//     pass 2, clearing setup, march and apply, then normals + traversability.
+//   - one graph of persistent launches: move, the wall rule's counts (zeroed,
+//     then counted) if a map uses it, fusion pass 1 and pass 2, the per-cell
+//     variances if a map uses time or outlier variance, clearing setup and
+//     march, then normals + traversability.
 // Every launch finds its work in the table, so a graph depends only on the
 // scratch address, the sort key width and the grid sizes.  Each stage's grid
 // is the tuned size capped at the stage's work rounded up to a power of two,
@@ -60,14 +62,17 @@ bool json_int(const char* js, const char* key, int* out) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// grid: move, zero, count, chunk, tile, variance, setup, march, cells
+constexpr int kGrids = 9;
+
 struct GraphKey {
   void* scratch;
   int key64;
-  int grid[6];
+  int grid[kGrids];
 
   bool operator==(const GraphKey& o) const {
     if (scratch != o.scratch || key64 != o.key64) return false;
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < kGrids; ++i)
       if (grid[i] != o.grid[i]) return false;
     return true;
   }
@@ -106,11 +111,6 @@ emx_status check_items(const emx_batch_item* items, int32_t n) {
     if (s != EMX_OK) return s;
     if (items[i].stages & ~(uint32_t)EMX_STAGE_ALL)
       return fail(EMX_EINVAL, "item %d: unknown stage bits", i);
-    if (items[i].map->p.time_variance != 0.0f || items[i].map->p.wall_min_count != 0 ||
-        items[i].map->p.upper_bound != 0)
-      return fail(EMX_EINVAL,
-                  "item %d: maps with time_variance, wall_min_count or upper_bound use the "
-                  "plain calls", i);
     if ((items[i].stages & (EMX_STAGE_FUSE | EMX_STAGE_CLEAR)) &&
         (s = check_frame(&items[i].frame)) != EMX_OK)
       return s;
@@ -138,14 +138,19 @@ size_t batch_layout(const emx_batch_item* items, int32_t n, int seg, char* base,
   for (int32_t i = 0; i < n; ++i) {
     const int64_t np = frame_points(items[i]);
     if (items[i].stages & EMX_STAGE_FUSE) {
-      const size_t f = fuse_scratch_layout(np, tiles_of(items[i].map->p), 0, nullptr, nullptr);
-      if (tab && base)
-        fuse_scratch_layout(np, tiles_of(items[i].map->p), 0, base + off, &tab->items[i].fs);
+      const emx_params& mp = items[i].map->p;
+      const int64_t cc = mp.wall_min_count > 0 ? (int64_t)mp.nx * mp.ny : 0;
+      const size_t f = fuse_scratch_layout(np, tiles_of(mp), cc, nullptr, nullptr);
+      if (tab && base) fuse_scratch_layout(np, tiles_of(mp), cc, base + off, &tab->items[i].fs);
       off = align256(off + f);
     }
-    if (tab) tab->items[i].ray_base = rays;
+    if (tab) {
+      tab->items[i].ray_base = rays;
+      tab->rays[i] = rays;
+    }
     if (items[i].stages & EMX_STAGE_CLEAR) rays += np;
   }
+  if (tab) tab->rays[n] = rays;
   ClearQueue cq = {};
   const size_t c = clear_scratch_layout(rays, seg, base ? base + off : nullptr, &cq);
   if (tab && base)
@@ -263,7 +268,9 @@ size_t emx_batch_scratch_bound(const emx_batch* b, const emx_params* largest, in
   // Every item's chunk count is at most n_i / kChunk + 1 and its fusion
   // arrays are each padded by under 256 bytes, plus the item's own padding.
   const int64_t recs = max_points + (int64_t)max_items * kChunk;
-  const size_t fuse = fuse_scratch_layout(recs, tiles_of(*largest), 0, nullptr, nullptr) +
+  const int64_t cc =
+      largest->wall_min_count > 0 ? (int64_t)max_items * largest->nx * largest->ny : 0;
+  const size_t fuse = fuse_scratch_layout(recs, tiles_of(*largest), cc, nullptr, nullptr) +
                       (size_t)max_items * 5 * 256;
   return align256(kCounterOffset + kCounterBytes) + fuse +
          clear_scratch_layout(max_points, b->tune.seg, nullptr, nullptr);
@@ -349,12 +356,18 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
     const bool moved = (st & EMX_STAGE_MOVE) && (it.sx != 0 || it.sy != 0);
     const bool fuse = (st & EMX_STAGE_FUSE) && it.n > 0;
     const bool clear = (st & EMX_STAGE_CLEAR) != 0;
-    // a move followed by a fusion with points runs inside the fusion's passes
-    it.fuse_move = moved && fuse ? 1 : 0;
-    tab->off[kBMove][i + 1] =
-        tab->off[kBMove][i] + (moved && !fuse ? move_units(it.c.nx, it.c.ny) : 0);
+    const int64_t cells = (int64_t)it.c.nx * it.c.ny;
+    const bool wall = fuse && it.fs.count != nullptr;
+    // the per-cell variances, as the plain call runs them (time variance also
+    // after an empty frame)
+    const bool var = (st & EMX_STAGE_FUSE) &&
+                     (it.c.var_t != 0.0f || (it.c.var_o != 0.0f && it.n > 0));
+    tab->off[kBMove][i + 1] = tab->off[kBMove][i] + (moved ? move_units(it.c.nx, it.c.ny) : 0);
+    tab->off[kBZero][i + 1] = tab->off[kBZero][i] + (wall ? zero_units(cells) : 0);
+    tab->off[kBCount][i + 1] = tab->off[kBCount][i] + (wall ? it.B : 0);
     tab->off[kBChunk][i + 1] = tab->off[kBChunk][i] + (fuse ? it.B : 0);
     tab->off[kBTile][i + 1] = tab->off[kBTile][i] + (fuse ? it.T : 0);
+    tab->off[kBVar][i + 1] = tab->off[kBVar][i] + (var ? var_units(cells) : 0);
     tab->off[kBSetup][i + 1] =
         tab->off[kBSetup][i] +
         (clear ? clear_setup_units(it.n, it.nprep, it.out_cleared != nullptr) : 0);
@@ -369,15 +382,20 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
   auto cap = [](int tuned, int64_t units) {
     return (int)(units < 1 ? 1 : (pow2_at_least(units) < tuned ? pow2_at_least(units) : tuned));
   };
+  // stages that only some maps use are skipped (grid 0) when none does
+  auto cap_opt = [&](int tuned, int64_t units) { return units < 1 ? 0 : cap(tuned, units); };
   GraphKey key;
   key.scratch = d_scratch;
   key.key64 = key64 ? 1 : 0;
   key.grid[0] = cap(t.grid_move, tab->off[kBMove][n]);
-  key.grid[1] = cap(t.grid_chunk, tab->off[kBChunk][n]);
-  key.grid[2] = cap(t.grid_tile, tab->off[kBTile][n]);
-  key.grid[3] = cap(t.grid_setup, tab->off[kBSetup][n]);
-  key.grid[4] = cap(t.grid_march, (2 * clear_rays + 255) / 256);
-  key.grid[5] = cap(t.grid_cells, tab->off[kBCells][n]);
+  key.grid[1] = cap_opt(t.grid_cells, tab->off[kBZero][n]);
+  key.grid[2] = cap_opt(t.grid_chunk, tab->off[kBCount][n]);
+  key.grid[3] = cap(t.grid_chunk, tab->off[kBChunk][n]);
+  key.grid[4] = cap(t.grid_tile, tab->off[kBTile][n]);
+  key.grid[5] = cap_opt(t.grid_cells, tab->off[kBVar][n]);
+  key.grid[6] = cap(t.grid_setup, tab->off[kBSetup][n]);
+  key.grid[7] = cap(t.grid_march, (2 * clear_rays + 255) / 256);
+  key.grid[8] = cap(t.grid_cells, tab->off[kBCells][n]);
 
   // ---- enqueue: the table upload, then a cached graph or the same launches
   hipStream_t st = (hipStream_t)stream;
@@ -386,10 +404,9 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
   if (e != hipSuccess) return hip_fail(e, "pipeline_batch: table upload");
   auto enqueue = [&](hipStream_t q) -> hipError_t {
     hipError_t r = launch_move_batch(d_tab, key.grid[0], q);
-    if (r == hipSuccess) r = launch_fuse_batch(d_tab, key64, key.grid[1], key.grid[2], q);
-    if (r == hipSuccess)
-      r = launch_clear_batch(d_tab, key.grid[3], key.grid[4], q);
-    if (r == hipSuccess) r = launch_cells_batch(d_tab, key.grid[5], q);
+    if (r == hipSuccess) r = launch_fuse_batch(d_tab, key64, key.grid + 1, q);
+    if (r == hipSuccess) r = launch_clear_batch(d_tab, key.grid[6], key.grid[7], q);
+    if (r == hipSuccess) r = launch_cells_batch(d_tab, key.grid[8], q);
     return r;
   };
   if (t.graph) {

@@ -76,11 +76,15 @@ __global__ __launch_bounds__(kNTf) void k_overlap(OverlapArgs a) {
 }
 
 // ---------------------------------------------------------------- stencil tile
-constexpr int kCellLog = 4;        // output tiles of 16 x 16 cells: one cell per thread
-constexpr int kSW = 1 << kCellLog;  // output tile width
-constexpr int kSH = 1 << kCellLog;  // output tile height
+// Output tiles of 64 x 16 cells, four per thread.  Each row of the halo tile is
+// read by one wave: lane l takes column x0 + l (one 256-byte load of heights
+// and one 64-byte load of validity per row), two lanes take the halo columns.
+constexpr int kSW = 64;            // output tile width (one wave per row)
+constexpr int kSH = 16;            // output tile height
 constexpr int kHW = kSW + 2;       // halo tile
 constexpr int kHH = kSH + 2;
+constexpr int kSWLog = 6;
+constexpr int kSHLog = 4;
 
 struct HaloTile {
   float h[kHH][kHW + 1];
@@ -89,20 +93,35 @@ struct HaloTile {
 
 __device__ __forceinline__ void load_halo(HaloTile& s, const Consts& c, const Layers& L, int x0,
                                           int y0) {
-  for (int idx = threadIdx.x; idx < kHH * kHW; idx += kNTf) {
-    const int ly = idx / kHW;
-    const int lx = idx - ly * kHW;
-    const int gx = x0 - 1 + lx;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int ly = wave; ly < kHH; ly += kNTf / 64) {
     const int gy = y0 - 1 + ly;
-    float hv = 0.0f;
-    uint8_t ok = 0;
-    if (gx >= 0 && gx < c.nx && gy >= 0 && gy < c.ny) {
-      const int64_t o = (int64_t)gy * c.nx + gx;
-      ok = L.valid[o];
-      hv = L.h[o];
+    const bool row = gy >= 0 && gy < c.ny;
+    const int64_t rb = (int64_t)gy * c.nx;
+    {  // body column lx = lane + 1
+      const int gx = x0 + lane;
+      float hv = 0.0f;
+      uint8_t ok = 0;
+      if (row && gx < c.nx) {
+        ok = L.valid[rb + gx];
+        hv = L.h[rb + gx];
+      }
+      s.h[ly][lane + 1] = hv;
+      s.ok[ly][lane + 1] = ok;
     }
-    s.h[ly][lx] = hv;
-    s.ok[ly][lx] = ok;
+    if (lane < 2) {  // halo columns lx = 0 and lx = kSW + 1
+      const int lx = lane == 0 ? 0 : kSW + 1;
+      const int gx = x0 - 1 + lx;
+      float hv = 0.0f;
+      uint8_t ok = 0;
+      if (row && gx >= 0 && gx < c.nx) {
+        ok = L.valid[rb + gx];
+        hv = L.h[rb + gx];
+      }
+      s.h[ly][lx] = hv;
+      s.ok[ly][lx] = ok;
+    }
   }
 }
 
@@ -156,7 +175,7 @@ __device__ __forceinline__ float trav_at(const HaloTile& s, int lx, int ly, cons
 __device__ __forceinline__ void cells_body(const Item& it, int64_t unit, bool do_n, bool do_t) {
   __shared__ HaloTile s;
   __shared__ float sw[89];
-  const int ux = blocks_of(it.c.nx, kCellLog);
+  const int ux = blocks_of(it.c.nx, kSWLog);
   const int x0 = (int)(unit % ux) * kSW;
   const int y0 = (int)(unit / ux) * kSH;
   if (do_t && threadIdx.x < 89) sw[threadIdx.x] = it.w[threadIdx.x];
@@ -226,7 +245,7 @@ __global__ __launch_bounds__(kNTf) void k_cells_b(const Batch* bt) {
 
 int64_t move_units(int nx, int ny) { return (int64_t)blocks_of(nx, 6) * ((ny + kMoveH - 1) / kMoveH); }
 int64_t cells_units(int nx, int ny) {
-  return (int64_t)blocks_of(nx, kCellLog) * blocks_of(ny, kCellLog);
+  return (int64_t)blocks_of(nx, kSWLog) * blocks_of(ny, kSHLog);
 }
 
 hipError_t launch_fill_prior(const Consts& c, const Layers& L, uint32_t* ctl, int nctl,

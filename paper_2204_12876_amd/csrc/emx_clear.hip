@@ -9,9 +9,9 @@
 //   - Block role: per block of 2^b x 2^b cells, the largest height of a cell
 //     that a ray could still remove: valid, older than the minimum age, with a
 //     normal.  It is -inf if there is none.  In blocks with such a cell the
-//     same pass writes each cell's 16-byte clearing record {h, or -inf if no
-//     ray may remove it, v, nx, ny}, so that the march tests a sample with one
-//     load.  Other blocks prune every sample, so their records are never read.
+//     same pass writes each cell's 8-byte clearing record {h, or -inf if no
+//     ray may remove it, v}, so that the march's height test takes one load.
+//     Other blocks prune every sample, so their records are never read.
 //   - Ray role, one thread per point:
 //       - the ray's exact in-map range of k.  A sample's cell is in the map over
 //         a contiguous range of k, because q_k.x and q_k.y are monotone in k:
@@ -20,17 +20,20 @@
 //         uses.
 //       - the range is cut into segments of `seg` samples.  Each workgroup
 //         reserves its segments with one integer atomic, in one of kSubQ
-//         sub-queues, so no counter is contended.  A ray that would overflow
-//         its bounded sub-queue goes whole to an overflow list (one entry per
-//         ray at most, so the list cannot overflow).
+//         sub-queues, so no counter is contended.  An entry names the ray by
+//         its point (8 bytes: the ray, the first sample and the count); the
+//         march rebuilds the ray from the point, so no per-ray record is
+//         written.  A ray that would overflow its bounded sub-queue goes whole
+//         to an overflow list (one entry per ray at most, so the list cannot
+//         overflow).
 //   - Block 0 zeroes the counter set of the next plain call, and the block
 //     role zeroes the caller's removed-cell mask.
 // march: a persistent grid drains the queue, one segment per thread.
 //   - A sample at height q.z >= the block maximum passes above every cell that
 //     could be removed, since removal needs h > q.z.  It is skipped without
 //     reading the cell: exact pruning.
-//   - Other samples read their cell's clearing record (and the normal's z
-//     only if the height test passes).
+//   - Other samples read their cell's clearing record (and the normal only
+//     if the height test passes).
 //   - A sample that removes its cell resets the cell to the prior on the spot
 //     (and flags it in the caller's mask).  The march reads only the setup's
 //     records and the normals, never the heights, variances or validity it
@@ -56,7 +59,6 @@ constexpr int kNTc = 256;
 struct Ray {
   float ox, oy, oz;
   float dx, dy, dz;
-  float Kf;
   double rK;  // 1/K, correctly rounded in double
 };
 
@@ -165,21 +167,45 @@ __device__ __forceinline__ void clear_cell(const Item& it, int c) {
 }
 
 // The removal test of sample q (height qz) in cell c, from the cell's
-// clearing record, written by the setup: one 16-byte load instead of seven,
-// and the normal's z only when the height test passes.  A cell no ray may
-// clear holds -inf, which fails hd > 0 for every finite sample height.  On maps with an upper
-// bound layer, a cell without an estimate holds NaN in place of the height
-// (no other record does), which sends the sample to its bound.
+// clearing record {h, v}, written by the setup: one 8-byte load for the height
+// test (which most samples fail), and the normal only when it passes.  A cell
+// no ray may clear holds -inf, which fails hd > 0 for every finite sample
+// height.  On maps with an upper bound layer, a cell without an estimate holds
+// NaN in place of the height (no other record does), which sends the sample
+// to its bound.
 __device__ __forceinline__ void test_cell_rec(const Item& it, const Ray& r, int c, float qz,
-                                              float an2dd, const float4 k) {
+                                              float an2dd, const float2 k) {
   if (isnan(k.x)) {
     atomic_min_f32(it.L.ub + c, qz);
     return;
   }
   const float hd = k.x - qz;
   if (!(hd > 0.0f) || !((hd * hd) > k.y)) return;
-  const float dot = (r.dx * k.z + r.dy * k.w) + r.dz * it.L.nz[c];
+  const float dot = (r.dx * it.L.nx[c] + r.dy * it.L.ny[c]) + r.dz * it.L.nz[c];
   if ((dot * dot) > an2dd) clear_cell(it, c);
+}
+
+// The ray of point i of the item: origin, direction, sample count K and the
+// end point's cell (or -1 outside).  False if the point casts no ray (not
+// valid, too long a ray, or K < 2: no samples).  The setup and the march both
+// build rays here, so a queued ray is rebuilt bit for bit from its point.
+__device__ __forceinline__ bool ray_of(const Item& it, int64_t i, Ray& r, int& K, int& end_cell) {
+  r.ox = it.P.t[0];
+  r.oy = it.P.t[1];
+  r.oz = it.P.t[2];
+  const PointEval e = eval_point(it.P, it.c, it.x[i], it.y[i], it.z[i]);
+  r.dx = e.xm - r.ox;
+  r.dy = e.ym - r.oy;
+  r.dz = e.zm - r.oz;
+  const float m = fmaxf(fabsf(r.dx), fabsf(r.dy));
+  const float ks = m * it.c.inv_step;
+  if (!e.valid || !(ks < 16777216.0f)) return false;
+  K = (int)ceilf(ks);
+  if (K < 2) return false;
+  r.rK = 1.0 / (double)K;
+  int ex, ey;
+  end_cell = bin_xy(e.xm, e.ym, it.c, ex, ey) ? ey * it.c.nx + ex : -1;
+  return true;
 }
 
 constexpr int kUnroll = 8;
@@ -222,10 +248,10 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
     for (int u = 0; u < kUnroll; ++u)
       cand[u] = (k + u <= kb) & (qz[u] < m[u]) & (cell[u] != end_cell);
     // the candidates' records, all requested before any is tested
-    float4 rec[kUnroll];
+    float2 rec[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      rec[u] = make_float4(-INFINITY, 0.0f, 0.0f, 0.0f);
+      rec[u] = make_float2(-INFINITY, 0.0f);
       if (cand[u]) rec[u] = it.L.clr[cell[u]];
     }
 #pragma unroll
@@ -277,41 +303,23 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
         // a NaN height can never be cleared (hd > 0 fails), so -inf serves
         const bool bound = it.L.ub && !it.L.valid[c[j]];
         const float hx = bound ? __builtin_nanf("") : (ok[j] && !isnan(h[j]) ? h[j] : -INFINITY);
-        it.L.clr[c[j]] = make_float4(hx, it.L.v[c[j]], it.L.nx[c[j]], it.L.ny[c[j]]);
+        it.L.clr[c[j]] = make_float2(hx, it.L.v[c[j]]);
       }
     }
     return;
   }
-  // ---- ray role
+  // ---- ray role: the ray's in-map sample range, queued in segments
   const int64_t i = (int64_t)(unit - it.nprep) * kNTc + threadIdx.x;
-  Ray r;
-  r.ox = it.P.t[0];
-  r.oy = it.P.t[1];
-  r.oz = it.P.t[2];
-  r.dx = r.dy = r.dz = 0.0f;
-  r.Kf = 1.0f;
-  r.rK = 1.0;
-  int k0 = 1, k1 = 0, end_cell = -1;
+  int k0 = 1, k1 = 0;
   if (i < it.n) {
-    const PointEval e = eval_point(it.P, it.c, it.x[i], it.y[i], it.z[i]);
-    r.dx = e.xm - r.ox;
-    r.dy = e.ym - r.oy;
-    r.dz = e.zm - r.oz;
-    const float m = fmaxf(fabsf(r.dx), fabsf(r.dy));
-    const float ks = m * it.c.inv_step;
-    if (e.valid && ks < 16777216.0f) {
-      const int K = (int)ceilf(ks);
-      if (K >= 2) {
-        r.Kf = (float)K;
-        r.rK = 1.0 / (double)K;
-        int ex, ey;
-        if (bin_xy(e.xm, e.ym, it.c, ex, ey)) end_cell = ey * it.c.nx + ex;
-        int lx, hx, ly, hy;
-        axis_range<true>(r, K, it.c.inv_r, it.c.nxf, r.dx >= 0.0f, lx, hx);
-        axis_range<false>(r, K, it.c.inv_r, it.c.nyf, r.dy >= 0.0f, ly, hy);
-        k0 = max(lx, ly);
-        k1 = min(hx, hy);
-      }
+    Ray r;
+    int K, end_cell;
+    if (ray_of(it, i, r, K, end_cell)) {
+      int lx, hx, ly, hy;
+      axis_range<true>(r, K, it.c.inv_r, it.c.nxf, r.dx >= 0.0f, lx, hx);
+      axis_range<false>(r, K, it.c.inv_r, it.c.nyf, r.dy >= 0.0f, ly, hy);
+      k0 = max(lx, ly);
+      k1 = min(hx, hy);
     }
   }
   const int seg = it.cq.seg;
@@ -330,11 +338,8 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
   if (nseg == 0) return;
   const int64_t first = (int64_t)s_base + off;
   uint2* q = cq.queue + (int64_t)sub * cq.qcap;
+  const int64_t gray = it.ray_base + i;
   if (first + nseg <= cq.qcap) {
-    const int64_t gray = it.ray_base + i;
-    cq.ray[gray] = make_float4(r.dx, r.dy, r.dz, r.Kf);
-    cq.ray_end[gray] = end_cell;
-    if (cq.ray_item) cq.ray_item[gray] = it.index;
     for (int sgi = 0; sgi < nseg; ++sgi) {
       const int ka = k0 + sgi * seg;
       const int cnt = min(seg, k1 - ka + 1);
@@ -344,10 +349,6 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
     // sub-queue full: leave empty entries in any reserved slots; the whole
     // ray goes to the overflow list, marched after the queue
     for (int64_t e = first; e < first + nseg && e < cq.qcap; ++e) q[e] = make_uint2(0u, 0u);
-    const int64_t gray = it.ray_base + i;
-    cq.ray[gray] = make_float4(r.dx, r.dy, r.dz, r.Kf);
-    cq.ray_end[gray] = end_cell;
-    if (cq.ray_item) cq.ray_item[gray] = it.index;
     const uint32_t o = atomicAdd(cq.counter + kOverCtr, 1u);
     cq.over[o] = make_uint4((uint32_t)gray, (uint32_t)k0, (uint32_t)k1, 0u);
   }
@@ -380,28 +381,32 @@ __device__ __forceinline__ uint2 queue_entry(const ClearQueue& cq, const int64_t
   return cq.queue[(int64_t)lo * cq.qcap + (g - s_qoff[lo])];
 }
 
-// Samples [ka, kb] of queued ray g.
-__device__ __forceinline__ void march_ray(const Item& it, const ClearQueue& cq, uint32_t g,
-                                          int ka, int kb, const float* cm) {
-  const float4 d = cq.ray[g];
+// Samples [ka, kb] of queued ray g (the item's point g - ray_base).
+__device__ __forceinline__ void march_ray(const Item& it, uint32_t g, int ka, int kb,
+                                          const float* cm) {
   Ray r;
-  r.ox = it.P.t[0];
-  r.oy = it.P.t[1];
-  r.oz = it.P.t[2];
-  r.dx = d.x;
-  r.dy = d.y;
-  r.dz = d.z;
-  r.Kf = d.w;
-  r.rK = 1.0 / (double)d.w;
-  march_range(it, r, ka, kb, cq.ray_end[g], cm);
+  int K, end_cell;
+  if (!ray_of(it, (int64_t)g - it.ray_base, r, K, end_cell)) return;  // never for a queued ray
+  march_range(it, r, ka, kb, end_cell, cm);
 }
 
-__device__ __forceinline__ void march_entry(const Item& it, const ClearQueue& cq, uint2 e,
-                                            const float* cm) {
+__device__ __forceinline__ void march_entry(const Item& it, uint2 e, const float* cm) {
   const int cnt = (int)(e.y & 255u);
   if (cnt == 0) return;
   const int ka = (int)(e.y >> 8);
-  march_ray(it, cq, e.x, ka, ka + cnt - 1, cm);
+  march_ray(it, e.x, ka, ka + cnt - 1, cm);
+}
+
+// Item of global ray g in a batch: the last item whose first ray is <= g
+// (items without rays are skipped over).  s_rays holds the batch's prefix.
+__device__ __forceinline__ int ray_item(const int64_t* s_rays, int n, int64_t g) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_rays[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 // ---------------------------------------------------------------- launches
@@ -418,13 +423,13 @@ __global__ __launch_bounds__(kNTc) void k_clear_march(Item it) {
   const int64_t total = s_qoff[kSubQ];
   for (int64_t g = (int64_t)blockIdx.x * kNTc + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * kNTc)
-    march_entry(it, it.cq, queue_entry(it.cq, s_qoff, g), it.L.cmax);
+    march_entry(it, queue_entry(it.cq, s_qoff, g), it.L.cmax);
   // then the rays that overflowed their sub-queue, whole
   const uint32_t nover = it.cq.counter[kOverCtr];
   for (int64_t g = (int64_t)blockIdx.x * kNTc + threadIdx.x; g < nover;
        g += (int64_t)gridDim.x * kNTc) {
     const uint4 o = it.cq.over[g];
-    march_ray(it, it.cq, o.x, (int)o.y, (int)o.z, it.L.cmax);
+    march_ray(it, o.x, (int)o.y, (int)o.z, it.L.cmax);
   }
 }
 
@@ -439,26 +444,29 @@ __global__ __launch_bounds__(kNTc) void k_clear_setup_b(const Batch* bt) {
 }
 
 // Every item of a batch shares one queue (the first item's view of it); a
-// queue entry's ray names its item.
+// queue entry's global ray index names its item.
 __global__ __launch_bounds__(kNTc) void k_clear_march_b(const Batch* bt) {
   __shared__ int64_t s_qoff[kSubQ + 1];
+  __shared__ int64_t s_rays[kMaxItems + 1];
   const ClearQueue& cq = bt->items[0].cq;
+  const int n = bt->n;
   queue_prefix(cq, s_qoff);
+  for (int k = threadIdx.x; k <= n; k += kNTc) s_rays[k] = bt->rays[k];
   __syncthreads();
   const int64_t total = s_qoff[kSubQ];
   for (int64_t g = (int64_t)blockIdx.x * kNTc + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * kNTc) {
     const uint2 e = queue_entry(cq, s_qoff, g);
     if ((e.y & 255u) == 0) continue;
-    const Item& it = bt->items[cq.ray_item[e.x]];
-    march_entry(it, cq, e, it.L.cmax);
+    const Item& it = bt->items[ray_item(s_rays, n, e.x)];
+    march_entry(it, e, it.L.cmax);
   }
   const uint32_t nover = cq.counter[kOverCtr];
   for (int64_t g = (int64_t)blockIdx.x * kNTc + threadIdx.x; g < nover;
        g += (int64_t)gridDim.x * kNTc) {
     const uint4 o = cq.over[g];
-    const Item& it = bt->items[cq.ray_item[o.x]];
-    march_ray(it, cq, o.x, (int)o.y, (int)o.z, it.L.cmax);
+    const Item& it = bt->items[ray_item(s_rays, n, o.x)];
+    march_ray(it, o.x, (int)o.y, (int)o.z, it.L.cmax);
   }
 }
 
@@ -479,20 +487,11 @@ size_t clear_scratch_layout(int64_t max_points, int seg, char* base, ClearQueue*
   const size_t n = (size_t)max_points;
   const size_t qcap = (size_t)clear_queue_cap(max_points, seg);
   size_t off = 0;
-  const size_t o_ray = off;
-  off = align256(off + n * sizeof(float4));
-  const size_t o_end = off;
-  off = align256(off + n * sizeof(int32_t));
-  const size_t o_item = off;
-  off = align256(off + n * sizeof(int32_t));
   const size_t o_q = off;
   off = align256(off + (size_t)kSubQ * qcap * sizeof(uint2));
   const size_t o_over = off;
   off = align256(off + n * sizeof(uint4));
   if (out && base) {
-    out->ray = (float4*)(base + o_ray);
-    out->ray_end = (int32_t*)(base + o_end);
-    out->ray_item = (int32_t*)(base + o_item);
     out->queue = (uint2*)(base + o_q);
     out->over = (uint4*)(base + o_over);
     out->qcap = (int64_t)qcap;

@@ -49,7 +49,7 @@ struct Layers {
   uint8_t* mark;  // clearing marks; all zero between calls
   float* cmax;    // per block: max height over cells a ray may clear (transient)
   float* ub;      // upper bound of the ground height (+inf: none), or null
-  float4* clr;    // per cell {h, or -inf if a ray may not clear it, v, nx, ny}
+  float2* clr;    // per cell {h, or -inf if a ray may not clear it, v}
                   // (transient; one array per map, shared by both sets)
 };
 
@@ -82,6 +82,10 @@ struct Consts {
   int32_t tau;     // clear_min_age_ms
   float var_t;     // time variance per fusion, 0 = off
   int32_t wall;    // wall/edge rule threshold, 0 = off
+  int32_t excl_on;     // exclusion area on
+  float excl_slope;    // float32(tan(theta_a))
+  float excl_b, excl_c, excl_d;
+  float var_o;     // outlier variance per fusion, 0 = off
 };
 
 // Sensor -> map-local transform, float32.
@@ -94,15 +98,17 @@ struct FuseScratch {
   uint16_t* rec_local;  // [B * kChunk] cell within its tile of each per-chunk partial
   float* rec_w;         // [B * kChunk] chunk partial of sum 1/sp2
   float* rec_wz;        // [B * kChunk] chunk partial of sum zm/sp2
-  uint32_t* dir;        // [B * T]  (start << 16 | count) of a tile's partials in a chunk
+  uint2* ent;           // [T * B] per tile, in no particular order: (chunk, start << 16 |
+                        // count) of the tile's partials in each chunk that touched it
+  uint32_t* tcnt;       // [T] entries per tile; part of the map state, zero between calls
+                        // (pass 2 resets each tile's count after reading it)
   uint32_t* count;      // [nx * ny] the frame's valid points per cell (wall rule), or null
 };
 
-// Where a clearing setup queues its ray segments.
+// Where a clearing setup queues its ray segments.  A ray is named by its
+// global index ray_base + i (i: its point in the item's frame); the march
+// rebuilds the ray from the point, in the same float32 operations.
 struct ClearQueue {
-  float4* ray;        // (dx, dy, dz, K) per ray, indexed ray_base + i
-  int32_t* ray_end;   // end point's cell or -1
-  int32_t* ray_item;  // item of the ray (batched launches), or nullptr
   uint2* queue;       // kSubQ sub-queues of qcap (ray, k_start << 8 | count) entries
   uint4* over;        // rays that did not fit their sub-queue: (ray, k0, k1, 0)
   uint32_t* counter;  // kSubQ sub-queue counters and the overflow counter (at
@@ -128,14 +134,13 @@ struct Item {
   Consts c;
   Pose32 P;
   Layers L;     // current buffer set (after any move)
-  Layers Lsrc;  // move source set
+  Layers Lsrc;  // move source set (the move kernel)
   const float* x;
   const float* y;
   const float* z;
   int64_t n;
   int32_t t_now;
   int sx, sy;   // move shift in cells
-  int fuse_move; // fusion also performs the move from Lsrc (shift sx, sy) into L
   uint32_t stages;
   const float* w;  // traversability weights (89)
   int32_t* out_cell;
@@ -153,13 +158,16 @@ struct Item {
 // Batched launches: a device-resident table of items and, per stage, the
 // prefix of work units over the items.
 constexpr int kMaxItems = 64;
-enum BatchStage { kBMove = 0, kBChunk, kBTile, kBSetup, kBCells, kBNum };
+// kBZero, kBCount: the wall/edge rule's per-cell counts (zeroed, then
+// counted); kBVar: the per-cell time and outlier variance after the fusion.
+enum BatchStage { kBMove = 0, kBZero, kBCount, kBChunk, kBTile, kBVar, kBSetup, kBCells, kBNum };
 
 // Only the header and the first n items are uploaded for a batch of n.
 struct Batch {
   int n;
   int key64;  // pass 1 sorts 64-bit keys for this batch
   int64_t off[kBNum][kMaxItems + 1];
+  int64_t rays[kMaxItems + 1];  // prefix of the items' clearing rays (ray_base)
   Item items[kMaxItems];
 };
 
@@ -181,6 +189,22 @@ __device__ __forceinline__ PointEval eval_point(const Pose32& P, const Consts& c
             (e.d2 >= c.rmin2) && isfinite(e.sp2);
   return e;
 }
+
+// Exclusion area: the point lies above the line around the sensor origin
+// (Pose32::t), in the ABI's float32 order.
+__device__ __forceinline__ bool excluded_point(const Pose32& P, const Consts& c,
+                                               const PointEval& e) {
+  const float dxr = e.xm - P.t[0];
+  const float dyr = e.ym - P.t[1];
+  const float rho = sqrtf(dxr * dxr + dyr * dyr);
+  const float eup = e.zm - P.t[2];
+  const float line = fminf(c.excl_b + c.excl_slope * fmaxf(rho - c.excl_c, 0.0f), c.excl_d);
+  return eup > line;
+}
+
+// Mark layer bits between the fusion's passes and its per-cell pass.
+constexpr uint8_t kMarkUpdated = 1;   // pass 2 updated the cell
+constexpr uint8_t kMarkOutlier = 2;   // a gate-rejected point fell in the (valid) cell
 
 // Half-open binning of map-local float32 coordinates; false outside.
 __device__ __forceinline__ bool bin_xy(float xm, float ym, const Consts& c, int& ix, int& iy) {
@@ -263,6 +287,24 @@ __device__ __forceinline__ int block_exclusive_sum(int v, int& total, int* sm) {
   __syncthreads();
   total = tot;
   return pre + x - v;
+}
+
+// Minimum of one uint32 per thread over a block of NT threads.  `sm` holds
+// NT/64 words.  Contains two barriers; every thread must call it.
+template <int NT>
+__device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t* sm) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t y = (uint32_t)__shfl_xor((int)v, o, 64);
+    v = y < v ? y : v;
+  }
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint32_t r = sm[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) r = sm[w] < r ? sm[w] : r;
+  __syncthreads();
+  return r;
 }
 
 // ------------------------------------------------------------- batched units

@@ -10,8 +10,10 @@ namespace emx {
 
 // Per-map control words after the two buffer sets: two sets of clearing
 // queue counters, used by alternate plain calls (each call's setup zeroes the
-// other set for the next call).
+// other set for the next call), then the fusion's per-tile entry counts (one
+// word per tile, zero between calls).
 constexpr int kCtlWords = 2 * kCtrWords;
+int64_t ctl_words(const emx_params& p);
 
 // Default clearing segment length (samples per queued segment) and march
 // workgroups per compute unit, from a sweep of both on MI355X.

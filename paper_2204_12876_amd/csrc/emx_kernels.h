@@ -36,7 +36,11 @@ size_t fuse_scratch_layout(int64_t max_points, int T, int64_t count_cells, char*
                            FuseScratch* out);
 // Runs the time variance pass even when it.n == 0.
 hipError_t launch_fuse(const Item& it, hipStream_t stream);
-hipError_t launch_fuse_batch(const Batch* d_batch, bool key64, int grid_chunk, int grid_tile,
+// Work units of the batched count zeroing and per-cell variance stages.
+int64_t zero_units(int64_t cells);
+int64_t var_units(int64_t cells);
+// grid: zero, count, chunk, tile, variance; a zero grid skips its stage.
+hipError_t launch_fuse_batch(const Batch* d_batch, bool key64, const int grid[5],
                              hipStream_t stream);
 
 // ---------------------------------------------------------------- clearing

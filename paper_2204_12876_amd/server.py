@@ -322,9 +322,11 @@ class GpuExecutor:
     def __init__(self, largest_params: dict, lanes: int = 2, max_items: int = 64,
                  max_batch_points: int = 4_000_000, pool_points: int = 16_000_000,
                  weights: torch.Tensor = None, tuning: str = None, single_plain: bool = True,
-                 device=None):
+                 wall_rule: bool = False, device=None):
         """single_plain: run a batch of one frame through the plain calls, which
-        give the same bits with less launch overhead."""
+        give the same bits with less launch overhead.  wall_rule: size each
+        lane's scratch for maps with the wall/edge rule (per-cell counts of
+        every item); without it such maps are not admitted."""
         import json
         from . import PipelineBatch, aligned_empty
         self.device = torch.device(device if device is not None else "cuda")
@@ -340,7 +342,9 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.lanes)]
         self.execs = [PipelineBatch(json.dumps(tune), device=self.device)
                       for _ in range(self.lanes)]
-        bound = _emx.batch_scratch_bound(self.execs[0].handle, _emx.make_params(largest_params),
+        self.wall_rule = bool(wall_rule)
+        sized = dict(largest_params, wall_min_count=1 if self.wall_rule else 0)
+        bound = _emx.batch_scratch_bound(self.execs[0].handle, _emx.make_params(sized),
                                          self.max_items, self.max_batch_points)
         if bound == 0:
             raise AdmissionError(_emx.last_error())
@@ -368,11 +372,9 @@ class GpuExecutor:
 
     def create_map(self, robot, params, cx, cy, t0):
         from . import ElevationMap
-        if (params.get("time_variance", 0.0) or params.get("wall_min_count", 0)
-                or params.get("upper_bound", 0)):
-            # batched launches run the base path only
-            raise ValueError("maps with time_variance, wall_min_count or upper_bound are not "
-                             "served in batches")
+        if params.get("wall_min_count", 0) and not self.wall_rule:
+            raise AdmissionError("maps with the wall/edge rule need an executor built with "
+                                 "wall_rule=True (its scratch holds their counts)")
         self.maps[robot] = ElevationMap(params, cx, cy, t0, device=self.device)
 
     def drop_map(self, robot):

@@ -111,4 +111,5 @@ def test_roofline_takes_the_kernel_with_the_most_time():
     assert math.isclose(r["frac"], r["achieved"] / 8000.0)
     assert math.isclose(r["alg_bytes_per_launch"], 6e9 / 5)
     fb = bench.frame_bytes(100, 50, 7, 5, 1.0)
-    assert fb["fuse_chunk"] == 1200 + 56 and fb["fuse_tile"] == 105 + 58 * 50
+    assert fb["fuse_chunk"] == 1200 + 56 and fb["fuse_tile"] == 105
+    assert fb["move"] == 58 * 50 and bench.frame_bytes(100, 50, 7, 5, 0.0)["move"] == 0

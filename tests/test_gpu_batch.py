@@ -51,12 +51,12 @@ SHAPES = [(64, 48, 0.05, 30000), (130, 97, 0.04, 2049), (33, 200, 0.1, 0),
 class Robot:
     """A map driven twice: once by the plain calls, once inside batches."""
 
-    def __init__(self, k, shape, dev, seed):
+    def __init__(self, k, shape, dev, seed, extra=None):
         from paper_2204_12876_amd import ElevationMap
         nx, ny, r, n = shape
         self.params = dict(nx=nx, ny=ny, resolution=r, noise_alpha=1e-3, gate_k=3.0,
                            min_range=0.01, ray_step=r, clear_min_age_ms=300,
-                           clear_normal_alpha=0.2)
+                           clear_normal_alpha=0.2, **(extra or {}))
         self.p = O.Params.from_dict(self.params)
         self.n = n
         self.rng = np.random.default_rng(seed)
@@ -135,6 +135,8 @@ def _drive(robots, pb, w, frames, stages_of=None):
             tag = f"frame {it} map {rb.k} ({rb.p.nx}x{rb.p.ny}, n={rb.n}, stages={st})"
             assert rb.plain.info() == rb.batch.info(), tag
             _same(rb.plain.export_state(), rb.batch.export_state(), tag + " state")
+            if rb.params.get("upper_bound"):
+                _same(rb.plain.upper_bound(), rb.batch.upper_bound(), tag + " upper bound")
             if st & _emx.STAGE_FUSE:
                 _same(op[0], ob[0], tag + " out_cell")
                 _same(op[1], ob[1], tag + " out_accept")
@@ -145,6 +147,31 @@ def _drive(robots, pb, w, frames, stages_of=None):
 
 def _robots(dev, shapes=SHAPES, seed=0):
     return [Robot(k, s, dev, 1000 * seed + k) for k, s in enumerate(shapes)]
+
+
+# every fusion extension and the upper bound layer, alone and together,
+# next to maps without them
+EXTRAS = [
+    {},
+    dict(wall_min_count=2),
+    dict(time_variance=0.003, upper_bound=1),      # this map's frames are empty
+    dict(upper_bound=1),
+    dict(excl_on=1, excl_theta=0.4, excl_b=0.3, excl_c=0.5, excl_d=0.9, outlier_variance=0.01),
+    dict(time_variance=0.001, wall_min_count=3, upper_bound=1, excl_on=1, excl_theta=0.6,
+         excl_b=0.2, excl_c=1.0, excl_d=0.7, outlier_variance=0.02),
+]
+
+
+def test_batch_with_every_extension(dev):
+    from paper_2204_12876_amd import PipelineBatch
+    _say("batch with every fusion extension")
+    w = torch.from_numpy(synth.trav_weights()).to(dev)
+    robots = [Robot(k, s, dev, 7000 + k, extra=e) for k, (s, e) in enumerate(zip(SHAPES, EXTRAS))]
+    assert robots[2].n == 0
+    for graph in (1, 0):
+        pb = PipelineBatch(json.dumps({"graph": graph}), device=dev)
+        _drive(robots, pb, w, 4)
+        pb.close()
 
 
 def test_batch_equals_plain_calls_with_graph_replays(dev):

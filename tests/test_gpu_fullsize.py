@@ -10,6 +10,9 @@ benchmark uses.
   * 16 maps of uneven size in one batched call with the tuned geometry: each
     map against the oracle (fusion on every point, twice; normals and
     traversability; clearing on sampled rays).
+  * The stress mix: the 2000x2000 map with a 4M-point frame and eight 400x400
+    maps with 300k-point frames in one batched call, each map against the
+    oracle in the same way.
   * 64 robots through the continuous-batching server: every map after a
     compressed trace equals, bit for bit, the map its frames give alone.
 """
@@ -171,6 +174,69 @@ def test_sixteen_maps_batched_full_size(dev):
         assert np.array_equal(got, marks), f"map {i}: marks differ"
         total += int(marks.sum())
     _say(f"16 maps batched: clearing matches ({total} cells cleared)")
+    pb.close()
+    for m in maps:
+        m.close()
+
+
+def test_stress_mix_batched_full_size(dev):
+    """The 2000x2000 map with a 4M-point frame and eight 400x400 maps with
+    300k-point frames, in one batched call with the tuned geometry: every map
+    against the oracle (fusion on every point, normals and traversability on
+    every cell), then clearing on sampled rays of every map in one more
+    batched call."""
+    from paper_2204_12876_amd import BatchEntry, ElevationMap, PipelineBatch, _emx
+    _say("stress mix batched, full size: generating")
+    big = synth.cfg4(n_frames=1, device=dev)
+    small = synth.cfg1(n_frames=8, device=dev)
+    w = torch.from_numpy(synth.trav_weights()).to(dev)
+    pb = PipelineBatch(_tuning(), device=dev)
+    specs = [(big["params"], big["centers"][0], big["frames"][0])]
+    specs += [(small["params"], small["centers"][k], small["frames"][k]) for k in range(8)]
+    ps = [O.Params.from_dict(pr) for pr, _, _ in specs]
+    maps = [ElevationMap(pr, *c, 0, device=dev) for pr, c, _ in specs]
+    dev_xyz = [(f.x.to(dev).contiguous(), f.y.to(dev).contiguous(), f.z.to(dev).contiguous())
+               for _, _, f in specs]
+    host_xyz = [f.numpy() for _, _, f in specs]
+    stages = _emx.STAGE_FUSE | _emx.STAGE_NORMALS | _emx.STAGE_TRAV
+    t_ms = 100
+    before = [state_from_gpu(m, *m.info())[0] for m in maps]
+    outs = [(torch.full((f.n,), -7, dtype=torch.int32, device=dev),
+             torch.full((f.n,), 7, dtype=torch.uint8, device=dev)) for _, _, f in specs]
+    _say("stress mix batched: one call, 9 maps,",
+         sum(f.n for _, _, f in specs), "points")
+    pb.run([BatchEntry(m, *xyz, f.pose, t_ms, weights=w, stages=stages, out_cell=c, out_accept=a)
+            for m, xyz, (_, _, f), (c, a) in zip(maps, dev_xyz, specs, outs)])
+    torch.cuda.synchronize()
+    for i, (m, p, (_, _, f)) in enumerate(zip(maps, ps, specs)):
+        _, g = state_from_gpu(m, *m.info())
+        r = O.fuse(p, before[i], *host_xyz[i], f.pose, t_ms)
+        assert_fuse_parity(r, before[i], g, outs[i][0].cpu().numpy(),
+                           outs[i][1].cpu().numpy(), t_ms)
+        assert_normals_parity(g, O.compute_normals(p, g["h"], g["valid"]))
+        T, S = O.traversability(g["h"], g["valid"], synth.trav_weights())
+        assert_trav_parity(g, T, S)
+        _say(f"stress mix batched: map {i} ({p.nx}x{p.ny}) fusion, normals, traversability match")
+    # clearing: one batched call on sampled rays of every map
+    before = [state_from_gpu(m, *m.info())[0] for m in maps]
+    picks, couts, entries = [], [], []
+    for i, (m, p, (_, _, f)) in enumerate(zip(maps, ps, specs)):
+        idx = _sample(f.n, 20000 if i == 0 else 5000, 40 + i)
+        sel = tuple(np.ascontiguousarray(a[idx]) for a in host_xyz[i])
+        picks.append(sel)
+        o = torch.full((p.nx * p.ny,), 9, dtype=torch.uint8, device=dev)
+        couts.append(o)
+        entries.append(BatchEntry(m, *(torch.from_numpy(a).to(dev) for a in sel), f.pose, 1500,
+                                  stages=_emx.STAGE_CLEAR, out_cleared=o))
+    pb.run(entries)
+    torch.cuda.synchronize()
+    total = 0
+    for i, (m, p, (_, _, f)) in enumerate(zip(maps, ps, specs)):
+        marks = O.clear_visibility(p, before[i], *picks[i], f.pose, 1500)
+        got = couts[i].cpu().numpy().reshape(p.ny, p.nx).astype(bool)
+        assert np.array_equal(got, marks), f"map {i}: marks differ"
+        total += int(marks.sum())
+    _say(f"stress mix batched: clearing matches ({total} cells cleared)")
     pb.close()
     for m in maps:
         m.close()

@@ -259,16 +259,109 @@ def test_drift_on_the_scene_recovers_a_height_offset(dev):
 
 
 # ------------------------------------------------------------- batch refusal
-def test_batch_refuses_the_extensions(dev):
-    from paper_2204_12876_amd import BatchEntry, EmxError, PipelineBatch, _emx
-    _say("batch refusal")
+def test_batch_runs_the_extensions_like_the_plain_calls(dev):
+    """Each extension alone, one map, one fusion: the batched call gives the
+    plain call's bits (the mixed, multi-frame case is in test_gpu_batch)."""
+    from paper_2204_12876_amd import BatchEntry, PipelineBatch, _emx
+    _say("batch with one extension each")
     pb = PipelineBatch(device=dev)
-    xyz = _dev(dev, np.zeros(10), np.zeros(10), np.full(10, -1.0))
-    for extra in (dict(time_variance=0.001), dict(wall_min_count=2), dict(upper_bound=1)):
-        params = dict(nx=16, ny=16, resolution=0.1, **extra)
-        m = _map(params, dev)
-        with pytest.raises(EmxError) as e:
-            pb.run([BatchEntry(m, *xyz, _pose((0, 0, 1)), 10, stages=_emx.STAGE_FUSE)])
-        assert e.value.status == _emx.EMX_EINVAL
-        m.close()
+    rng = np.random.default_rng(9)
+    xs, ys, zs = _clustered_cloud(rng, 3000, 16, 16, 0.1, 1.0)
+    xyz = _dev(dev, xs, ys, zs)
+    for extra in (dict(time_variance=0.001), dict(wall_min_count=2), dict(upper_bound=1),
+                  dict(excl_on=1, excl_theta=0.3, excl_b=0.2, excl_c=0.3, excl_d=0.6),
+                  dict(outlier_variance=0.01, gate_k=1.0)):
+        params = dict(dict(nx=16, ny=16, resolution=0.1), **extra)
+        p = O.Params.from_dict(params)
+        st = random_state(p, rng, valid_frac=0.7)
+        a, b = _map(params, dev), _map(params, dev)
+        load_state(a, st)
+        load_state(b, st)
+        a.fuse_points(*xyz, _pose((0, 0, 1)), 10)
+        pb.run([BatchEntry(b, *xyz, _pose((0, 0, 1)), 10, stages=_emx.STAGE_FUSE)])
+        torch.cuda.synchronize()
+        assert torch.equal(a.export_state(), b.export_state()), extra
+        a.close()
+        b.close()
     pb.close()
+
+
+# ------------------------------------------------------ exclusion area (ramp)
+@pytest.mark.parametrize("wall", [0, 3])
+def test_exclusion_area_fusion(dev, wall):
+    _say("exclusion area, wall rule", wall)
+    rng = np.random.default_rng(200 + wall)
+    params = dict(nx=70, ny=45, resolution=0.1, noise_alpha=0.01, gate_k=1e3, min_range=0.05,
+                  wall_min_count=wall, excl_on=1, excl_theta=0.5, excl_b=0.1, excl_c=0.8,
+                  excl_d=0.5)
+    p = O.Params.from_dict(params)
+    m = _map(params, dev)
+    st = random_state(p, rng, valid_frac=0.8)
+    load_state(m, st)
+    n = 6 * 1024 + 37
+    xs, ys, zs = _clustered_cloud(rng, n, p.nx, p.ny, p.resolution, 0.3)
+    pose = _pose((0.0, 0.0, 0.3))
+    cell, acc = gpu_fuse(m, _dev(dev, xs, ys, zs), pose, 40)
+    _, g = state_from_gpu(m, st.cgx, st.cgy, st.t0)
+    r = O.fuse(p, st, xs, ys, zs, pose, 40)
+    assert_fuse_parity(r, st, g, cell, acc, 40)
+    dd = O.point_decisions(p, st, xs, ys, zs, pose)
+    _say(f"exclusion area: {int(dd['excluded'].sum())} points ignored, "
+         f"{int(dd['walled'].sum())} by the wall rule")
+    assert 500 < dd["excluded"].sum() < n - 500
+    if wall:
+        assert dd["walled"].sum() > 20
+    m.close()
+
+
+# ------------------------------------------------------------ outlier variance
+def _assert_outlier_parity(r, before, g, cell, acc, t_now, p, dec):
+    """As assert_fuse_parity, but cells that gain the outlier variance (and, with
+    it, the time variance) without being updated hold the oracle's float32
+    additions bit for bit."""
+    assert np.array_equal(cell, r.cell.astype(np.int32))
+    assert np.array_equal(acc.astype(bool), r.accept)
+    u = r.updated
+    changed = ~u & (r.state.v != before.v)
+    for k in ("h", "t_upd", "valid"):
+        assert np.array_equal(g[k][~u], getattr(before, k)[~u]), f"untouched {k} changed"
+    assert np.array_equal(g["v"][~u].view(np.uint32), r.state.v[~u].view(np.uint32)), \
+        "untouched variance differs from the oracle's float32 additions"
+    dv = np.abs(g["v"][u].astype(np.float64) - r.v[u])
+    assert np.all(dv <= 1e-5 * r.v[u])
+    scale = np.maximum(np.abs(r.h[u]), r.h_scale[u])
+    assert np.all(np.abs(g["h"][u].astype(np.float64) - r.h[u]) <= 1e-5 * scale)
+    return int(changed.sum())
+
+
+@pytest.mark.parametrize("var_t", [0.0, 0.002])
+def test_outlier_variance_fusion(dev, var_t):
+    _say("outlier variance, time variance", var_t)
+    rng = np.random.default_rng(300 + int(var_t * 1e4))
+    params = dict(nx=70, ny=45, resolution=0.1, noise_alpha=0.01, gate_k=2.0, min_range=0.05,
+                  outlier_variance=0.0125, time_variance=var_t, wall_min_count=4)
+    p = O.Params.from_dict(params)
+    m = _map(params, dev)
+    st = random_state(p, rng, valid_frac=0.7)
+    load_state(m, st)
+    n = 5 * 1024 + 501
+    xs, ys, zs = _clustered_cloud(rng, n, p.nx, p.ny, p.resolution, 1.2)
+    pose = _pose((0.0, 0.0, 1.2))
+    cell, acc = gpu_fuse(m, _dev(dev, xs, ys, zs), pose, 40)
+    _, g = state_from_gpu(m, st.cgx, st.cgy, st.t0)
+    r = O.fuse(p, st, xs, ys, zs, pose, 40)
+    dec = O.point_decisions(p, st, xs, ys, zs, pose)
+    inflated = _assert_outlier_parity(r, st, g, cell, acc, 40, p, dec)
+    rej_cells = np.unique(dec["cell"][dec["rejected"]])
+    _say(f"outlier variance: {int(dec['rejected'].sum())} rejected points in "
+         f"{rej_cells.size} cells; {inflated} cells changed without an update")
+    assert dec["rejected"].sum() > 100
+    # a second call: every mark was cleared, so only this frame's outliers count
+    st2, _ = state_from_gpu(m, st.cgx, st.cgy, st.t0)
+    xs2, ys2, zs2 = _clustered_cloud(rng, 3000, p.nx, p.ny, p.resolution, 1.2)
+    cell, acc = gpu_fuse(m, _dev(dev, xs2, ys2, zs2), pose, 80)
+    _, g = state_from_gpu(m, st.cgx, st.cgy, st.t0)
+    r = O.fuse(p, st2, xs2, ys2, zs2, pose, 80)
+    _assert_outlier_parity(r, st2, g, cell, acc, 80, p,
+                           O.point_decisions(p, st2, xs2, ys2, zs2, pose))
+    m.close()
