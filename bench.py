@@ -32,7 +32,9 @@ Sub-records, each with its plain comparison where one exists:
   * stress: the 2000x2000 map with 4M-point LiDAR frames, plain, and batched
     together with 8 400x400 maps;
   * cpu_baseline: the oracle on a bounded sample of the headline workload, on
-    the host cores, one map per process; and on the 128x128 fusion case.
+    the host cores, one map per process; the 16-map batch and the stress mix,
+    one map per process (clearing on sampled rays, scaled); and on the 128x128
+    fusion case.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -58,6 +60,9 @@ TUNING_FILE = os.path.join(ROOT, "paper_2204_12876_amd", "tuning_mi355x.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
 BUDGET_BYTES = 32 << 30
 SLO_S = 0.05          # one frame period at 20 Hz: a later update lags the robot by a frame
+# host copies of the batched and stress workloads' maps and frames, for the
+# oracle baseline: (params, centre, x, y, z, pose) per map
+HOST_SPECS = {}
 
 
 def say(*a):
@@ -109,7 +114,7 @@ def pct(a, q):
 
 
 # ------------------------------------------------------------ algorithmic bytes
-def frame_bytes(n: float, C: float, touched: float, updated: float, moved: float) -> dict:
+def frame_bytes(n: float, C: float, touched: float, updated: float, entering: float) -> dict:
     """Bytes each stage of one frame must move at the least, by kernel role.
       fuse_chunk: the points (12 B) and the prior h, v of each distinct in-map
         cell they hit (8 B);
@@ -119,11 +124,11 @@ def frame_bytes(n: float, C: float, touched: float, updated: float, moved: float
         maxima (9 B); clear_march: each cell's h, v, t_upd, valid and normal
         read once (25 B);
       cells: normals and traversability from h, valid (5 B in, 16 B out);
-      move (a frame whose centre cell changes): every layer read and written
-      once (2 x 29 B)."""
+      move (a frame whose centre cell changes): the ring turns and the cells
+      entering the map are written once (29 B each)."""
     return {"fuse_chunk": 12 * n + 8 * touched, "fuse_tile": 21 * updated,
             "clear_setup": 12 * n + 9 * C, "clear_march": 25 * C, "cells": 21 * C,
-            "move": 58 * C * moved}
+            "move": 29 * entering}
 
 
 PLAIN_KERNEL = {"fuse_chunk": "k_fuse_chunk", "fuse_tile": "k_fuse_tile",
@@ -235,7 +240,7 @@ def serving_context(args, dev):
         a = acc.cpu().numpy().astype(bool)
         m.close()
         C = it["params"]["nx"] * it["params"]["ny"]
-        stats.append(dict(n=f.n, C=C, touched=np.unique(c[c >= 0]).size,
+        stats.append(dict(n=f.n, C=C, ny=it["params"]["ny"], touched=np.unique(c[c >= 0]).size,
                           updated=np.unique(c[a]).size))
     largest = max((it["params"] for it in items), key=lambda p: p["nx"] * p["ny"])
     return dict(items=items, host=host, device=device, stats=stats, weights=w,
@@ -367,7 +372,8 @@ def _serving_kernels(ctx, srv, mk, robots, K, W):
     for r in treqs:
         s = ctx["stats"][r.robot]
         names = BATCH_KERNEL if r.batch_items > 1 else PLAIN_KERNEL
-        for role, b in frame_bytes(s["n"], s["C"], s["touched"], s["updated"], 1.0).items():
+        # the centre alternates by one cell in x: one column enters
+        for role, b in frame_bytes(s["n"], s["C"], s["touched"], s["updated"], s["ny"]).items():
             alg[names[role]] = alg.get(names[role], 0.0) + b
     kernels = kernel_table(kt, alg)
     return kernels, roofline(kernels)
@@ -548,9 +554,11 @@ def single_robot(args, dev):
         n = frames[W + j][0].numel()
         c = cell[:n].cpu().numpy()
         a = acc[:n].cpu().numpy().astype(bool)
-        moved = float(cell_of[W + j] != cell_of[W + j - 1])
+        sx = min(abs(cell_of[W + j][0] - cell_of[W + j - 1][0]), params["nx"])
+        sy = min(abs(cell_of[W + j][1] - cell_of[W + j - 1][1]), params["ny"])
+        entering = sx * params["ny"] + sy * params["nx"] - sx * sy
         for role, b in frame_bytes(n, C, np.unique(c[c >= 0]).size, np.unique(c[a]).size,
-                                   moved).items():
+                                   entering).items():
             if b > 0:
                 alg[PLAIN_KERNEL[role]] = alg.get(PLAIN_KERNEL[role], 0.0) + b
     m.close()
@@ -827,6 +835,12 @@ def batch_vs_plain(args, dev, tuning, specs, label: str, reps: int, cold_copies:
     return out
 
 
+def _host_specs(specs):
+    """(params, centre, x, y, z, pose) with the points copied to host numpy."""
+    return [(p, c, f[0].cpu().numpy(), f[1].cpu().numpy(), f[2].cpu().numpy(),
+             np.asarray(f[3])) for p, c, f in specs]
+
+
 def batched_maps(args, dev, tuning):
     import torch
 
@@ -841,8 +855,9 @@ def batched_maps(args, dev, tuning):
                                                  f.z.contiguous(), f.pose)))
     say(f"generated 16 maps / {sum(f[0].numel() for _, _, f in specs)} points in "
         f"{time.perf_counter() - t_gen:.1f} s")
-    # every copy holds the maps' state (two buffer sets, about 60 B per cell)
-    # and the frames; four copies pass 256 MB several times over
+    HOST_SPECS["batched"] = _host_specs(specs)
+    # every copy holds the maps' state (about 30 B per cell) and the frames;
+    # four copies pass 256 MB several times over
     out = batch_vs_plain(args, dev, tuning, specs, "16 maps", args.batched_reps, cold_copies=4)
     out["workload"] = ("16 maps, sides U{200..1000} at 0.02-0.1 m, one frame each of "
                        "logU[20k, 1M] points, full path")
@@ -904,6 +919,7 @@ def stress(args, dev, tuning, single_ctx):
     sf, sc, sp = single_ctx["frames"], single_ctx["centers"], single_ctx["params"]
     for k in range(8):
         specs.append((sp, sc[k], sf[k][:4]))
+    HOST_SPECS["stress_mix"] = _host_specs(specs)
     b = batch_vs_plain(args, dev, tuning, specs, "stress batch", max(3, args.batched_reps // 4))
     b["workload"] = ("the 2000x2000 map with one 4M-point frame and 8 400x400 maps with one "
                      "300k-point frame each, one batched launch per step")
@@ -943,6 +959,32 @@ def _oracle_worker(job):
             if t_cpu >= seconds:
                 break
     return pts, t_cpu, nfr
+
+
+def _oracle_map_job(job):
+    """One map's frame through the oracle's full path in one process: fusion
+    of every point, clearing of a seeded sample of the rays (its time scaled
+    to all of them), normals and traversability of every cell.  Returns
+    (points, seconds, sampled rays)."""
+    import oracle as O
+    params, centre, xs, ys, zs, pose, weights, ray_sample = job
+    p = O.Params.from_dict(params)
+    st = O.init_map(p, centre[0], centre[1], 0)
+    n = xs.size
+    s = time.perf_counter()
+    st = O.fuse(p, st, xs, ys, zs, pose, 100).state
+    t_fuse = time.perf_counter() - s
+    k = min(n, ray_sample)
+    idx = np.sort(np.random.default_rng(12876).choice(n, size=k, replace=False))
+    s = time.perf_counter()
+    mk = O.clear_visibility(p, st, xs[idx], ys[idx], zs[idx], pose, 100)
+    t_clear = (time.perf_counter() - s) * (n / max(k, 1))
+    st = O.apply_clear(p, st, mk)
+    s = time.perf_counter()
+    st.nrm[:] = O.compute_normals(p, st.h, st.valid).astype(np.float32)
+    T, _ = O.traversability(st.h, st.valid, weights)
+    t_cells = time.perf_counter() - s
+    return n, t_fuse + t_clear + t_cells, k
 
 
 def _cfg0_worker(job):
@@ -1007,6 +1049,25 @@ def cpu_baseline(args, ctx, pool, procs):
     cfg0 = pool.submit(_cfg0_worker, 20).result()
     n0, ts0 = cfg0
     used = len([j for j in jobs if j])
+    # the batched and stress workloads: one map per process
+    multi = {}
+    for key, specs in HOST_SPECS.items():
+        sample = 20000 if key == "batched" else 5000
+        res_m = list(pool.map(_oracle_map_job, [(pr, c_, x_, y_, z_, po_, wts, sample)
+                                                for pr, c_, x_, y_, z_, po_ in specs]))
+        # maps dealt to the processes in turn; the slowest process sets the wall
+        load = [0.0] * procs
+        for i, (_, secs, _) in enumerate(res_m):
+            load[i % procs] += secs
+        n_all = sum(r[0] for r in res_m)
+        multi[key] = {"points_per_s": n_all / max(load), "maps": len(res_m),
+                      "cores": min(procs, len(res_m)), "points": int(n_all),
+                      "seconds_slowest_process": max(load),
+                      "sample": f"fusion of every point, normals and traversability of every "
+                                f"cell; clearing timed on {sample} seeded rays per map and "
+                                f"scaled to all of them"}
+        say(f"oracle on {key}: {n_all / max(load) / 1e6:.2f} M points/s over "
+            f"{min(procs, len(res_m))} processes")
     return {"value": pts / wall, "unit": "points/s", "cores": used, "kind": "oracle",
             "sample": f"the serving workload's robot frames (full path: move, fusion, clearing, "
                       f"normals, traversability), {used} processes of one thread each, each "
@@ -1017,7 +1078,8 @@ def cpu_baseline(args, ctx, pool, procs):
                             "seconds": one[1], "cores": 1},
             "fusion_128x128_20k": {"points_per_s": n0 / float(np.median(ts0)),
                                    "median_ms": float(np.median(ts0) * 1e3), "reps": len(ts0),
-                                   "cores": 1}}
+                                   "cores": 1},
+            "per_workload": multi}
 
 
 def autotune_batched(dev, out_path):

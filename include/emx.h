@@ -134,10 +134,11 @@ const char* emx_last_error(void);
 /* Host-only check of a parameter block.  Returns EMX_OK or EMX_EINVAL. */
 emx_status emx_params_check(const emx_params* params);
 
-/* Device bytes of one map's state: two buffer sets of layers (move_map writes
- * the shifted map into the other set; with upper_bound = 1 each set also holds
- * the upper bound layer), 16 bytes of clearing scratch per cell and a small
- * control block.  Returns 0 for invalid parameters. */
+/* Device bytes of one map's state: one set of layers stored as a ring (see
+ * emx_layer; with upper_bound = 1 it also holds the upper bound layer), 8
+ * bytes of clearing scratch per cell and a small control block (the clearing
+ * queue counters and one word per 32x16-cell fusion tile).  Returns 0 for
+ * invalid parameters. */
 size_t emx_state_bytes(const emx_params* params);
 
 /* Device scratch bytes emx_fuse_points and emx_clear_visibility need for
@@ -182,8 +183,9 @@ emx_status emx_free_map(emx_map* map);
  * shifts by whole cells to centre cell (floor(cx/r), floor(cy/r)).
  *   - Cells that stay in the map keep every layer.
  *   - Cells that enter take the prior, as in emx_init_map.
- * A zero shift enqueues nothing.  Layer pointers from emx_layer() change after
- * a non-zero shift. */
+ * The layers are a ring: the move turns it (emx_map_origin changes) and resets
+ * only the entering rows and columns, so its cost is the strips, not the map.
+ * A zero shift enqueues nothing.  Layer pointers from emx_layer() stay valid. */
 emx_status emx_move_map(emx_map* map, double cx, double cy, void* stream);
 
 /* Fuse one point cloud into the map (Sec. II-C, Eq. 1 and Eq. 2).
@@ -359,14 +361,23 @@ emx_status emx_inpaint_min(emx_map* map, float* d_out, void* d_scratch, size_t s
 emx_status emx_smooth(const float* d_in, float* d_out, int32_t nx, int32_t ny, int32_t kind,
                       int32_t ksize, float sigma, void* stream);
 
-/* Device pointer of a layer of the current buffer set. */
+/* Device pointer of a layer, [ny][nx] elements stored as a ring: local cell
+ * (ix, iy) is element ((iy + oy) mod ny) * nx + (ix + ox) mod nx, with the
+ * ring origin (ox, oy) of emx_map_origin.  A move turns the ring (the origin
+ * changes) and resets only the cells that enter the map; the pointer stays
+ * valid for the map's lifetime. */
 emx_status emx_layer(emx_map* map, int32_t layer, void** d_ptr);
+
+/* The ring origin of the map's layers (see emx_layer), as of the last call
+ * enqueued on the map.  Out-pointers may be NULL. */
+emx_status emx_map_origin(emx_map* map, int32_t* ox, int32_t* oy);
 
 /* Host-side geometry of a map.  Out-pointers may be NULL. */
 emx_status emx_map_info(emx_map* map, int32_t* cgx, int32_t* cgy, int64_t* t0_ms);
 
 /* Copy the layers out to (or in from) a packed device buffer of
- * emx_export_bytes() bytes, in the format described there. */
+ * emx_export_bytes() bytes, in the format described there, in local cell
+ * order (the ring is unrolled; the origin does not change). */
 emx_status emx_export_state(emx_map* map, void* d_dst, void* stream);
 emx_status emx_import_state(emx_map* map, const void* d_src, void* stream);
 

@@ -186,9 +186,9 @@ class ElevationMap:
         return out
 
     def upper_bound(self) -> torch.Tensor:
-        """The upper bound layer (Sec. II-H), a [ny, nx] float32 view; the map
-        must have been created with upper_bound=1."""
-        return self.layer(_emx.LAYER_UPPER)
+        """The upper bound layer (Sec. II-H) in local cell order, a [ny, nx]
+        float32 copy; the map must have been created with upper_bound=1."""
+        return self.local(_emx.LAYER_UPPER)
 
     def compute_normals(self):
         _emx.compute_normals(self.handle, _stream(self.device))
@@ -207,7 +207,9 @@ class ElevationMap:
 
     # ----------------------------------------------------------------- state
     def layer(self, layer_id: int) -> torch.Tensor:
-        """A [ny, nx] view of one layer of the current buffer set."""
+        """A [ny, nx] view of one layer as stored: a ring with origin
+        ``origin()`` (local cell (ix, iy) at row (iy + oy) % ny, column
+        (ix + ox) % nx)."""
         ptr = _emx.layer(self.handle, layer_id)
         off = ptr - self._state.data_ptr()
         C = self.nx * self.ny
@@ -215,6 +217,15 @@ class ElevationMap:
             return self._state[off:off + C].view(self.ny, self.nx)
         dt = torch.int32 if layer_id == _emx.LAYER_TIME else torch.float32
         return self._state[off:off + 4 * C].view(dt).view(self.ny, self.nx)
+
+    def origin(self):
+        """The ring origin (ox, oy) of the stored layers."""
+        return _emx.map_origin(self.handle)
+
+    def local(self, layer_id: int) -> torch.Tensor:
+        """One layer in local cell order (a copy of the ring, unrolled)."""
+        ox, oy = self.origin()
+        return torch.roll(self.layer(layer_id), shifts=(-oy, -ox), dims=(0, 1)).contiguous()
 
     def info(self):
         return _emx.map_info(self.handle)

@@ -95,6 +95,7 @@ _SIGS = {
     "emx_normals_traversability": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "emx_layer": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
     "emx_map_info": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int64)]),
+    "emx_map_origin": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     "emx_export_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "emx_import_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "emx_batch_create": (c_int32, [c_char_p, POINTER(c_void_p)]),
@@ -295,6 +296,12 @@ def layer(h: int, layer_id: int) -> int:
     p = c_void_p()
     check(lib().emx_layer(c_void_p(h), int(layer_id), byref(p)))
     return p.value
+
+
+def map_origin(h: int):
+    ox, oy = c_int32(), c_int32()
+    check(lib().emx_map_origin(c_void_p(h), byref(ox), byref(oy)))
+    return ox.value, oy.value
 
 
 def map_info(h: int):

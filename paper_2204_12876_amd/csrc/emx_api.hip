@@ -101,6 +101,8 @@ Consts make_consts(const emx_params& p) {
   c.excl_c = p.excl_c;
   c.excl_d = p.excl_d;
   c.var_o = p.outlier_variance;
+  c.ox = 0;
+  c.oy = 0;
   return c;
 }
 
@@ -167,8 +169,7 @@ emx_status check_frame(const emx_frame* f) {
 emx_status make_item(const emx_map* m, const emx_frame* f, Item* it) {
   memset(it, 0, sizeof(Item));
   it->c = m->c;
-  it->L = m->sets[m->cur];
-  it->Lsrc = m->sets[m->cur];
+  it->L = m->L;
   it->tiles_x = tiles_x_of(m->p.nx);
   it->T = tiles_of(m->p);
   it->bl = block_log_of(m->p.nx, m->p.ny);
@@ -202,6 +203,11 @@ emx_status make_item(const emx_map* m, const emx_frame* f, Item* it) {
   return EMX_OK;
 }
 
+void turn_ring(const Consts& c, int sx, int sy, int* ox, int* oy) {
+  *ox = (int)((((int64_t)c.ox + sx) % c.nx + c.nx) % c.nx);
+  *oy = (int)((((int64_t)c.oy + sy) % c.ny + c.ny) % c.ny);
+}
+
 bool plan_move(const emx_map* m, double cx, double cy, int64_t* ngx, int64_t* ngy, int* sx,
                int* sy) {
   if (!center_cell(cx, m->p.resolution, ngx) || !center_cell(cy, m->p.resolution, ngy))
@@ -227,7 +233,7 @@ emx_status emx_params_check(const emx_params* params) { return check_params(para
 
 size_t emx_state_bytes(const emx_params* params) {
   if (check_params(params) != EMX_OK) return 0;
-  return align256(2 * set_layout(*params, nullptr, nullptr) + clr_bytes(*params) +
+  return align256(set_layout(*params, nullptr, nullptr) + clr_bytes(*params) +
                   ctl_words(*params) * sizeof(uint32_t));
 }
 
@@ -271,18 +277,13 @@ emx_status emx_init_map(const emx_params* params, double cx, double cy, int64_t 
   m->cgy = cgy;
   m->t0 = t0_ms;
   m->state = (char*)d_state;
-  m->set_bytes = set_layout(*params, nullptr, nullptr);
-  set_layout(*params, m->state, &m->sets[0]);
-  set_layout(*params, m->state + m->set_bytes, &m->sets[1]);
-  float2* clr = (float2*)(m->state + 2 * m->set_bytes);
-  m->sets[0].clr = clr;
-  m->sets[1].clr = clr;
-  m->cur = 0;
+  const size_t set_bytes = set_layout(*params, m->state, &m->L);
+  m->L.clr = (float2*)(m->state + set_bytes);
   m->ctr_sel = 0;
-  m->ctl = (uint32_t*)(m->state + 2 * m->set_bytes + clr_bytes(*params));
+  m->ctl = (uint32_t*)(m->state + set_bytes + clr_bytes(*params));
   m->march_grid = persistent_grid(kMarchPerCU);
   hipError_t e =
-      launch_fill_prior(m->c, m->sets[0], m->ctl, (int)ctl_words(*params), (hipStream_t)stream);
+      launch_fill_prior(m->c, m->L, m->ctl, (int)ctl_words(*params), (hipStream_t)stream);
   if (e != hipSuccess) {
     delete m;
     return hip_fail(e, "init_map");
@@ -305,16 +306,16 @@ emx_status emx_move_map(emx_map* m, double cx, double cy, void* stream) {
   if (!plan_move(m, cx, cy, &ngx, &ngy, &sx, &sy))
     return fail(EMX_EINVAL, "map centre out of range");
   if (sx == 0 && sy == 0) return EMX_OK;
-  const int nxt = 1 - m->cur;
+  emx_map moved = *m;
+  turn_ring(m->c, sx, sy, &moved.c.ox, &moved.c.oy);
   Item it;
-  make_item(m, nullptr, &it);
-  it.Lsrc = m->sets[m->cur];
-  it.L = m->sets[nxt];
+  make_item(&moved, nullptr, &it);
   it.sx = sx;
   it.sy = sy;
   hipError_t e = launch_move(it, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "move_map");
-  m->cur = nxt;
+  m->c.ox = moved.c.ox;
+  m->c.oy = moved.c.oy;
   m->cgx = ngx;
   m->cgy = ngy;
   return EMX_OK;
@@ -333,16 +334,15 @@ static emx_status fuse_impl(emx_map* m, const emx_frame* f, bool move, double cx
   if (move && !plan_move(m, cx, cy, &ngx, &ngy, &sx, &sy))
     return fail(EMX_EINVAL, "map centre out of range");
   const bool shift = sx != 0 || sy != 0;
-  // the item on the moved map: new origin, the other buffer set
+  // the item on the moved map: new centre, the ring turned
   emx_map moved = *m;
   if (shift) {
     moved.cgx = ngx;
     moved.cgy = ngy;
-    moved.cur = 1 - m->cur;
+    turn_ring(m->c, sx, sy, &moved.c.ox, &moved.c.oy);
   }
   Item it;
   if ((s = make_item(&moved, f, &it)) != EMX_OK) return s;
-  it.Lsrc = m->sets[m->cur];
   it.sx = sx;
   it.sy = sy;
   const bool run = f->n > 0 || m->p.time_variance != 0.0f;  // time variance: every call
@@ -364,7 +364,8 @@ static emx_status fuse_impl(emx_map* m, const emx_frame* f, bool move, double cx
   if (e == hipSuccess && run) e = launch_fuse(it, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, move ? "move_fuse_points" : "fuse_points");
   if (shift) {
-    m->cur = moved.cur;
+    m->c.ox = moved.c.ox;
+    m->c.oy = moved.c.oy;
     m->cgx = ngx;
     m->cgy = ngy;
   }
@@ -510,7 +511,7 @@ emx_status emx_overlap_clear(emx_map* m, double rx, double ry, double rz, float 
   const double oy = (double)(m->cgy - m->p.ny / 2) * m->p.resolution;
   OverlapArgs a;
   a.c = m->c;
-  a.L = m->sets[m->cur];
+  a.L = m->L;
   a.r32 = (float)m->p.resolution;
   a.rx = (float)(rx - ox);
   a.ry = (float)(ry - oy);
@@ -542,7 +543,7 @@ emx_status emx_inpaint_min(emx_map* m, float* d_out, void* d_scratch, size_t scr
   if (scratch_bytes < need)
     return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
   hipError_t e =
-      launch_inpaint(m->c, m->sets[m->cur], d_out, (char*)d_scratch, (hipStream_t)stream);
+      launch_inpaint(m->c, m->L, d_out, (char*)d_scratch, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "inpaint_min");
   return EMX_OK;
 }
@@ -612,7 +613,7 @@ emx_status emx_layer(emx_map* m, int32_t layer, void** d_ptr) {
   emx_status s = check_map(m);
   if (s != EMX_OK) return s;
   if (!d_ptr) return fail(EMX_EINVAL, "d_ptr is NULL");
-  const Layers& L = m->sets[m->cur];
+  const Layers& L = m->L;
   void* p = nullptr;
   switch (layer) {
     case EMX_LAYER_HEIGHT: p = L.h; break;
@@ -642,17 +643,43 @@ emx_status emx_map_info(emx_map* m, int32_t* cgx, int32_t* cgy, int64_t* t0_ms) 
   return EMX_OK;
 }
 
+emx_status emx_map_origin(emx_map* m, int32_t* ox, int32_t* oy) {
+  emx_status s = check_map(m);
+  if (s != EMX_OK) return s;
+  if (ox) *ox = m->c.ox;
+  if (oy) *oy = m->c.oy;
+  return EMX_OK;
+}
+
+// Between the packed logical layers and the ring: each layer is four
+// rectangles, logical [0, nx-ox) x [0, ny-oy) at physical (ox, oy), and so on.
 static emx_status copy_state(emx_map* m, char* packed, bool out, hipStream_t st) {
-  const Layers& L = m->sets[m->cur];
-  const size_t C = (size_t)m->p.nx * (size_t)m->p.ny;
+  const Layers& L = m->L;
+  const int nx = m->p.nx, ny = m->p.ny, ox = m->c.ox, oy = m->c.oy;
+  const size_t C = (size_t)nx * (size_t)ny;
   void* lay[8] = {L.h, L.v, L.t, L.nx, L.ny, L.nz, L.trav, L.valid};
+  // logical start, physical start and extent of the two pieces of an axis
+  const int lx[2] = {0, nx - ox}, px[2] = {ox, 0}, wx[2] = {nx - ox, ox};
+  const int ly[2] = {0, ny - oy}, py[2] = {oy, 0}, hy[2] = {ny - oy, oy};
   size_t off = 0;
   for (int k = 0; k < 8; ++k) {
-    const size_t bytes = (k < 7 ? 4 : 1) * C;
-    hipError_t e = out ? hipMemcpyAsync(packed + off, lay[k], bytes, hipMemcpyDeviceToDevice, st)
-                       : hipMemcpyAsync(lay[k], packed + off, bytes, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, out ? "export_state" : "import_state");
-    off += bytes;
+    const size_t es = k < 7 ? 4 : 1;
+    char* pk = packed + off;
+    char* ring = (char*)lay[k];
+    for (int j = 0; j < 2; ++j)
+      for (int i = 0; i < 2; ++i) {
+        if (wx[i] == 0 || hy[j] == 0) continue;
+        char* lp = pk + ((size_t)ly[j] * nx + lx[i]) * es;
+        char* rp = ring + ((size_t)py[j] * nx + px[i]) * es;
+        const size_t pitch = (size_t)nx * es;
+        hipError_t e =
+            out ? hipMemcpy2DAsync(lp, pitch, rp, pitch, (size_t)wx[i] * es, (size_t)hy[j],
+                                   hipMemcpyDeviceToDevice, st)
+                : hipMemcpy2DAsync(rp, pitch, lp, pitch, (size_t)wx[i] * es, (size_t)hy[j],
+                                   hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, out ? "export_state" : "import_state");
+      }
+    off += es * C;
   }
   return EMX_OK;
 }

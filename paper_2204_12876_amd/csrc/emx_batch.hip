@@ -312,7 +312,7 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
   bool key64 = false;
   // plan every item on copies of the map geometry: no map changes until the
   // whole batch has been checked
-  int cur[kMaxItems];
+  int ox[kMaxItems], oy[kMaxItems];
   int64_t cgx[kMaxItems], cgy[kMaxItems];
   for (int32_t i = 0; i < n; ++i) {
     const emx_batch_item& bi = items[i];
@@ -323,7 +323,7 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
       int64_t ngx, ngy;
       plan_move(bi.map, bi.cx, bi.cy, &ngx, &ngy, &sx, &sy);
       if (sx != 0 || sy != 0) {
-        tmp.cur = 1 - tmp.cur;
+        turn_ring(bi.map->c, sx, sy, &tmp.c.ox, &tmp.c.oy);
         tmp.cgx = ngx;
         tmp.cgy = ngy;
       }
@@ -331,7 +331,6 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
     const bool pts = (bi.stages & (EMX_STAGE_FUSE | EMX_STAGE_CLEAR)) != 0;
     s = make_item(&tmp, pts ? &bi.frame : nullptr, &it);
     if (s != EMX_OK) return fail(s, "item %d: %s", i, last_error_text());
-    it.Lsrc = bi.map->sets[bi.map->cur];
     it.sx = sx;
     it.sy = sy;
     it.stages = bi.stages;
@@ -340,7 +339,8 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
     it.out_accept = bi.d_out_accept;
     it.out_cleared = bi.d_out_cleared;
     it.index = i;
-    cur[i] = tmp.cur;
+    ox[i] = tmp.c.ox;
+    oy[i] = tmp.c.oy;
     cgx[i] = tmp.cgx;
     cgy[i] = tmp.cgy;
     if ((bi.stages & EMX_STAGE_FUSE) && it.n > 0 && fuse_needs_key64(it.T)) key64 = true;
@@ -362,7 +362,7 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
     // after an empty frame)
     const bool var = (st & EMX_STAGE_FUSE) &&
                      (it.c.var_t != 0.0f || (it.c.var_o != 0.0f && it.n > 0));
-    tab->off[kBMove][i + 1] = tab->off[kBMove][i] + (moved ? move_units(it.c.nx, it.c.ny) : 0);
+    tab->off[kBMove][i + 1] = tab->off[kBMove][i] + (moved ? move_units(it) : 0);
     tab->off[kBZero][i + 1] = tab->off[kBZero][i] + (wall ? zero_units(cells) : 0);
     tab->off[kBCount][i + 1] = tab->off[kBCount][i] + (wall ? it.B : 0);
     tab->off[kBChunk][i + 1] = tab->off[kBChunk][i] + (fuse ? it.B : 0);
@@ -457,7 +457,8 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
   ++b->batches;
   // the moves are enqueued: commit the maps' new geometry
   for (int32_t i = 0; i < n; ++i) {
-    items[i].map->cur = cur[i];
+    items[i].map->c.ox = ox[i];
+    items[i].map->c.oy = oy[i];
     items[i].map->cgx = cgx[i];
     items[i].map->cgy = cgy[i];
   }

@@ -41,36 +41,69 @@ __global__ __launch_bounds__(kNTf) void k_fill_prior(FillArgs a) {
 }
 
 // ------------------------------------------------------------------------ move
-constexpr int kMoveW = 64;  // a move unit is 64 x 4 cells
-constexpr int kMoveH = kNTf / kMoveW;
+// The ring has already turned (it.c holds the new origin); the cells that
+// enter the map go back to the prior.  With a shift (sx, sy) they are the
+// logical columns [nx - sx, nx) (sx > 0) or [0, -sx) (sx < 0) in every row,
+// and the logical rows [ny - sy, ny) or [0, -sy) in every column; a shift of a
+// whole side resets every cell.  One thread per cell: the column strip, then
+// the row strip (their corner twice, with the same values).
+struct Strips {
+  int ncol, nrow;   // entering columns and rows
+  bool all;         // every cell enters
+  int64_t cells;    // threads needed
+};
 
-// One thread per cell of a 64 x 4 unit.
+__host__ __device__ __forceinline__ Strips strips_of(const Item& it) {
+  Strips s;
+  const int ax = it.sx < 0 ? -it.sx : it.sx;
+  const int ay = it.sy < 0 ? -it.sy : it.sy;
+  s.ncol = ax < it.c.nx ? ax : it.c.nx;
+  s.nrow = ay < it.c.ny ? ay : it.c.ny;
+  s.all = s.ncol == it.c.nx || s.nrow == it.c.ny;
+  s.cells = s.all ? (int64_t)it.c.nx * it.c.ny
+                  : (int64_t)s.ncol * it.c.ny + (int64_t)s.nrow * it.c.nx;
+  return s;
+}
+
 __device__ __forceinline__ void move_body(const Item& it, int64_t unit) {
-  const int ux = blocks_of(it.c.nx, 6);
-  const int ix = (int)(unit % ux) * kMoveW + (threadIdx.x & (kMoveW - 1));
-  const int iy = (int)(unit / ux) * kMoveH + (threadIdx.x / kMoveW);
-  if (ix >= it.c.nx || iy >= it.c.ny) return;
-  float h, v;
-  move_cell(it, ix, iy, h, v);
+  const Strips st = strips_of(it);
+  const int64_t q = unit * kNTf + threadIdx.x;
+  if (q >= st.cells) return;
+  int ix, iy;
+  if (st.all) {
+    iy = (int)(q / it.c.nx);
+    ix = (int)(q - (int64_t)iy * it.c.nx);
+  } else if (q < (int64_t)st.ncol * it.c.ny) {
+    iy = (int)(q / st.ncol);
+    const int k = (int)(q - (int64_t)iy * st.ncol);
+    ix = it.sx > 0 ? it.c.nx - st.ncol + k : k;
+  } else {
+    const int64_t q2 = q - (int64_t)st.ncol * it.c.ny;
+    const int k = (int)(q2 / it.c.nx);
+    ix = (int)(q2 - (int64_t)k * it.c.nx);
+    iy = it.sy > 0 ? it.c.ny - st.nrow + k : k;
+  }
+  prior_cell(it.c, it.L, pcell(it.c, ix, iy));
 }
 
 // ------------------------------------------------------------ overlap clearance
 // Valid cells within a horizontal radius of the robot whose height differs
 // from the robot's by more than the threshold return to the prior.
 __global__ __launch_bounds__(kNTf) void k_overlap(OverlapArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * kNTf + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kNTf + threadIdx.x;  // logical cell
   const int64_t C = (int64_t)a.c.nx * a.c.ny;
   if (i >= C) return;
   const int iy = (int)(i / a.c.nx);
   const int ix = (int)(i - (int64_t)iy * a.c.nx);
+  const int64_t p = pcell(a.c, ix, iy);
   const float dx = ((float)ix + 0.5f) * a.r32 - a.rx;
   const float dy = ((float)iy + 0.5f) * a.r32 - a.ry;
-  const bool hit = a.L.valid[i] && ((dx * dx + dy * dy) <= a.rad2) &&
-                   (fabsf(a.L.h[i] - a.rz) > a.thr);
+  const bool hit = a.L.valid[p] && ((dx * dx + dy * dy) <= a.rad2) &&
+                   (fabsf(a.L.h[p] - a.rz) > a.thr);
   if (hit) {
-    a.L.h[i] = a.c.h_init;
-    a.L.v[i] = a.c.v_init;
-    a.L.valid[i] = 0;
+    a.L.h[p] = a.c.h_init;
+    a.L.v[p] = a.c.v_init;
+    a.L.valid[p] = 0;
   }
   if (a.out) a.out[i] = hit ? 1 : 0;
 }
@@ -98,14 +131,14 @@ __device__ __forceinline__ void load_halo(HaloTile& s, const Consts& c, const La
   for (int ly = wave; ly < kHH; ly += kNTf / 64) {
     const int gy = y0 - 1 + ly;
     const bool row = gy >= 0 && gy < c.ny;
-    const int64_t rb = (int64_t)gy * c.nx;
     {  // body column lx = lane + 1
       const int gx = x0 + lane;
       float hv = 0.0f;
       uint8_t ok = 0;
       if (row && gx < c.nx) {
-        ok = L.valid[rb + gx];
-        hv = L.h[rb + gx];
+        const int64_t o = pcell(c, gx, gy);
+        ok = L.valid[o];
+        hv = L.h[o];
       }
       s.h[ly][lane + 1] = hv;
       s.ok[ly][lane + 1] = ok;
@@ -116,8 +149,9 @@ __device__ __forceinline__ void load_halo(HaloTile& s, const Consts& c, const La
       float hv = 0.0f;
       uint8_t ok = 0;
       if (row && gx >= 0 && gx < c.nx) {
-        ok = L.valid[rb + gx];
-        hv = L.h[rb + gx];
+        const int64_t o = pcell(c, gx, gy);
+        ok = L.valid[o];
+        hv = L.h[o];
       }
       s.h[ly][lx] = hv;
       s.ok[ly][lx] = ok;
@@ -193,7 +227,7 @@ __device__ __forceinline__ void cells_body(const Item& it, int64_t unit, bool do
     const int lx = tx + 1;
     const int ly = ty + 1;
     const bool ok = window_ok(s, it.c, gx, gy, lx, ly);
-    const int64_t o = (int64_t)gy * it.c.nx + gx;
+    const int64_t o = pcell(it.c, gx, gy);
     if (do_n) {
       float nx = qnan, ny = qnan, nz = qnan;
       if (ok) normal_at(s, lx, ly, it.c.inv6r, nx, ny, nz);
@@ -243,7 +277,7 @@ __global__ __launch_bounds__(kNTf) void k_cells_b(const Batch* bt) {
 
 }  // namespace
 
-int64_t move_units(int nx, int ny) { return (int64_t)blocks_of(nx, 6) * ((ny + kMoveH - 1) / kMoveH); }
+int64_t move_units(const Item& it) { return (strips_of(it).cells + kNTf - 1) / kNTf; }
 int64_t cells_units(int nx, int ny) {
   return (int64_t)blocks_of(nx, kSWLog) * blocks_of(ny, kSHLog);
 }
@@ -271,9 +305,10 @@ hipError_t launch_overlap(const OverlapArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_move(const Item& it, hipStream_t stream) {
+  const int64_t units = move_units(it);
+  if (units == 0) return hipSuccess;
   TimedLaunch tl("k_move", stream);
-  hipLaunchKernelGGL(k_move, dim3((unsigned)move_units(it.c.nx, it.c.ny)), dim3(kNTf), 0, stream,
-                     it);
+  hipLaunchKernelGGL(k_move, dim3((unsigned)units), dim3(kNTf), 0, stream, it);
   return hipGetLastError();
 }
 

@@ -151,19 +151,20 @@ __device__ __forceinline__ void atomic_min_f32(float* a, float v) {
   else atomicMax(reinterpret_cast<unsigned int*>(a), __float_as_uint(v));
 }
 
-// A cell can be removed only if it is valid, older than the minimum age and
-// has a normal.
-__device__ __forceinline__ bool clearable(const Item& it, int64_t c) {
-  return it.L.valid[c] && (((int64_t)it.t_now - (int64_t)it.L.t[c]) > (int64_t)it.c.tau) &&
-         !isnan(it.L.nz[c]);
+// A cell (physical index pc) can be removed only if it is valid, older than
+// the minimum age and has a normal.
+__device__ __forceinline__ bool clearable(const Item& it, int64_t pc) {
+  return it.L.valid[pc] && (((int64_t)it.t_now - (int64_t)it.L.t[pc]) > (int64_t)it.c.tau) &&
+         !isnan(it.L.nz[pc]);
 }
 
-// Removal of cell c: back to the prior, invalid; flagged in the caller's mask.
-__device__ __forceinline__ void clear_cell(const Item& it, int c) {
-  it.L.h[c] = it.c.h_init;
-  it.L.v[c] = it.c.v_init;
-  it.L.valid[c] = 0;
-  if (it.out_cleared) it.out_cleared[c] = 1;
+// Removal of a cell: back to the prior, invalid (physical index pc); flagged
+// in the caller's mask (logical index lc).
+__device__ __forceinline__ void clear_cell(const Item& it, int64_t pc, int lc) {
+  it.L.h[pc] = it.c.h_init;
+  it.L.v[pc] = it.c.v_init;
+  it.L.valid[pc] = 0;
+  if (it.out_cleared) it.out_cleared[lc] = 1;
 }
 
 // The removal test of sample q (height qz) in cell c, from the cell's
@@ -173,16 +174,16 @@ __device__ __forceinline__ void clear_cell(const Item& it, int c) {
 // height.  On maps with an upper bound layer, a cell without an estimate holds
 // NaN in place of the height (no other record does), which sends the sample
 // to its bound.
-__device__ __forceinline__ void test_cell_rec(const Item& it, const Ray& r, int c, float qz,
-                                              float an2dd, const float2 k) {
+__device__ __forceinline__ void test_cell_rec(const Item& it, const Ray& r, int lc, int64_t pc,
+                                              float qz, float an2dd, const float2 k) {
   if (isnan(k.x)) {
-    atomic_min_f32(it.L.ub + c, qz);
+    atomic_min_f32(it.L.ub + pc, qz);
     return;
   }
   const float hd = k.x - qz;
   if (!(hd > 0.0f) || !((hd * hd) > k.y)) return;
-  const float dot = (r.dx * it.L.nx[c] + r.dy * it.L.ny[c]) + r.dz * it.L.nz[c];
-  if ((dot * dot) > an2dd) clear_cell(it, c);
+  const float dot = (r.dx * it.L.nx[pc] + r.dy * it.L.ny[pc]) + r.dz * it.L.nz[pc];
+  if ((dot * dot) > an2dd) clear_cell(it, pc, lc);
 }
 
 // The ray of point i of the item: origin, direction, sample count K and the
@@ -222,7 +223,8 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
   const float inv_r = it.c.inv_r;
   const int nx = it.c.nx;
   for (int k = ka; k <= kb; k += kUnroll) {
-    int cell[kUnroll];
+    int cell[kUnroll];     // logical: the end-cell test, the records
+    int64_t pc[kUnroll];   // physical: the layers
     float qz[kUnroll];
     float m[kUnroll];
     bool cand[kUnroll];
@@ -240,6 +242,7 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
       const int ix = (int)(qx * inv_r);
       const int iy = (int)(qy * inv_r);
       cell[u] = iy * nx + ix;
+      pc[u] = pcell(it.c, ix, iy);
       // every slot's block maximum is loaded before any is used, so the
       // loads of the kUnroll samples are in flight together
       m[u] = cm[(uint32_t)((iy >> bl) * bx + (ix >> bl))];
@@ -257,7 +260,7 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (!cand[u]) continue;
-      test_cell_rec(it, r, cell[u], qz[u], an2dd, rec[u]);
+      test_cell_rec(it, r, cell[u], pc[u], qz[u], an2dd, rec[u]);
     }
   }
 }
@@ -273,7 +276,8 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
     // one cell of each per lane, so their loads are in flight together
     const int b0 = (unit * (kNTc / 64) + (threadIdx.x >> 6)) * it.bpw;
     const int side = 1 << it.bl;
-    int64_t c[kMaxBlocksPerWave];
+    int64_t c[kMaxBlocksPerWave];   // logical cell: the mask, the records
+    int64_t p[kMaxBlocksPerWave];   // physical cell: the layers
     bool inside[kMaxBlocksPerWave], ok[kMaxBlocksPerWave];
     float h[kMaxBlocksPerWave], v[kMaxBlocksPerWave];
 #pragma unroll
@@ -283,13 +287,14 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
       const int iy = ((b / it.bx) << it.bl) + (lane >> it.bl);
       inside[j] = j < it.bpw && b < it.nb && ix < it.c.nx && iy < it.c.ny;
       c[j] = inside[j] ? (int64_t)iy * it.c.nx + ix : 0;
+      p[j] = inside[j] ? pcell(it.c, ix, iy) : 0;
       if (inside[j] && it.out_cleared) it.out_cleared[c[j]] = 0;  // the march sets removals
-      ok[j] = inside[j] && clearable(it, c[j]);
-      h[j] = inside[j] ? it.L.h[c[j]] : 0.0f;
+      ok[j] = inside[j] && clearable(it, p[j]);
+      h[j] = inside[j] ? it.L.h[p[j]] : 0.0f;
       v[j] = ok[j] ? h[j] : -INFINITY;
       // with an upper bound layer, a sample below the bound of a cell without
       // an estimate lowers it: such cells take part in the maximum too
-      if (it.L.ub && inside[j] && !it.L.valid[c[j]]) v[j] = it.L.ub[c[j]];
+      if (it.L.ub && inside[j] && !it.L.valid[p[j]]) v[j] = it.L.ub[p[j]];
     }
 #pragma unroll
     for (int j = 0; j < kMaxBlocksPerWave; ++j) {
@@ -301,9 +306,9 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
       // some sample may pass below the block maximum
       if (v[j] > -INFINITY && inside[j]) {
         // a NaN height can never be cleared (hd > 0 fails), so -inf serves
-        const bool bound = it.L.ub && !it.L.valid[c[j]];
+        const bool bound = it.L.ub && !it.L.valid[p[j]];
         const float hx = bound ? __builtin_nanf("") : (ok[j] && !isnan(h[j]) ? h[j] : -INFINITY);
-        it.L.clr[c[j]] = make_float2(hx, it.L.v[c[j]]);
+        it.L.clr[c[j]] = make_float2(hx, it.L.v[p[j]]);
       }
     }
     return;

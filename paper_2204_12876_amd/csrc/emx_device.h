@@ -37,6 +37,7 @@ constexpr int kOverCtr = kSubQ * kCtrStride;          // the overflow list's cou
 constexpr int kCtrWords = (kSubQ + 1) * kCtrStride;   // one set of queue counters
 
 // One buffer set of map layers, row-major [ny][nx].
+// The map's layers, [ny][nx] each in the ring layout (pcell).
 struct Layers {
   float* h;
   float* v;
@@ -46,11 +47,10 @@ struct Layers {
   float* nz;
   float* trav;
   uint8_t* valid;
-  uint8_t* mark;  // clearing marks; all zero between calls
-  float* cmax;    // per block: max height over cells a ray may clear (transient)
+  uint8_t* mark;  // the fusion's per-cell flags (kMark*); all zero between calls
+  float* cmax;    // per logical block: max height over cells a ray may clear (transient)
   float* ub;      // upper bound of the ground height (+inf: none), or null
-  float2* clr;    // per cell {h, or -inf if a ray may not clear it, v}
-                  // (transient; one array per map, shared by both sets)
+  float2* clr;    // per logical cell {h, or -inf if a ray may not clear it, v} (transient)
 };
 
 // Clearing prunes samples by square blocks of 8 x 8 cells: one cell per lane
@@ -86,6 +86,7 @@ struct Consts {
   float excl_slope;    // float32(tan(theta_a))
   float excl_b, excl_c, excl_d;
   float var_o;     // outlier variance per fusion, 0 = off
+  int ox, oy;      // ring origin: physical column and row of logical cell (0, 0)
 };
 
 // Sensor -> map-local transform, float32.
@@ -133,14 +134,13 @@ constexpr uint32_t kStageTrav = 16u;
 struct Item {
   Consts c;
   Pose32 P;
-  Layers L;     // current buffer set (after any move)
-  Layers Lsrc;  // move source set (the move kernel)
+  Layers L;     // the map's layers (ring layout; c holds the origin after any move)
   const float* x;
   const float* y;
   const float* z;
   int64_t n;
   int32_t t_now;
-  int sx, sy;   // move shift in cells
+  int sx, sy;   // move shift in cells (the cells entering the map)
   uint32_t stages;
   const float* w;  // traversability weights (89)
   int32_t* out_cell;
@@ -216,50 +216,33 @@ __device__ __forceinline__ bool bin_xy(float xm, float ym, const Consts& c, int&
   return true;
 }
 
-// ---------------------------------------------------------------- move
-// Source cell of local cell (ix, iy) under the move by (sx, sy), or -1 where
-// the cell enters the map.
-__device__ __forceinline__ int64_t move_source(const Item& it, int ix, int iy) {
-  const int jx = ix + it.sx;
-  const int jy = iy + it.sy;
-  if (jx < 0 || jx >= it.c.nx || jy < 0 || jy >= it.c.ny) return -1;
-  return (int64_t)jy * it.c.nx + jx;
+// ---------------------------------------------------------------- ring layout
+// The map is stored as a ring (a circular buffer in both axes): logical cell
+// (ix, iy) lives at physical cell pcell(c, ix, iy), with the origin (ox, oy)
+// the physical column and row of logical (0, 0).  A move turns the ring
+// instead of copying the layers; only the cells that enter the map are reset.
+__host__ __device__ __forceinline__ int64_t pcell(const Consts& c, int ix, int iy) {
+  int px = ix + c.ox;
+  px -= (px >= c.nx) ? c.nx : 0;
+  int py = iy + c.oy;
+  py -= (py >= c.ny) ? c.ny : 0;
+  return (int64_t)py * c.nx + px;
 }
 
-// dst(ix, iy) <- src(ix + sx, iy + sy), or the prior where that is outside;
-// the mark is cleared.  Returns the cell's height and variance.
-__device__ __forceinline__ void move_cell(const Item& it, int ix, int iy, float& h, float& v) {
-  const Layers& src = it.Lsrc;
-  const Layers& dst = it.L;
-  const int64_t o = (int64_t)iy * it.c.nx + ix;
-  const int64_t s = move_source(it, ix, iy);
-  if (s >= 0) {
-    h = src.h[s];
-    v = src.v[s];
-    dst.h[o] = h;
-    dst.v[o] = v;
-    dst.t[o] = src.t[s];
-    dst.nx[o] = src.nx[s];
-    dst.ny[o] = src.ny[s];
-    dst.nz[o] = src.nz[s];
-    dst.trav[o] = src.trav[s];
-    dst.valid[o] = src.valid[s];
-    if (dst.ub) dst.ub[o] = src.ub[s];
-  } else {
-    const float qnan = __builtin_nanf("");
-    h = it.c.h_init;
-    v = it.c.v_init;
-    dst.h[o] = h;
-    dst.v[o] = v;
-    dst.t[o] = 0;
-    dst.nx[o] = qnan;
-    dst.ny[o] = qnan;
-    dst.nz[o] = qnan;
-    dst.trav[o] = qnan;
-    dst.valid[o] = 0;
-    if (dst.ub) dst.ub[o] = INFINITY;
-  }
-  dst.mark[o] = 0;
+// Physical cell o back to the prior: no estimate, no normal or
+// traversability, no bound; the mark is cleared.
+__device__ __forceinline__ void prior_cell(const Consts& c, const Layers& L, int64_t o) {
+  const float qnan = __builtin_nanf("");
+  L.h[o] = c.h_init;
+  L.v[o] = c.v_init;
+  L.t[o] = 0;
+  L.nx[o] = qnan;
+  L.ny[o] = qnan;
+  L.nz[o] = qnan;
+  L.trav[o] = qnan;
+  L.valid[o] = 0;
+  L.mark[o] = 0;
+  if (L.ub) L.ub[o] = INFINITY;
 }
 
 // ---------------------------------------------------------------- block scans

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kNTd) void k_drift_partial(DriftArgs a) {
       const PointEval e = eval_point(it.P, it.c, it.x[i], it.y[i], it.z[i]);
       int ix, iy;
       use[j] = e.valid && bin_xy(e.xm, e.ym, it.c, ix, iy);
-      if (use[j]) cell[j] = (int64_t)iy * it.c.nx + ix;
+      if (use[j]) cell[j] = pcell(it.c, ix, iy);  // physical: the layers
       zm[j] = e.zm;
     }
   }

@@ -121,6 +121,14 @@ __device__ __forceinline__ void lds_unite(int* par, int a, int b) {
   }
 }
 
+// Physical cell of logical cell i (the map's ring layout).  The union-find
+// works on logical cells; only the map's layers are read through the ring.
+__device__ __forceinline__ int64_t lphys(const Consts& c, int64_t i) {
+  const int iy = (int)(i / c.nx);
+  const int ix = (int)(i - (int64_t)iy * c.nx);
+  return pcell(c, ix, iy);
+}
+
 __global__ __launch_bounds__(kNTl) void k_inp_local(InpaintArgs a) {
   __shared__ int s_par[kNTl];
   __shared__ uint32_t s_best[kNTl];
@@ -135,7 +143,7 @@ __global__ __launch_bounds__(kNTl) void k_inp_local(InpaintArgs a) {
   const int gy = y0 + ly;
   const bool in = gx < nx && gy < ny;
   const int64_t i = (int64_t)gy * nx + gx;
-  const bool ok = in && a.L.valid[i];
+  const bool ok = in && a.L.valid[lphys(a.c, i)];
   const bool hole = in && !ok;
   // Rows first, without atomics: a hole's parent is the first cell of its
   // run of holes along the row (a tile row is half a wave: one ballot).
@@ -155,7 +163,7 @@ __global__ __launch_bounds__(kNTl) void k_inp_local(InpaintArgs a) {
   // region takes one LDS atomic per wave
   {
     volatile int* vp = s_par;
-    const uint32_t k = ok ? f32_key(a.L.h[i]) : kNoKey;
+    const uint32_t k = ok ? f32_key(a.L.h[lphys(a.c, i)]) : kNoKey;
     const int nb[4] = {lx > 0 ? tid - 1 : -1, lx + 1 < kIT && gx + 1 < nx ? tid + 1 : -1,
                        ly > 0 ? tid - kIT : -1, ly + 1 < kIT && gy + 1 < ny ? tid + kIT : -1};
 #pragma unroll
@@ -190,13 +198,13 @@ __global__ __launch_bounds__(kNTi) void k_inp_merge(InpaintArgs a) {
   const int ix = (int)(i - (int64_t)iy * nx);
   const bool right = (ix % kIT) == kIT - 1 && ix + 1 < nx;
   const bool down = (iy % kIT) == kIT - 1 && iy + 1 < a.c.ny;
-  if (!(right || down) || a.L.valid[i]) return;
+  if (!(right || down) || a.L.valid[lphys(a.c, i)]) return;
   // Along an edge, hole pairs next to each other are already joined on both
   // sides: only the first pair of each run of pairs unites.
-  if (right && !a.L.valid[i + 1] &&
-      (iy % kIT == 0 || a.L.valid[i - nx] || a.L.valid[i - nx + 1]))
+  if (right && !a.L.valid[lphys(a.c, i + 1)] &&
+      (iy % kIT == 0 || a.L.valid[lphys(a.c, i - nx)] || a.L.valid[lphys(a.c, i - nx + 1)]))
     unite(a.parent, (int32_t)i, (int32_t)(i + 1));
-  if (down && !a.L.valid[i + nx] && (ix % kIT == 0 || a.L.valid[i - 1] || a.L.valid[i + nx - 1]))
+  if (down && !a.L.valid[lphys(a.c, i + nx)] && (ix % kIT == 0 || a.L.valid[lphys(a.c, i - 1)] || a.L.valid[lphys(a.c, i + nx - 1)]))
     unite(a.parent, (int32_t)i, (int32_t)(i + nx));
 }
 
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(kNTi) void k_inp_border(InpaintArgs a) {
   if (i >= (int64_t)nx * ny) return;
   const int iy = (int)(i / nx);
   const int ix = (int)(i - (int64_t)iy * nx);
-  if (!a.L.valid[i]) {
+  if (!a.L.valid[lphys(a.c, i)]) {
     // a local root hands its tile's minimum to the final root
     const uint32_t k = a.best[i];
     if (k == kNoKey) return;
@@ -219,20 +227,20 @@ __global__ __launch_bounds__(kNTi) void k_inp_border(InpaintArgs a) {
   const int tx = ix % kIT;
   const int ty = iy % kIT;
   if (tx != 0 && tx != kIT - 1 && ty != 0 && ty != kIT - 1) return;
-  const uint32_t k = f32_key(a.L.h[i]);
-  if (tx == 0 && ix > 0 && !a.L.valid[i - 1]) atomicMin(a.best + find_root(a.parent, (int32_t)(i - 1)), k);
-  if (tx == kIT - 1 && ix + 1 < nx && !a.L.valid[i + 1])
+  const uint32_t k = f32_key(a.L.h[lphys(a.c, i)]);
+  if (tx == 0 && ix > 0 && !a.L.valid[lphys(a.c, i - 1)]) atomicMin(a.best + find_root(a.parent, (int32_t)(i - 1)), k);
+  if (tx == kIT - 1 && ix + 1 < nx && !a.L.valid[lphys(a.c, i + 1)])
     atomicMin(a.best + find_root(a.parent, (int32_t)(i + 1)), k);
-  if (ty == 0 && iy > 0 && !a.L.valid[i - nx])
+  if (ty == 0 && iy > 0 && !a.L.valid[lphys(a.c, i - nx)])
     atomicMin(a.best + find_root(a.parent, (int32_t)(i - nx)), k);
-  if (ty == kIT - 1 && iy + 1 < ny && !a.L.valid[i + nx])
+  if (ty == kIT - 1 && iy + 1 < ny && !a.L.valid[lphys(a.c, i + nx)])
     atomicMin(a.best + find_root(a.parent, (int32_t)(i + nx)), k);
 }
 
 __global__ __launch_bounds__(kNTi) void k_inp_fill(InpaintArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kNTi + threadIdx.x;
   if (i >= (int64_t)a.c.nx * a.c.ny) return;
-  a.out[i] = a.L.valid[i] ? a.L.h[i] : key_f32(a.best[find_root(a.parent, (int32_t)i)]);
+  a.out[i] = a.L.valid[lphys(a.c, i)] ? a.L.h[lphys(a.c, i)] : key_f32(a.best[find_root(a.parent, (int32_t)i)]);
 }
 
 // -------------------------------------------------------------- smoothing

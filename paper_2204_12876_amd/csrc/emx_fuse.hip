@@ -329,23 +329,25 @@ __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
       const PointEval e = eval_point(it.P, it.c, it.x[i], it.y[i], it.z[i]);
       int cell = -1;
       int ix = 0, iy = 0;
+      int64_t pc = 0;
       if (e.valid && bin_xy(e.xm, e.ym, it.c, ix, iy)) {
         cell = iy * it.c.nx + ix;
+        pc = pcell(it.c, ix, iy);
         // points of the exclusion area are ignored
         if (!it.c.excl_on || !excluded_point(it.P, it.c, e)) {
-          const float h0 = it.L.h[cell];
-          const float v0 = it.L.v[cell];
+          const float h0 = it.L.h[pc];
+          const float v0 = it.L.v[pc];
           const float d = e.zm - h0;
           const bool inside = (d * d) <= (it.c.k2 * (v0 + e.sp2));
           // wall/edge rule: in a crowded cell that holds an estimate, points
           // below the estimate are ignored (before the gate)
           const bool walled = it.fs.count && e.zm < h0 &&
-                              it.fs.count[cell] > (uint32_t)it.c.wall && it.L.valid[cell];
+                              it.fs.count[pc] > (uint32_t)it.c.wall && it.L.valid[pc];
           acc[j] = inside && !walled;
           // a gate-rejected point in a cell with an estimate flags the cell
           // for the outlier variance (a plain store: every writer stores 2)
-          if (it.c.var_o != 0.0f && !inside && !walled && it.L.valid[cell])
-            it.L.mark[cell] = kMarkOutlier;
+          if (it.c.var_o != 0.0f && !inside && !walled && it.L.valid[pc])
+            it.L.mark[pc] = kMarkOutlier;
         }
       }
       if (it.out_cell) it.out_cell[i] = cell;
@@ -353,9 +355,12 @@ __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk) {
       if (acc[j]) {
         w[j] = 1.0f / e.sp2;
         wz[j] = w[j] * e.zm;
-        const uint32_t tile = (uint32_t)((iy >> kTileLogY) * it.tiles_x + (ix >> kTileLogX));
+        // tiles cover the physical layout, so pass 2 writes whole rows
+        const int py = (int)(pc / it.c.nx);
+        const int px = (int)(pc - (int64_t)py * it.c.nx);
+        const uint32_t tile = (uint32_t)((py >> kTileLogY) * it.tiles_x + (px >> kTileLogX));
         const uint32_t local =
-            (uint32_t)(((iy & (kTileH - 1)) << kTileLogX) | (ix & (kTileW - 1)));
+            (uint32_t)(((py & (kTileH - 1)) << kTileLogX) | (px & (kTileW - 1)));
         seg[j] = (tile << kSegBits) | local;
       }
     }
@@ -476,6 +481,7 @@ __device__ __forceinline__ void tile_body(const Item& it, int t) {
   bool hit = false;
   const int tx = t % it.tiles_x;
   const int ty = t / it.tiles_x;
+  // the owned cell, physical (tiles cover the ring layout as stored)
   const int ix = (tx << kTileLogX) + (l & (kTileW - 1));
   const int iy = (ty << kTileLogY) + (l >> kTileLogX);
   const int64_t cell = (int64_t)iy * it.c.nx + ix;
@@ -640,7 +646,7 @@ __device__ __forceinline__ void count_body(const Item& it, int64_t chunk) {
     int ix, iy;
     if (!e.valid || !bin_xy(e.xm, e.ym, it.c, ix, iy)) continue;
     if (it.c.excl_on && excluded_point(it.P, it.c, e)) continue;
-    const uint32_t key = (uint32_t)iy * (uint32_t)it.c.nx + (uint32_t)ix + 1u;
+    const uint32_t key = (uint32_t)pcell(it.c, ix, iy) + 1u;
     uint32_t h = (key * 2654435761u) >> (32 - kCountSlotsLog);
     while (true) {
       const uint32_t prev = atomicCAS(s_key + h, 0u, key);

@@ -8,7 +8,7 @@
 
 namespace emx {
 
-// Per-map control words after the two buffer sets: two sets of clearing
+// Per-map control words after the layers: two sets of clearing
 // queue counters, used by alternate plain calls (each call's setup zeroes the
 // other set for the next call), then the fusion's per-tile entry counts (one
 // word per tile, zero between calls).
@@ -40,9 +40,7 @@ struct emx_map {
   int64_t cgx, cgy;
   int64_t t0;
   char* state;
-  size_t set_bytes;
-  int cur;
-  emx::Layers sets[2];
+  emx::Layers L;  // the layers, in the ring layout with origin (c.ox, c.oy)
   uint32_t* ctl;
   int ctr_sel;  // the counter set the next clear_visibility uses
   int march_grid;
@@ -61,5 +59,9 @@ emx_status make_item(const emx_map* m, const emx_frame* f, Item* it);
 // false if the centre is out of range.
 bool plan_move(const emx_map* m, double cx, double cy, int64_t* ngx, int64_t* ngy, int* sx,
                int* sy);
+
+// The ring origin after a move by (sx, sy): logical cell (0, 0) of the moved
+// map is logical cell (sx, sy) of the map before the move.
+void turn_ring(const Consts& c, int sx, int sy, int* ox, int* oy);
 
 }  // namespace emx

@@ -59,7 +59,8 @@ hipError_t launch_clear_batch(const Batch* d_batch, int grid_setup, int grid_mar
                               hipStream_t stream);
 
 // --------------------------------------------------------------- per cell
-int64_t move_units(int nx, int ny);
+// Threads' worth of work of the move: the cells that enter the map.
+int64_t move_units(const Item& it);
 int64_t cells_units(int nx, int ny);
 // Fills L with the prior and zeroes ctl[0..nctl).
 hipError_t launch_fill_prior(const Consts& c, const Layers& L, uint32_t* ctl, int nctl,

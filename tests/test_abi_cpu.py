@@ -26,7 +26,7 @@ def test_version_and_sizes(L):
     assert _emx.params_check(p) == 0
     C = 400 * 400
     sb = _emx.state_bytes(p)
-    assert sb >= 2 * 30 * C and sb % 256 == 0
+    assert sb >= 30 * C and sb % 256 == 0
     assert _emx.export_bytes(p) == 29 * C
     assert _emx.scratch_bytes(p, 0) == 0
     s1 = _emx.scratch_bytes(p, 300000)
@@ -64,7 +64,8 @@ def test_init_map_argument_checks_need_no_gpu(L):
 
 @pytest.mark.parametrize("field,value", [
     ("time_variance", -1e-3), ("time_variance", float("nan")), ("wall_min_count", -1),
-    ("upper_bound", 2), ("upper_bound", -1),
+    ("upper_bound", 2), ("upper_bound", -1), ("excl_on", 2), ("excl_on", -1),
+    ("outlier_variance", -0.1), ("outlier_variance", float("inf")),
 ])
 def test_bad_extension_params_rejected(L, field, value):
     d = dict(nx=64, ny=64, resolution=0.04)
@@ -74,12 +75,22 @@ def test_bad_extension_params_rejected(L, field, value):
     assert _emx.state_bytes(p) == 0 and _emx.inpaint_scratch_bytes(p) == 0
 
 
+@pytest.mark.parametrize("extra", [dict(excl_theta=-0.1), dict(excl_theta=1.6),
+                                   dict(excl_b=float("nan")), dict(excl_d=float("inf"))])
+def test_bad_exclusion_area_rejected(L, extra):
+    p = _emx.make_params(dict(nx=64, ny=64, resolution=0.04, excl_on=1, **extra))
+    assert _emx.params_check(p) == _emx.EMX_EINVAL
+    # with the area off its parameters are not looked at
+    q = _emx.make_params(dict(nx=64, ny=64, resolution=0.04, excl_on=0, **extra))
+    assert _emx.params_check(q) == _emx.EMX_OK
+
+
 def test_extension_sizes(L):
     C = 64 * 48
     base = _emx.make_params(dict(nx=64, ny=48, resolution=0.04))
     ub = _emx.make_params(dict(nx=64, ny=48, resolution=0.04, upper_bound=1))
-    # the bound layer: one float per cell in each of the two buffer sets
-    assert _emx.state_bytes(ub) - _emx.state_bytes(base) >= 2 * 4 * C
+    # the bound layer: one float per cell
+    assert _emx.state_bytes(ub) - _emx.state_bytes(base) >= 4 * C
     wall = _emx.make_params(dict(nx=64, ny=48, resolution=0.04, wall_min_count=3))
     # fusion's part grows by the per-cell counts (the buffer is the larger of
     # fusion's and clearing's needs)

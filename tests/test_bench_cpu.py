@@ -59,10 +59,20 @@ def test_cpu_baseline_runs_on_a_stub_workload():
     args = bench.parse(["--steps", "20", "--warmup", "5", "--cpu-seconds", "0.3",
                         "--cpu-procs", "2"])
     pool, procs = bench.cpu_pool(args)
+    ctx = _stub_ctx()
+    # two small maps stand in for a multi-map workload (one map per process)
+    bench.HOST_SPECS.clear()
+    bench.HOST_SPECS["batched"] = [
+        (it["params"], c, *(a.numpy() for a in xyz), pose)
+        for it, (xyz, pose, c) in zip(ctx["items"][:2], ctx["host"][:2])]
     try:
-        out = bench.cpu_baseline(args, _stub_ctx(), pool, procs)
+        out = bench.cpu_baseline(args, ctx, pool, procs)
     finally:
         pool.shutdown()
+        bench.HOST_SPECS.clear()
+    b = out["per_workload"]["batched"]
+    assert b["maps"] == 2 and b["cores"] == 2 and b["points_per_s"] > 0
+    assert b["points"] == 2 * 1500
     assert out["kind"] == "oracle" and out["unit"] == "points/s"
     assert out["cores"] == 2 and out["value"] > 0
     assert out["single_core"]["cores"] == 1 and out["single_core"]["value"] > 0
@@ -110,6 +120,6 @@ def test_roofline_takes_the_kernel_with_the_most_time():
     assert math.isclose(r["achieved"], 6e9 / 3e-3 / 1e9)
     assert math.isclose(r["frac"], r["achieved"] / 8000.0)
     assert math.isclose(r["alg_bytes_per_launch"], 6e9 / 5)
-    fb = bench.frame_bytes(100, 50, 7, 5, 1.0)
+    fb = bench.frame_bytes(100, 50, 7, 5, 10)
     assert fb["fuse_chunk"] == 1200 + 56 and fb["fuse_tile"] == 105
-    assert fb["move"] == 58 * 50 and bench.frame_bytes(100, 50, 7, 5, 0.0)["move"] == 0
+    assert fb["move"] == 29 * 10 and bench.frame_bytes(100, 50, 7, 5, 0)["move"] == 0

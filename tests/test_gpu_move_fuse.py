@@ -95,3 +95,48 @@ def test_move_fuse_refuses_like_the_two_calls(dev):
     assert m.info() == (0, 0, 0)
     assert torch.equal(before, m.export_state())
     m.close()
+
+
+def test_ring_layout_after_moves(dev):
+    """The layers are a ring: a move turns the origin by the shift and resets
+    only the entering strips.  The stored layer unrolled from the origin is the
+    exported (local order) layer, and the state equals the oracle's copy-based
+    move after every shift, including shifts past a whole side."""
+    from paper_2204_12876_amd import ElevationMap, _emx
+    _say("ring layout")
+    params = dict(nx=37, ny=23, resolution=0.1, upper_bound=1)
+    p = O.Params.from_dict(params)
+    rng = np.random.default_rng(17)
+    st = random_state(p, rng, valid_frac=0.6)
+    m = ElevationMap(params, 0.0, 0.0, 0, device=dev)
+    load_state(m, st)
+    r = p.resolution
+    ox = oy = 0
+    cx = cy = 0.0
+    for dx, dy in [(3, 0), (0, -2), (-5, 4), (36, 1), (-40, -30), (1, 1), (0, 0)]:
+        cx += dx * r
+        cy += dy * r
+        m.move_map(cx + 0.5 * r, cy + 0.5 * r)
+        st = O.move_map(p, st, cx + 0.5 * r, cy + 0.5 * r)
+        torch.cuda.synchronize()
+        g = m.state_numpy()
+        for k in ("h", "v", "t_upd", "valid", "trav"):
+            assert np.array_equal(g[k].view(np.uint8), getattr(st, k).view(np.uint8)), (dx, dy, k)
+        assert np.array_equal(g["nrm"].view(np.uint8), st.nrm.view(np.uint8)), (dx, dy)
+        # the origin turns by the shift, modulo the sides
+        ox, oy = (ox + dx) % p.nx, (oy + dy) % p.ny
+        assert m.origin() == (ox, oy), (dx, dy)
+        for lid, key in ((_emx.LAYER_HEIGHT, "h"), (_emx.LAYER_VARIANCE, "v"),
+                         (_emx.LAYER_VALID, "valid")):
+            assert np.array_equal(m.local(lid).cpu().numpy(), g[key]), (dx, dy, key)
+        # the extra layer carries through the ring too
+        assert np.array_equal(np.isinf(m.upper_bound().cpu().numpy()),
+                              np.ones((p.ny, p.nx), bool)), (dx, dy)
+    # import writes through the ring: a state loaded at a non-zero origin
+    # exports unchanged
+    st2 = random_state(p, rng, valid_frac=0.5)
+    load_state(m, st2)
+    g = m.state_numpy()
+    for k in ("h", "v", "t_upd", "valid"):
+        assert np.array_equal(g[k], getattr(st2, k)), k
+    m.close()
