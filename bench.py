@@ -89,6 +89,11 @@ def parse(argv=None):
     ap.add_argument("--cpu-procs", type=int, default=0, help="0: min(16, host cores)")
     for leg in ("pcie", "sweep", "single", "features", "batched", "stress"):
         ap.add_argument(f"--skip-{leg}", action="store_true")
+    ap.add_argument("--skip-stress-batch", action="store_true",
+                    help="time the 2000x2000 map's plain calls only")
+    ap.add_argument("--skip-serving", action="store_true",
+                    help="profiling runs of one leg: no headline (value is null), no CPU "
+                         "baseline, no PCIe or sweep legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default=None, help="batch tuning JSON (default: the tuned file)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -914,6 +919,8 @@ def stress(args, dev, tuning, single_ctx):
                      "points_per_s": pts / wall,
                      "kernels": {k: {"launches": c, "avg_us": tot / c * 1e3}
                                  for k, (c, tot) in kt.items()}}}
+    if args.skip_stress_batch:
+        return out
     # batched with 8 smaller maps
     specs = [(params, centers[0], frames[0][:4])]
     sf, sc, sp = single_ctx["frames"], single_ctx["centers"], single_ctx["params"]
@@ -1123,6 +1130,8 @@ def main(argv=None):
               "of this workload fits one MI355X.", file=sys.stderr)
         sys.exit(2)
     pool = procs = None
+    if args.skip_serving:
+        args.no_cpu_baseline = args.skip_pcie = args.skip_sweep = True
     if not args.no_cpu_baseline and not args.autotune:
         pool, procs = cpu_pool(args)        # the workers start before the GPU is touched
     import torch
@@ -1139,8 +1148,11 @@ def main(argv=None):
         torch.cuda.synchronize()
         say("calibration copy: 268435456 bytes read, 268435456 bytes written")
         del src, dst
-    ctx = serving_context(args, dev)
-    head = serving_headline(args, dev, ctx)
+    if args.skip_serving:
+        ctx, head = None, {"value": None, "ms_per_step": None}
+    else:
+        ctx = serving_context(args, dev)
+        head = serving_headline(args, dev, ctx)
     out = {
         "metric": METRIC,
         "value": head.pop("value"),
@@ -1154,11 +1166,11 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"serving: {len(ctx['items'])} robots, maps U{{256..800}}^2 at "
+        "config": {"workload": f"serving: {args.robots} robots, maps U{{256..800}}^2 at "
                                "0.04 m, frames logU[50k, 500k] points (dome LiDAR + 4 depth "
                                "frustums) resident in device memory, full path per frame, "
                                "continuous-batching server under a 32 GiB device budget",
-                   "robots": len(ctx["items"]), "frames_per_step": len(ctx["items"]),
+                   "robots": args.robots, "frames_per_step": args.robots,
                    "lanes": args.lanes,
                    "mode": "closed-loop clients: each robot submits its next frame when the "
                            "previous one completes"},
@@ -1170,7 +1182,8 @@ def main(argv=None):
     if not args.skip_sweep:
         out["sweep"] = serving_sweep(args, dev, ctx)
     single_ctx = None
-    if not args.skip_single or not args.skip_features or not args.skip_stress:
+    if not args.skip_single or not args.skip_features or \
+            not (args.skip_stress or args.skip_stress_batch):
         single, single_ctx = single_robot(args, dev)
         if not args.skip_single:
             out["single_robot"] = single

@@ -75,7 +75,7 @@ typedef struct {
   int32_t nx, ny;            /* cells; 3..16384 each                                 */
   double resolution;         /* r, metres per cell, 1e-6..1e6                        */
   float init_height;         /* prior height h_init of a fresh or removed cell       */
-  float init_variance;       /* prior variance, "a large number" (Sec. II-C), > 0    */
+  float init_variance;       /* prior variance, large (Sec. II-C), > 0               */
   float noise_alpha;         /* alpha_d in sigma_p^2 = alpha_d * d^2 (Sec. II-C), > 0 */
   float gate_k;              /* Mahalanobis gate k, in sigmas (Sec. II-C), >= 0       */
   float min_range;           /* points with d < min_range are dropped, > 0           */
@@ -135,15 +135,18 @@ const char* emx_last_error(void);
 emx_status emx_params_check(const emx_params* params);
 
 /* Device bytes of one map's state: one set of layers stored as a ring (see
- * emx_layer; with upper_bound = 1 it also holds the upper bound layer), 8
- * bytes of clearing scratch per cell and a small control block (the clearing
- * queue counters and one word per 32x16-cell fusion tile).  Returns 0 for
- * invalid parameters. */
+ * emx_layer; with upper_bound = 1 it also holds the upper bound layer), the
+ * fusion's fixed-point sums (32 bytes per cell, zero between calls), 8 bytes
+ * of clearing scratch per cell and a small control block (the clearing queue
+ * counters and one word per 32x16-cell fusion tile).  Returns 0 for invalid
+ * parameters. */
 size_t emx_state_bytes(const emx_params* params);
 
 /* Device scratch bytes emx_fuse_points and emx_clear_visibility need for
  * frames of up to max_points points (one buffer serves both calls, which use
- * it in turn).  Returns 0 for invalid parameters or max_points < 0. */
+ * it in turn; the fusion's part is the wall rule's per-cell counts, 4 bytes
+ * per cell with wall_min_count > 0, else none).  Returns 0 for invalid
+ * parameters or max_points < 0. */
 size_t emx_scratch_bytes(const emx_params* params, int64_t max_points);
 
 /* Bytes of the packed export format: the layers in identifier order, each
@@ -153,7 +156,7 @@ size_t emx_export_bytes(const emx_params* params);
 
 /* Create a map centred on world (cx, cy).  Every cell starts at the prior:
  * h_init, init_variance, t_upd 0, invalid, NaN normals and traversability
- * (Sec. II-C: the variance is "initialized to a large number").
+ * (Sec. II-C starts the variance at a large value).
  *   d_state:      caller-owned device buffer of state_bytes >= emx_state_bytes(),
  *                 256-byte aligned; retained by the handle until emx_free_map.
  *   t0_ms:        the time origin of the int32 time layer.
@@ -216,13 +219,20 @@ emx_status emx_move_map(emx_map* map, double cx, double cy, void* stream);
  *   W = 1/v0 + sum_A 1/sp2;  v = 1/W;  h = (h0/v0 + sum_A zm/sp2) * v
  *   valid = 1, t_upd = t_ms - t0.
  *   This equals Eq. 1 and 2 applied point by point, in exact arithmetic.
- *   The float32 sums are formed in a fixed order of the points.  That order
- *   depends only on the frame and the map's placement (chunks of 1024 points
- *   in index order: within a chunk, a segmented scan over its accepted points
- *   in order sums each run of consecutive points in one cell, and a second
- *   one over the runs sorted by cell sums each cell's runs; then chunk
- *   partials in chunk order), so results are identical from run to run and
- *   across batching.
+ *   The sums are formed exactly, in fixed point.  A point's float32 terms
+ *     w = 1/sp2;  u = w * rz,  rz = (R20*xs + R21*ys) + R22*zs  (zm = rz + tz)
+ *   are rounded to integers at the scales 2^Sw and 2^Su (ties to even; a w
+ *   that rounds to zero counts as one unit) and summed as integers.  The
+ *   shifts are chosen per call so that no sum can overflow:
+ *     Sw = 93 - ceil(log2 n) - Ew,  2^(Ew-1) <= wmax < 2^Ew,
+ *     wmax = (1 + 2^-10) * float32(1 / float32(alpha * float32(min_range^2))),
+ *   and Su likewise with umax = (1 + 2^-10) * (|R20| + |R21| + |R22|) /
+ *   (alpha * sqrt(float32(min_range^2))), bounds of every accepted w and |u|.
+ *   In float64, sum 1/sp2 = Iw * 2^-Sw and sum zm/sp2 = Iu * 2^-Su +
+ *   tz * sum 1/sp2 (Iw, Iu: the integer sums); each is then rounded to
+ *   float32 for the update above.  The integer sums do not depend on the
+ *   order of the points, so results are identical from run to run and across
+ *   batching.
  * Cells with no accepted point are left bitwise unchanged, except that with
  * time_variance > 0 each valid one gets v = v + float32(time_variance).
  * With outlier_variance > 0, each cell that is valid when the call starts and
@@ -239,10 +249,11 @@ emx_status emx_fuse_points(emx_map* map, const emx_frame* frame, void* d_scratch
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc).
  *   Scratch: a built-in device array of emx_noalloc_scratch_limit() bytes
- *   (64 MiB), one per GPU, held from the first call on that GPU until the
- *   process ends.  A frame whose fusion scratch on this map
- *   (emx_scratch_bytes' fusion part) exceeds it is refused with EMX_ENOMEM and
- *   nothing is enqueued: about 5M points on a 400x400 map.
+ *   (16 MiB), one per GPU, held from the first call on that GPU until the
+ *   process ends.  It holds the fusion's scratch: the wall rule's per-cell
+ *   counts (4 bytes per cell with wall_min_count > 0; without the rule the
+ *   fusion uses none).  A map whose counts exceed it (more than 4,194,304
+ *   cells) is refused with EMX_ENOMEM and nothing is enqueued.
  *   Every call on one GPU shares that GPU's array.  Calls that overlap on one
  *   GPU (on different streams, or from different threads without ordering)
  *   race on it; calls in order on one stream do not.

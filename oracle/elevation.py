@@ -15,7 +15,7 @@ the cell it falls in with a scalar Kalman step:
 Visibility clean-up marches each sensor ray and removes cells the ray passes
 below.  A cell is removed only if all of these hold (Sec. II-E):
   * the ray passes below the cell's height minus its standard deviation (Eq. 3);
-  * the cell has not been updated for a set time;
+  * the cell is older than a set age (no update within it);
   * the cell's normal is well aligned with the ray (Eq. 4).
 Normals (Sec. II-A) and a small convolutional traversability filter
 (Sec. II-G) run over the cells afterwards.
@@ -178,7 +178,7 @@ class MapState:
 
 def init_map(p: Params, cx: float, cy: float, t0_ms: int = 0) -> MapState:
     """Every cell starts at the prior: the height estimate h_init and a large
-    variance (Sec. II-C, "initialized to a large number")."""
+    variance (Sec. II-C starts the variance at a large value)."""
     c = f32_constants(p)
     shp = (p.ny, p.nx)
     return MapState(
@@ -571,9 +571,9 @@ def move_layer(p: Params, st: MapState, layer: np.ndarray, cx: float, cy: float,
 
 
 def apply_clear(p: Params, st: MapState, marks: np.ndarray) -> MapState:
-    """A removed cell goes back to the prior and becomes invalid (Sec. II-E,
-    "the height value is removed").  Normals and traversability are left for
-    the next per-cell pass."""
+    """A removed cell goes back to the prior and becomes invalid (Sec. II-E
+    removes the cell's height).  Normals and traversability are left for the
+    next per-cell pass."""
     c = f32_constants(p)
     new = st.copy()
     new.h = np.where(marks, c["h_init"], st.h).astype(F32)

@@ -107,7 +107,8 @@ Consts make_consts(const emx_params& p) {
 }
 
 // One buffer set: seven 4-byte layers, two byte layers, the clearing block
-// maxima, then the upper bound layer if the map keeps one; each 256-aligned.
+// maxima, the upper bound layer if the map keeps one, then the fusion's four
+// planes of fixed-point sums (8 bytes per cell each); each 256-aligned.
 size_t set_layout(const emx_params& p, char* base, Layers* L) {
   const size_t C = (size_t)p.nx * (size_t)p.ny;
   const size_t l4 = align256(C * 4);
@@ -126,8 +127,10 @@ size_t set_layout(const emx_params& p, char* base, Layers* L) {
     L->mark = (uint8_t*)(base + 7 * l4 + l1);
     L->cmax = (float*)(base + 7 * l4 + 2 * l1);
     L->ub = p.upper_bound ? (float*)(base + 7 * l4 + 2 * l1 + lb) : nullptr;
+    L->fx = (uint64_t*)(base + 7 * l4 + 2 * l1 + lb + (p.upper_bound ? l4 : 0));
+    L->fxs = (int64_t)(align256(C * 8) / 8);
   }
-  return 7 * l4 + 2 * l1 + lb + (p.upper_bound ? l4 : 0);
+  return 7 * l4 + 2 * l1 + lb + (p.upper_bound ? l4 : 0) + kFxWords * align256(C * 8);
 }
 
 size_t clr_bytes(const emx_params& p) { return align256((size_t)p.nx * (size_t)p.ny * 8); }
@@ -200,6 +203,7 @@ emx_status make_item(const emx_map* m, const emx_frame* f, Item* it) {
   it->z = f->z;
   it->n = f->n;
   it->B = (int)((f->n + kChunk - 1) / kChunk);
+  fuse_fixed_shifts(it->c, it->P, f->n, &it->fxw, &it->fxz);
   return EMX_OK;
 }
 
@@ -245,8 +249,7 @@ size_t emx_scratch_bytes(const emx_params* params, int64_t max_points) {
   }
   const int64_t count_cells =
       params->wall_min_count > 0 ? (int64_t)params->nx * params->ny : 0;
-  const size_t f = fuse_scratch_layout(max_points, tiles_of(*params), count_cells, nullptr,
-                                       nullptr);
+  const size_t f = fuse_scratch_layout(count_cells, nullptr, nullptr);
   const size_t c = clear_scratch_layout(max_points, kDefaultSeg, nullptr, nullptr);
   return f > c ? f : c;
 }
@@ -348,13 +351,13 @@ static emx_status fuse_impl(emx_map* m, const emx_frame* f, bool move, double cx
   const bool run = f->n > 0 || m->p.time_variance != 0.0f;  // time variance: every call
   if (f->n > 0) {
     const int64_t count_cells = m->p.wall_min_count > 0 ? (int64_t)m->p.nx * m->p.ny : 0;
-    const size_t need = fuse_scratch_layout(f->n, it.T, count_cells, nullptr, nullptr);
+    const size_t need = fuse_scratch_layout(count_cells, nullptr, nullptr);
     if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
     if (((uintptr_t)d_scratch & 255u) != 0)
       return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
     if (scratch_bytes < need)
       return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
-    fuse_scratch_layout(f->n, it.T, count_cells, (char*)d_scratch, &it.fs);
+    fuse_scratch_layout(count_cells, (char*)d_scratch, &it.fs);
   }
   it.out_cell = d_out_cell;
   it.out_accept = d_out_accept;
@@ -385,7 +388,7 @@ emx_status emx_fuse_points(emx_map* m, const emx_frame* f, void* d_scratch, size
 // In host code the array's name is only a stand-in for the device address:
 // the address is looked up once per device and kept in g_noalloc_ptr.
 namespace {
-constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+constexpr size_t kNoallocScratchBytes = (size_t)16 << 20;
 constexpr int kNoallocMaxDevices = 64;
 static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 std::mutex g_noalloc_mu;
@@ -422,12 +425,12 @@ emx_status emx_fuse_points_noalloc(emx_map* m, const emx_frame* f, int32_t* d_ou
   if (s != EMX_OK) return s;
   if ((s = check_frame(f)) != EMX_OK) return s;
   const int64_t count_cells = m->p.wall_min_count > 0 ? (int64_t)m->p.nx * m->p.ny : 0;
-  const size_t need = fuse_scratch_layout(f->n, tiles_of(m->p), count_cells, nullptr, nullptr);
+  const size_t need = fuse_scratch_layout(count_cells, nullptr, nullptr);
   if (need > kNoallocScratchBytes)
     return fail(EMX_ENOMEM,
-                "frame of %lld points needs %zu bytes of fusion scratch on this map; the "
-                "built-in scratch holds %zu",
-                (long long)f->n, need, kNoallocScratchBytes);
+                "the wall rule's per-cell counts of this map need %zu bytes of fusion "
+                "scratch; the built-in scratch holds %zu",
+                need, kNoallocScratchBytes);
   void* d_scratch = nullptr;
   if ((s = noalloc_scratch(&d_scratch)) != EMX_OK) return s;
   return fuse_impl(m, f, false, 0.0, 0.0, d_scratch, kNoallocScratchBytes, d_out_cell,

@@ -67,11 +67,10 @@ constexpr int kGrids = 9;
 
 struct GraphKey {
   void* scratch;
-  int key64;
   int grid[kGrids];
 
   bool operator==(const GraphKey& o) const {
-    if (scratch != o.scratch || key64 != o.key64) return false;
+    if (scratch != o.scratch) return false;
     for (int i = 0; i < kGrids; ++i)
       if (grid[i] != o.grid[i]) return false;
     return true;
@@ -140,8 +139,8 @@ size_t batch_layout(const emx_batch_item* items, int32_t n, int seg, char* base,
     if (items[i].stages & EMX_STAGE_FUSE) {
       const emx_params& mp = items[i].map->p;
       const int64_t cc = mp.wall_min_count > 0 ? (int64_t)mp.nx * mp.ny : 0;
-      const size_t f = fuse_scratch_layout(np, tiles_of(mp), cc, nullptr, nullptr);
-      if (tab && base) fuse_scratch_layout(np, tiles_of(mp), cc, base + off, &tab->items[i].fs);
+      const size_t f = fuse_scratch_layout(cc, nullptr, nullptr);
+      if (tab && base) fuse_scratch_layout(cc, base + off, &tab->items[i].fs);
       off = align256(off + f);
     }
     if (tab) {
@@ -265,13 +264,11 @@ size_t emx_batch_scratch_bound(const emx_batch* b, const emx_params* largest, in
   if (!b || check_params(largest) != EMX_OK) return 0;
   if (max_items < 1 || max_items > kMaxItems || max_points < 0 || max_points > 2147483647LL)
     return 0;
-  // Every item's chunk count is at most n_i / kChunk + 1 and its fusion
-  // arrays are each padded by under 256 bytes, plus the item's own padding.
-  const int64_t recs = max_points + (int64_t)max_items * kChunk;
+  // The fusion's scratch is each item's wall-rule counts, padded by under 256
+  // bytes per item.
   const int64_t cc =
       largest->wall_min_count > 0 ? (int64_t)max_items * largest->nx * largest->ny : 0;
-  const size_t fuse = fuse_scratch_layout(recs, tiles_of(*largest), cc, nullptr, nullptr) +
-                      (size_t)max_items * 5 * 256;
+  const size_t fuse = fuse_scratch_layout(cc, nullptr, nullptr) + (size_t)max_items * 256;
   return align256(kCounterOffset + kCounterBytes) + fuse +
          clear_scratch_layout(max_points, b->tune.seg, nullptr, nullptr);
 }
@@ -309,7 +306,6 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
   memset(tab, 0, upload);
   tab->n = n;
   Batch* d_tab = (Batch*)d_scratch;
-  bool key64 = false;
   // plan every item on copies of the map geometry: no map changes until the
   // whole batch has been checked
   int ox[kMaxItems], oy[kMaxItems];
@@ -343,10 +339,8 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
     oy[i] = tmp.c.oy;
     cgx[i] = tmp.cgx;
     cgy[i] = tmp.cgy;
-    if ((bi.stages & EMX_STAGE_FUSE) && it.n > 0 && fuse_needs_key64(it.T)) key64 = true;
   }
   batch_layout(items, n, b->tune.seg, (char*)d_scratch, tab);
-  tab->key64 = key64 ? 1 : 0;
   int64_t clear_rays = 0;
   for (int32_t i = 0; i < n; ++i) {
     Item& it = tab->items[i];
@@ -386,7 +380,6 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
   auto cap_opt = [&](int tuned, int64_t units) { return units < 1 ? 0 : cap(tuned, units); };
   GraphKey key;
   key.scratch = d_scratch;
-  key.key64 = key64 ? 1 : 0;
   key.grid[0] = cap(t.grid_move, tab->off[kBMove][n]);
   key.grid[1] = cap_opt(t.grid_cells, tab->off[kBZero][n]);
   key.grid[2] = cap_opt(t.grid_chunk, tab->off[kBCount][n]);
@@ -404,7 +397,7 @@ emx_status emx_pipeline_batch(emx_batch* b, const emx_batch_item* items, int32_t
   if (e != hipSuccess) return hip_fail(e, "pipeline_batch: table upload");
   auto enqueue = [&](hipStream_t q) -> hipError_t {
     hipError_t r = launch_move_batch(d_tab, key.grid[0], q);
-    if (r == hipSuccess) r = launch_fuse_batch(d_tab, key64, key.grid + 1, q);
+    if (r == hipSuccess) r = launch_fuse_batch(d_tab, key.grid + 1, q);
     if (r == hipSuccess) r = launch_clear_batch(d_tab, key.grid[6], key.grid[7], q);
     if (r == hipSuccess) r = launch_cells_batch(d_tab, key.grid[8], q);
     return r;

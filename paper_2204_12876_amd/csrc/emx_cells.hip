@@ -38,6 +38,7 @@ __global__ __launch_bounds__(kNTf) void k_fill_prior(FillArgs a) {
   a.L.valid[i] = 0;
   a.L.mark[i] = 0;
   if (a.L.ub) a.L.ub[i] = INFINITY;
+  for (int k = 0; k < kFxWords; ++k) a.L.fx[k * a.L.fxs + i] = 0u;
 }
 
 // ------------------------------------------------------------------------ move

@@ -212,9 +212,10 @@ __device__ __forceinline__ bool ray_of(const Item& it, int64_t i, Ray& r, int& K
 constexpr int kUnroll = 8;
 
 // Test samples k in [ka, kb] of ray r against the map; cm holds the block
-// maxima.  kUnroll samples at a time: their cells and block maxima are found
-// without branches, so the block-maximum loads issue together.  The per-sample
-// work is kept to the sample itself.
+// maxima.  kUnroll samples at a time: their cells and blocks are found without
+// branches, then the block maxima are loaded together, one load per change of
+// block along the ray (a ray spends about five samples in a block of 8 x 8
+// cells).  The per-sample work is kept to the sample itself.
 __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka, int kb,
                                             int end_cell, const float* cm) {
   const float an2dd = it.c.an2 * ((r.dx * r.dx + r.dy * r.dy) + r.dz * r.dz);
@@ -222,9 +223,12 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
   const int bx = it.bx;
   const float inv_r = it.c.inv_r;
   const int nx = it.c.nx;
+  uint32_t pblk = 0xFFFFFFFFu;  // the block of the previous sample, and its maximum
+  float pm = 0.0f;
   for (int k = ka; k <= kb; k += kUnroll) {
     int cell[kUnroll];     // logical: the end-cell test, the records
     int64_t pc[kUnroll];   // physical: the layers
+    uint32_t blk[kUnroll];
     float qz[kUnroll];
     float m[kUnroll];
     bool cand[kUnroll];
@@ -243,10 +247,20 @@ __device__ __forceinline__ void march_range(const Item& it, const Ray& r, int ka
       const int iy = (int)(qy * inv_r);
       cell[u] = iy * nx + ix;
       pc[u] = pcell(it.c, ix, iy);
-      // every slot's block maximum is loaded before any is used, so the
-      // loads of the kUnroll samples are in flight together
-      m[u] = cm[(uint32_t)((iy >> bl) * bx + (ix >> bl))];
+      blk[u] = (uint32_t)((iy >> bl) * bx + (ix >> bl));
     }
+    // the block maxima where the block changes, every load issued before any
+    // is used; the other slots take their predecessor's
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      m[u] = 0.0f;
+      if (blk[u] != (u ? blk[u - 1] : pblk)) m[u] = cm[blk[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (blk[u] == (u ? blk[u - 1] : pblk)) m[u] = u ? m[u - 1] : pm;
+    pblk = blk[kUnroll - 1];
+    pm = m[kUnroll - 1];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
       cand[u] = (k + u <= kb) & (qz[u] < m[u]) & (cell[u] != end_cell);

@@ -17,12 +17,11 @@
 
 namespace emx {
 
-// Points per fusion chunk.  This fixes the float32 summation order of the fused
-// sums, so it is a constant of the library, not a tunable.
+// Points per fusion work unit (one workgroup of pass 1, the wall counts and
+// the drift partials).
 constexpr int kChunk = 1024;
-// Map tiles of 32 x 16 cells own the per-cell merge (pass 2 runs one thread
-// per cell of a tile; a 400 x 400 map has 338 tiles, more than the chip's
-// compute units).
+// Map tiles of 32 x 16 cells: pass 2 of the fusion visits only the tiles the
+// frame touched, one thread per cell (a 400 x 400 map has 338 tiles).
 constexpr int kTileLogX = 5;
 constexpr int kTileLogY = 4;
 constexpr int kTileW = 1 << kTileLogX;
@@ -51,7 +50,18 @@ struct Layers {
   float* cmax;    // per logical block: max height over cells a ray may clear (transient)
   float* ub;      // upper bound of the ground height (+inf: none), or null
   float2* clr;    // per logical cell {h, or -inf if a ray may not clear it, v} (transient)
+  uint64_t* fx;   // the fusion's fixed-point sums: kFxWords planes of fxs words, one word
+                  // per physical cell each; all zero between calls
+  int64_t fxs;    // plane stride in words
 };
+
+// Fixed-point sums of a cell, one word in each plane.  A value x enters as the
+// integer X = round(x * 2^S) (S: the item's shift for that sum), split as
+// X = hi * 2^32 + lo with 0 <= lo < 2^32; the hi and lo parts are summed in
+// separate words (hi as two's complement).  Integer addition is associative,
+// so the sums do not depend on the order of the atomics that form them: the
+// fused result is the same in every run, alone or batched.
+enum FxWord { kFxWhi = 0, kFxWlo, kFxZhi, kFxZlo, kFxWords };  // sum 1/sp2; sum rz/sp2
 
 // Clearing prunes samples by square blocks of 8 x 8 cells: one cell per lane
 // of the wave that computes a block's maximum (the setup relies on it).  The maxima are read through
@@ -96,13 +106,8 @@ struct Pose32 {
 };
 
 struct FuseScratch {
-  uint16_t* rec_local;  // [B * kChunk] cell within its tile of each per-chunk partial
-  float* rec_w;         // [B * kChunk] chunk partial of sum 1/sp2
-  float* rec_wz;        // [B * kChunk] chunk partial of sum zm/sp2
-  uint2* ent;           // [T * B] per tile, in no particular order: (chunk, start << 16 |
-                        // count) of the tile's partials in each chunk that touched it
-  uint32_t* tcnt;       // [T] entries per tile; part of the map state, zero between calls
-                        // (pass 2 resets each tile's count after reading it)
+  uint32_t* tcnt;       // [T] nonzero if pass 1 added to a cell of the tile; part of the
+                        // map state, zero between calls (pass 2 resets it)
   uint32_t* count;      // [nx * ny] the frame's valid points per cell (wall rule), or null
 };
 
@@ -149,6 +154,7 @@ struct Item {
   FuseScratch fs;
   ClearQueue cq;
   int64_t ray_base;  // this item's first ray in cq
+  int fxw, fxz;      // fixed-point shifts S of the sums of 1/sp2 and rz/sp2 (FxAcc)
   int tiles_x, T, B;
   int bl, bx, by, nb, nprep;
   int bpw;           // clearing blocks per wave in the setup's block role
@@ -165,7 +171,6 @@ enum BatchStage { kBMove = 0, kBZero, kBCount, kBChunk, kBTile, kBVar, kBSetup, 
 // Only the header and the first n items are uploaded for a batch of n.
 struct Batch {
   int n;
-  int key64;  // pass 1 sorts 64-bit keys for this batch
   int64_t off[kBNum][kMaxItems + 1];
   int64_t rays[kMaxItems + 1];  // prefix of the items' clearing rays (ray_base)
   Item items[kMaxItems];
@@ -173,6 +178,7 @@ struct Batch {
 
 struct PointEval {
   float xm, ym, zm, d2, sp2;
+  float rz;  // the rotated point's height (zm before the translation is added)
   bool valid;
 };
 
@@ -182,7 +188,8 @@ __device__ __forceinline__ PointEval eval_point(const Pose32& P, const Consts& c
   PointEval e;
   e.xm = ((P.R[0] * xs + P.R[1] * ys) + P.R[2] * zs) + P.t[0];
   e.ym = ((P.R[3] * xs + P.R[4] * ys) + P.R[5] * zs) + P.t[1];
-  e.zm = ((P.R[6] * xs + P.R[7] * ys) + P.R[8] * zs) + P.t[2];
+  e.rz = (P.R[6] * xs + P.R[7] * ys) + P.R[8] * zs;
+  e.zm = e.rz + P.t[2];
   e.d2 = (xs * xs + ys * ys) + zs * zs;
   e.sp2 = c.alpha * e.d2;
   e.valid = isfinite(xs) && isfinite(ys) && isfinite(zs) && isfinite(e.d2) &&

@@ -30,18 +30,18 @@ class TimedLaunch {
 // ------------------------------------------------------------------ fusion
 int tiles_x_of(int nx);
 int tiles_y_of(int ny);
-bool fuse_needs_key64(int T);
-// count_cells: cells of the per-cell point counts of the wall/edge rule (0: none).
-size_t fuse_scratch_layout(int64_t max_points, int T, int64_t count_cells, char* base,
-                           FuseScratch* out);
+// The fixed-point shifts of a frame of n points (Item::fxw, Item::fxz).
+void fuse_fixed_shifts(const Consts& c, const Pose32& P, int64_t n, int* fxw, int* fxz);
+// count_cells: cells of the per-cell point counts of the wall/edge rule (0:
+// none); the fusion's only scratch.  Sets out->count.
+size_t fuse_scratch_layout(int64_t count_cells, char* base, FuseScratch* out);
 // Runs the time variance pass even when it.n == 0.
 hipError_t launch_fuse(const Item& it, hipStream_t stream);
 // Work units of the batched count zeroing and per-cell variance stages.
 int64_t zero_units(int64_t cells);
 int64_t var_units(int64_t cells);
 // grid: zero, count, chunk, tile, variance; a zero grid skips its stage.
-hipError_t launch_fuse_batch(const Batch* d_batch, bool key64, const int grid[5],
-                             hipStream_t stream);
+hipError_t launch_fuse_batch(const Batch* d_batch, const int grid[5], hipStream_t stream);
 
 // ---------------------------------------------------------------- clearing
 int64_t clear_queue_cap(int64_t max_points, int seg);

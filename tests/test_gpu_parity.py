@@ -375,9 +375,13 @@ def test_abi_rejects_bad_arguments(dev):
     f = _emx.make_frame(x.data_ptr(), x.data_ptr(), x.data_ptr(), 10, _pose((0, 0, 1)), 0)
     from paper_2204_12876_amd import aligned_empty
     small = aligned_empty(256, dev)
-    with pytest.raises(EmxError) as e:
-        _emx.fuse_points(m.handle, f, small.data_ptr(), 16, 0, 0, 0)
-    assert e.value.status == _emx.EMX_ENOMEM
+    # the fusion's only scratch is the wall rule's per-cell counts: none here
+    _emx.fuse_points(m.handle, f, small.data_ptr(), 16, 0, 0, 0)
     with pytest.raises(EmxError):
         _emx.layer(m.handle, 99)
     m.close()
+    mw = _map(dict(params, wall_min_count=2), dev)           # 4 bytes per cell
+    with pytest.raises(EmxError) as e:
+        _emx.fuse_points(mw.handle, f, small.data_ptr(), 16 * 16 * 4 - 1, 0, 0, 0)
+    assert e.value.status == _emx.EMX_ENOMEM
+    mw.close()

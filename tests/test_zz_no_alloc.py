@@ -1,8 +1,8 @@
 """emx_fuse_points_noalloc (the fusion on the library's built-in scratch)
 against emx_fuse_points (the same kernels on a caller's scratch): the same
 state layers and per-point outputs, bit for bit, over two calls in a row, the
-second with a smaller frame; and the refusal of a frame too large for the
-built-in scratch, with nothing enqueued."""
+second with a smaller frame; and the refusal of a map whose wall-rule counts
+do not fit the built-in scratch, with nothing enqueued."""
 import os
 import sys
 
@@ -75,24 +75,35 @@ def test_noalloc_equals_scratch_call(dev, extra):
     b.close()
 
 
-def test_noalloc_refuses_oversized_frame(dev):
+def test_noalloc_limit_is_the_wall_counts(dev):
+    """The fusion's only scratch is the wall rule's per-cell counts (4 bytes a
+    cell): the largest map they fit in the built-in scratch is served, one row
+    more is refused with nothing enqueued, and without the rule any size is."""
     from paper_2204_12876_amd import ElevationMap, _emx
-    d = synth.cfg0(n_frames=1)
-    m = ElevationMap(d["params"], 0.0, 0.0, 0, device=dev)
     limit = _emx.noalloc_scratch_limit()
-    assert limit == 64 << 20
-    # fusion scratch takes at least 10 bytes per point (a partial's cell,
-    # weight and weighted height), so 8M points need more than 64 MiB
-    n = 8 << 20
-    _say("noalloc refusal, points", n)
-    x = torch.zeros(n, dtype=torch.float32, device=dev)
-    before = _state(m)
-    with pytest.raises(_emx.EmxError) as ei:
-        m.fuse_points_noalloc(x, x, x, d["frames"][0].pose, 0)
-    assert ei.value.status == _emx.EMX_ENOMEM
-    assert "built-in scratch" in str(ei.value)
-    torch.cuda.synchronize()
-    after = _state(m)
-    for key in before:
-        assert np.array_equal(before[key], after[key]), key
-    m.close()
+    assert limit == 16 << 20
+    d = synth.cfg0(n_frames=1)
+    f = d["frames"][0]
+    side = 2048                                   # 2048 * 2048 * 4 bytes = 16 MiB
+    assert side * side * 4 == limit
+    for ny, wall, ok in ((side, 4, True), (side + 1, 4, False), (side + 1, 0, True)):
+        params = dict(d["params"], nx=side, ny=ny, wall_min_count=wall)
+        _say("noalloc limit, map", side, "x", ny, "wall", wall)
+        m = ElevationMap(params, 0.0, 0.0, 0, device=dev)
+        xyz = tuple(t.to(dev).contiguous() for t in (f.x, f.y, f.z))
+        before = _state(m)
+        if ok:
+            acc = torch.full((f.n,), 7, dtype=torch.uint8, device=dev)
+            m.fuse_points_noalloc(*xyz, f.pose, f.t_ms, out_accept=acc)
+            torch.cuda.synchronize()
+            assert int((acc == 1).sum()) > 0
+        else:
+            with pytest.raises(_emx.EmxError) as ei:
+                m.fuse_points_noalloc(*xyz, f.pose, f.t_ms)
+            assert ei.value.status == _emx.EMX_ENOMEM
+            assert "built-in scratch" in str(ei.value)
+            torch.cuda.synchronize()
+            after = _state(m)
+            for key in before:
+                assert np.array_equal(before[key], after[key]), key
+        m.close()
