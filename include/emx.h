@@ -95,8 +95,8 @@ typedef struct {
   float excl_b;              /* the line's height above the sensor near it, m        */
   float excl_c;              /* horizontal distance where the line starts to rise, m */
   float excl_d;              /* the line's greatest height above the sensor, m       */
-  float outlier_variance;    /* sigma_o^2 (Sec. II-C, the outlier check "increases   */
-                             /* the variance"): added once per fuse call to each     */
+  float outlier_variance;    /* sigma_o^2 (Sec. II-C: outlier detection raises the   */
+                             /* cell's variance): added once per fuse call to each   */
                              /* cell that is valid when the call starts and gets a   */
                              /* gate-rejected point; >= 0, 0 off                     */
 } emx_params;
@@ -239,6 +239,8 @@ emx_status emx_move_map(emx_map* map, double cx, double cy, void* stream);
  * gets a point that reaches the gate and fails it gets, after the above,
  * v = v + float32(outlier_variance), once per call.
  *   d_scratch:    >= emx_scratch_bytes(params, frame->n) bytes, 256-aligned.
+ *                 The fusion reads it only with wall_min_count > 0 (per-cell
+ *                 counts); otherwise it may be NULL.
  *   d_out_cell:   optional int32[n]: cell, or -1 (dropped or outside).
  *   d_out_accept: optional uint8[n]: 1 iff the point passed the gate. */
 emx_status emx_fuse_points(emx_map* map, const emx_frame* frame, void* d_scratch,

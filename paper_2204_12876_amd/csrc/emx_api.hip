@@ -352,12 +352,14 @@ static emx_status fuse_impl(emx_map* m, const emx_frame* f, bool move, double cx
   if (f->n > 0) {
     const int64_t count_cells = m->p.wall_min_count > 0 ? (int64_t)m->p.nx * m->p.ny : 0;
     const size_t need = fuse_scratch_layout(count_cells, nullptr, nullptr);
-    if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
-    if (((uintptr_t)d_scratch & 255u) != 0)
-      return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
-    if (scratch_bytes < need)
-      return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
-    fuse_scratch_layout(count_cells, (char*)d_scratch, &it.fs);
+    if (need > 0) {
+      if (!d_scratch) return fail(EMX_EINVAL, "d_scratch is NULL");
+      if (((uintptr_t)d_scratch & 255u) != 0)
+        return fail(EMX_EINVAL, "d_scratch must be 256-byte aligned");
+      if (scratch_bytes < need)
+        return fail(EMX_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
+      fuse_scratch_layout(count_cells, (char*)d_scratch, &it.fs);
+    }
   }
   it.out_cell = d_out_cell;
   it.out_accept = d_out_accept;

@@ -154,7 +154,7 @@ struct Item {
   FuseScratch fs;
   ClearQueue cq;
   int64_t ray_base;  // this item's first ray in cq
-  int fxw, fxz;      // fixed-point shifts S of the sums of 1/sp2 and rz/sp2 (FxAcc)
+  int fxw, fxz;      // fixed-point shifts S of the sums of 1/sp2 and rz/sp2 (FxWord)
   int tiles_x, T, B;
   int bl, bx, by, nb, nprep;
   int bpw;           // clearing blocks per wave in the setup's block role

@@ -3,7 +3,7 @@
 //
 // Eq. 2 fuses a cell's accepted points through two sums, of 1/sp2 and of
 // zm/sp2.  Both are formed in fixed point: a term x enters as the integer
-// round(x * 2^S), held as hi * 2^32 + lo (FxAcc), with one shift S per sum and
+// round(x * 2^S), held as hi * 2^32 + lo (FxWord), with one shift S per sum and
 // frame chosen on the host so that no sum can overflow (fuse_fixed_shifts).
 // Integer addition is associative, so the sums come out the same whatever the
 // order the additions land in: results are bitwise identical from run to run,
@@ -18,13 +18,14 @@
 //     pass 2, which keeps the terms independent of the sensor's height).
 //   - Sums each run of consecutive lanes in one cell within the wave
 //     (sensors emit points in scan order, so most runs span several points),
-//     and adds the run's sums to the cell's FxAcc with integer atomics; the
-//     cell's tile is flagged.
+//     then each cell's runs in an LDS table for the chunk, and adds the
+//     chunk's sums to the cell's words (FxWord planes) with integer atomics;
+//     the cell's tile is flagged.
 // Pass 2, tile body: one workgroup per 32 x 16-cell tile of the physical
 // layout, one thread per cell.  An unflagged tile returns at once; otherwise
 // the flag is reset, and each cell with a nonzero sum converts its sums back
 // to floating point, applies the information-form update once and resets
-// its FxAcc to zero for the next call.
+// its words to zero for the next call.
 #include <math.h>
 
 #include "emx_kernels.h"

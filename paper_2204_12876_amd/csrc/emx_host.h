@@ -10,8 +10,8 @@ namespace emx {
 
 // Per-map control words after the layers: two sets of clearing
 // queue counters, used by alternate plain calls (each call's setup zeroes the
-// other set for the next call), then the fusion's per-tile entry counts (one
-// word per tile, zero between calls).
+// other set for the next call), then the fusion's per-tile flags (one word
+// per tile, zero between calls).
 constexpr int kCtlWords = 2 * kCtrWords;
 int64_t ctl_words(const emx_params& p);
 
