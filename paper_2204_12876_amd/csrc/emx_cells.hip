@@ -12,6 +12,37 @@ namespace emx {
 
 namespace {
 
+// ------------------------------------------------------- XCD-aware unit order
+// Workgroups are dispatched to the chip's 8 XCDs (each with its own L2) in
+// turn: workgroup b goes to XCD b % 8.  Stencil tiles share their halos with
+// their neighbours, so each XCD is given a contiguous range of the n units
+// (unit order is row-major over tiles), and neighbouring tiles meet in one L2.
+constexpr int kXcds = 8;
+
+// The unit of workgroup b in a launch of exactly n workgroups, a bijection of
+// [0, n).
+__device__ __forceinline__ int64_t xcd_unit(int64_t b, int64_t n) {
+  const int64_t q = n / kXcds, r = n % kXcds;
+  const int64_t x = b % kXcds;
+  return x * q + (x < r ? x : r) + b / kXcds;
+}
+
+// The k-th unit of workgroup b in a persistent launch of g workgroups over n
+// units, or -1 past its share.  With g a multiple of 8, the g/8 workgroups of
+// XCD x walk that XCD's contiguous range in turn; otherwise units go round
+// robin (b, b + g, ...).
+__device__ __forceinline__ int64_t xcd_unit_k(int64_t b, int64_t g, int64_t n, int64_t k) {
+  if (g % kXcds != 0) {
+    const int64_t u = b + k * g;
+    return u < n ? u : -1;
+  }
+  const int64_t q = n / kXcds, r = n % kXcds;
+  const int64_t x = b % kXcds;
+  const int64_t cnt = q + (x < r ? 1 : 0);
+  const int64_t j = b / kXcds + k * (g / kXcds);
+  return j < cnt ? x * q + (x < r ? x : r) + j : -1;
+}
+
 constexpr int kNTf = 256;
 
 // ------------------------------------------------------------------ prior fill
@@ -242,15 +273,16 @@ __device__ __forceinline__ void cells_body(const Item& it, int64_t unit, bool do
 
 // ---------------------------------------------------------------- launches
 __global__ __launch_bounds__(kNTf) void k_move(Item it) { move_body(it, blockIdx.x); }
+// One workgroup per output tile, each XCD taking a contiguous range of tiles.
 __global__ __launch_bounds__(kNTf) void k_normals(Item it) {
-  cells_body(it, blockIdx.x, true, false);
+  cells_body(it, xcd_unit(blockIdx.x, gridDim.x), true, false);
 }
 __global__ __launch_bounds__(kNTf) void k_trav(Item it) {
-  cells_body(it, blockIdx.x, false, true);
+  cells_body(it, xcd_unit(blockIdx.x, gridDim.x), false, true);
 }
 // Both from one staged tile: the heights are read once.
 __global__ __launch_bounds__(kNTf) void k_normals_trav(Item it) {
-  cells_body(it, blockIdx.x, true, true);
+  cells_body(it, xcd_unit(blockIdx.x, gridDim.x), true, true);
 }
 
 // The batch's first launch: also zeroes the clearing queue counters, which
@@ -265,9 +297,12 @@ __global__ __launch_bounds__(kNTf) void k_move_b(const Batch* bt) {
   }
 }
 
+// Each XCD takes a contiguous range of the batch's tiles (xcd_unit_k).
 __global__ __launch_bounds__(kNTf) void k_cells_b(const Batch* bt) {
   const int64_t total = bt->off[kBCells][bt->n];
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+  for (int64_t k = 0;; ++k) {
+    const int64_t w = xcd_unit_k(blockIdx.x, gridDim.x, total, k);
+    if (w < 0) break;
     const int i = batch_item(bt, kBCells, w);
     const Item& it = bt->items[i];
     cells_body(it, w - bt->off[kBCells][i], (it.stages & kStageNormals) != 0,
