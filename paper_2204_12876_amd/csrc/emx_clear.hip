@@ -151,11 +151,10 @@ __device__ __forceinline__ void atomic_min_f32(float* a, float v) {
   else atomicMax(reinterpret_cast<unsigned int*>(a), __float_as_uint(v));
 }
 
-// A cell (physical index pc) can be removed only if it is valid, older than
-// the minimum age and has a normal.
-__device__ __forceinline__ bool clearable(const Item& it, int64_t pc) {
-  return it.L.valid[pc] && (((int64_t)it.t_now - (int64_t)it.L.t[pc]) > (int64_t)it.c.tau) &&
-         !isnan(it.L.nz[pc]);
+// A cell can be removed only if it is valid, older than the minimum age and
+// has a normal (its validity, update time and normal z given).
+__device__ __forceinline__ bool clearable(const Item& it, uint8_t valid, int32_t t_upd, float nz) {
+  return valid && (((int64_t)it.t_now - (int64_t)t_upd) > (int64_t)it.c.tau) && !isnan(nz);
 }
 
 // Removal of a cell: back to the prior, invalid (physical index pc); flagged
@@ -302,13 +301,37 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
       inside[j] = j < it.bpw && b < it.nb && ix < it.c.nx && iy < it.c.ny;
       c[j] = inside[j] ? (int64_t)iy * it.c.nx + ix : 0;
       p[j] = inside[j] ? pcell(it.c, ix, iy) : 0;
+    }
+    // every layer's load of the wave's blocks issued before any is used, not
+    // one after another behind the tests (cell 0 stands in for cells outside
+    // the map)
+    uint8_t vd[kMaxBlocksPerWave];
+    int32_t tu[kMaxBlocksPerWave];
+    float nz[kMaxBlocksPerWave], ubv[kMaxBlocksPerWave];
+#pragma unroll
+    for (int j = 0; j < kMaxBlocksPerWave; ++j) {
+      vd[j] = 0;
+      tu[j] = 0;
+      nz[j] = 0.0f;
+      h[j] = 0.0f;
+      ubv[j] = INFINITY;
+      if (j < it.bpw) {  // uniform
+        vd[j] = it.L.valid[p[j]];
+        tu[j] = it.L.t[p[j]];
+        nz[j] = it.L.nz[p[j]];
+        h[j] = it.L.h[p[j]];
+        if (it.L.ub) ubv[j] = it.L.ub[p[j]];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxBlocksPerWave; ++j) {
       if (inside[j] && it.out_cleared) it.out_cleared[c[j]] = 0;  // the march sets removals
-      ok[j] = inside[j] && clearable(it, p[j]);
-      h[j] = inside[j] ? it.L.h[p[j]] : 0.0f;
+      ok[j] = inside[j] && clearable(it, vd[j], tu[j], nz[j]);
+      if (!inside[j]) h[j] = 0.0f;
       v[j] = ok[j] ? h[j] : -INFINITY;
       // with an upper bound layer, a sample below the bound of a cell without
       // an estimate lowers it: such cells take part in the maximum too
-      if (it.L.ub && inside[j] && !it.L.valid[p[j]]) v[j] = it.L.ub[p[j]];
+      if (it.L.ub && inside[j] && !vd[j]) v[j] = ubv[j];
     }
 #pragma unroll
     for (int j = 0; j < kMaxBlocksPerWave; ++j) {
@@ -320,7 +343,7 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
       // some sample may pass below the block maximum
       if (v[j] > -INFINITY && inside[j]) {
         // a NaN height can never be cleared (hd > 0 fails), so -inf serves
-        const bool bound = it.L.ub && !it.L.valid[p[j]];
+        const bool bound = it.L.ub && !vd[j];
         const float hx = bound ? __builtin_nanf("") : (ok[j] && !isnan(h[j]) ? h[j] : -INFINITY);
         it.L.clr[c[j]] = make_float2(hx, it.L.v[p[j]]);
       }
