@@ -302,32 +302,35 @@ __device__ __forceinline__ void setup_body(const Item& it, int unit, int qsel) {
       c[j] = inside[j] ? (int64_t)iy * it.c.nx + ix : 0;
       p[j] = inside[j] ? pcell(it.c, ix, iy) : 0;
     }
-    // every layer's load of the wave's blocks issued before any is used, not
-    // one after another behind the tests (cell 0 stands in for cells outside
-    // the map)
+    // two rounds of loads for all of the wave's blocks, not one round per
+    // test: first the validity, then what a valid cell's tests need (update
+    // time, normal z, height), or a cell without an estimate's bound.  Cells
+    // that cannot matter load nothing more (cell 0 stands in for cells
+    // outside the map).
     uint8_t vd[kMaxBlocksPerWave];
     int32_t tu[kMaxBlocksPerWave];
     float nz[kMaxBlocksPerWave], ubv[kMaxBlocksPerWave];
 #pragma unroll
+    for (int j = 0; j < kMaxBlocksPerWave; ++j)
+      vd[j] = (j < it.bpw && inside[j]) ? it.L.valid[p[j]] : 0;
+#pragma unroll
     for (int j = 0; j < kMaxBlocksPerWave; ++j) {
-      vd[j] = 0;
       tu[j] = 0;
       nz[j] = 0.0f;
       h[j] = 0.0f;
       ubv[j] = INFINITY;
-      if (j < it.bpw) {  // uniform
-        vd[j] = it.L.valid[p[j]];
+      if (vd[j]) {
         tu[j] = it.L.t[p[j]];
         nz[j] = it.L.nz[p[j]];
         h[j] = it.L.h[p[j]];
-        if (it.L.ub) ubv[j] = it.L.ub[p[j]];
+      } else if (it.L.ub && inside[j]) {
+        ubv[j] = it.L.ub[p[j]];
       }
     }
 #pragma unroll
     for (int j = 0; j < kMaxBlocksPerWave; ++j) {
       if (inside[j] && it.out_cleared) it.out_cleared[c[j]] = 0;  // the march sets removals
       ok[j] = inside[j] && clearable(it, vd[j], tu[j], nz[j]);
-      if (!inside[j]) h[j] = 0.0f;
       v[j] = ok[j] ? h[j] : -INFINITY;
       // with an upper bound layer, a sample below the bound of a cell without
       // an estimate lowers it: such cells take part in the maximum too
