@@ -21,11 +21,12 @@
 //     then each cell's runs in an LDS table for the chunk, and adds the
 //     chunk's sums to the cell's words (FxWord planes) with integer atomics;
 //     the cell's tile is flagged.
-// Pass 2, tile body: one workgroup per 32 x 16-cell tile of the physical
-// layout, one thread per cell.  An unflagged tile returns at once; otherwise
-// the flag is reset, and each cell with a nonzero sum converts its sums back
-// to floating point, applies the information-form update once and resets
-// its words to zero for the next call.
+// Pass 2, tile body: per 32 x 16-cell tile of the physical layout, a
+// workgroup with one thread per cell (plain calls) or one wave with eight
+// cells per lane (batches).  An unflagged tile returns after one load;
+// otherwise the flag is reset, and each cell with a nonzero sum converts its
+// sums back to floating point, applies the information-form update once and
+// resets its words to zero for the next call.
 #include <math.h>
 
 #include "emx_kernels.h"
@@ -257,37 +258,25 @@ __device__ __forceinline__ void chunk_body(const Item& it, int64_t chunk, AggTab
 }
 
 // ------------------------------------------------------------------ pass 2
-constexpr int kNT2 = kTileCells;  // pass-2 threads: one per cell of the tile
+constexpr int kNT2 = kTileCells;               // plain pass 2: one thread per cell of the tile
+constexpr int kNT2b = 256;                     // batched pass 2: one wave per tile
+constexpr int kTilesPerGroup = kNT2b / 64;
+constexpr int kCellsPerLane = kTileCells / 64;  // 8: lane l owns cells l, l + 64, ...
+constexpr int kHalf = kCellsPerLane / 2;
 
-__device__ __forceinline__ void tile_body(const Item& it, int t) {
-  if (it.fs.tcnt[t] == 0u) return;  // uniform: the frame added to no cell of the tile
-  __syncthreads();                  // every thread has read the flag
-  if (threadIdx.x == 0) it.fs.tcnt[t] = 0u;  // zero again for the next call
-  const int l = threadIdx.x;
-  const int tx = t % it.tiles_x;
-  const int ty = t / it.tiles_x;
-  // the owned cell, physical (tiles cover the ring layout as stored)
-  const int px = (tx << kTileLogX) + (l & (kTileW - 1));
-  const int py = (ty << kTileLogY) + (l >> kTileLogX);
-  if (px >= it.c.nx || py >= it.c.ny) return;
-  const int64_t cell = (int64_t)py * it.c.nx + px;
+// Information-form update of physical cell `cell` from its sums (Σw's words
+// whi, wlo given, not both zero); the sums are reset to zero.
+__device__ __forceinline__ void update_cell(const Item& it, int64_t cell, int64_t whi,
+                                            uint64_t wlo, int64_t zhi, uint64_t zlo, float h0,
+                                            float v0) {
   uint64_t* f = it.L.fx + cell;
   const int64_t fs = it.L.fxs;
-  const int64_t whi = (int64_t)f[kFxWhi * fs];
-  const uint64_t wlo = f[kFxWlo * fs];
-  if (whi == 0 && wlo == 0) return;  // no accepted point: every term is positive
-  const int64_t zhi = (int64_t)f[kFxZhi * fs];
-  const uint64_t zlo = f[kFxZlo * fs];
 #pragma unroll
   for (int k = 0; k < kFxWords; ++k) f[k * fs] = 0u;
   const double sw = fx_value(whi, wlo, it.fxw);
   const double srz = fx_value(zhi, zlo, it.fxz);
   const float acc_w = (float)sw;
   const float acc_wz = (float)(srz + (double)it.P.t[2] * sw);
-
-  // ---- information-form update of the owned cell
-  const float h0 = it.L.h[cell];
-  const float v0 = it.L.v[cell];
   const float W = (1.0f / v0) + acc_w;
   const float v1 = 1.0f / W;
   const float h1 = ((h0 / v0) + acc_wz) * v1;
@@ -297,6 +286,89 @@ __device__ __forceinline__ void tile_body(const Item& it, int t) {
   it.L.valid[cell] = 1;
   // updated: no time variance (the owning thread keeps pass 1's outlier flag)
   if (it.c.var_t != 0.0f) it.L.mark[cell] = it.L.mark[cell] | kMarkUpdated;
+}
+
+// Tile t, by a workgroup of kNT2 threads, one cell each: the plain call's
+// form, where a single frame's tiles are few and each cell's loads should be
+// in flight at once.
+__device__ __forceinline__ void tile_body_group(const Item& it, int64_t t) {
+  if (it.fs.tcnt[t] == 0u) return;  // uniform: the frame added to no cell of the tile
+  __syncthreads();                  // every thread has read the flag
+  if (threadIdx.x == 0) it.fs.tcnt[t] = 0u;  // zero again for the next call
+  const int l = threadIdx.x;
+  const int tx = (int)(t % it.tiles_x);
+  const int ty = (int)(t / it.tiles_x);
+  // the owned cell, physical (tiles cover the ring layout as stored)
+  const int px = (tx << kTileLogX) + (l & (kTileW - 1));
+  const int py = (ty << kTileLogY) + (l >> kTileLogX);
+  if (px >= it.c.nx || py >= it.c.ny) return;
+  const int64_t cell = (int64_t)py * it.c.nx + px;
+  const int64_t fs = it.L.fxs;
+  const int64_t whi = (int64_t)it.L.fx[kFxWhi * fs + cell];
+  const uint64_t wlo = it.L.fx[kFxWlo * fs + cell];
+  if (whi == 0 && wlo == 0) return;  // no accepted point: every term is positive
+  update_cell(it, cell, whi, wlo, (int64_t)it.L.fx[kFxZhi * fs + cell],
+              it.L.fx[kFxZlo * fs + cell], it.L.h[cell], it.L.v[cell]);
+}
+
+// Tile t, by one wave: lane l takes cells l + 64 i of the tile (two rows of 32
+// per step), in two halves of kHalf cells, each half's loads issued together.
+// The batched form: a batch holds tens of thousands of tiles, many untouched,
+// so a workgroup's waves take one tile each and an untouched tile costs one
+// wave one load.  The same update_cell as the plain form: the same bits.
+__device__ __forceinline__ void tile_body_wave(const Item& it, int64_t t) {
+  const int lane = threadIdx.x & 63;
+  if (it.fs.tcnt[t] == 0u) return;  // wave-uniform: the frame added to no cell of the tile
+  // the flag's load has completed for the whole wave (the branch used it)
+  if (lane == 0) it.fs.tcnt[t] = 0u;  // zero again for the next call
+  const int tx = (int)(t % it.tiles_x);
+  const int ty = (int)(t / it.tiles_x);
+  const int64_t fs = it.L.fxs;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    int64_t cell[kHalf];
+    bool in[kHalf];
+    int64_t whi[kHalf];
+    uint64_t wlo[kHalf];
+#pragma unroll
+    for (int i = 0; i < kHalf; ++i) {
+      const int c = lane + 64 * (half * kHalf + i);
+      // the cell, physical (tiles cover the ring layout as stored)
+      const int px = (tx << kTileLogX) + (c & (kTileW - 1));
+      const int py = (ty << kTileLogY) + (c >> kTileLogX);
+      in[i] = px < it.c.nx && py < it.c.ny;
+      cell[i] = in[i] ? (int64_t)py * it.c.nx + px : 0;
+      whi[i] = 0;
+      wlo[i] = 0;
+      if (in[i]) {
+        whi[i] = (int64_t)it.L.fx[kFxWhi * fs + cell[i]];
+        wlo[i] = it.L.fx[kFxWlo * fs + cell[i]];
+      }
+    }
+    // cells with an accepted point (every term is positive): the rest of
+    // their sums and their prior, all loads issued before any is used
+    bool hit[kHalf];
+    int64_t zhi[kHalf];
+    uint64_t zlo[kHalf];
+    float h0[kHalf], v0[kHalf];
+#pragma unroll
+    for (int i = 0; i < kHalf; ++i) {
+      hit[i] = in[i] && (whi[i] != 0 || wlo[i] != 0);
+      zhi[i] = 0;
+      zlo[i] = 0;
+      h0[i] = 0.0f;
+      v0[i] = 1.0f;
+      if (hit[i]) {
+        zhi[i] = (int64_t)it.L.fx[kFxZhi * fs + cell[i]];
+        zlo[i] = it.L.fx[kFxZlo * fs + cell[i]];
+        h0[i] = it.L.h[cell[i]];
+        v0[i] = it.L.v[cell[i]];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kHalf; ++i)
+      if (hit[i]) update_cell(it, cell[i], whi[i], wlo[i], zhi[i], zlo[i], h0[i], v0[i]);
+  }
 }
 
 // ------------------------------------------------------- wall rule: counts
@@ -381,7 +453,7 @@ __global__ __launch_bounds__(kNT1) void k_fuse_chunk(Item it) {
   chunk_body(it, blockIdx.x, tab);
 }
 
-__global__ __launch_bounds__(kNT2) void k_fuse_tile(Item it) { tile_body(it, blockIdx.x); }
+__global__ __launch_bounds__(kNT2) void k_fuse_tile(Item it) { tile_body_group(it, blockIdx.x); }
 
 __global__ __launch_bounds__(kNT1) void k_fuse_chunk_b(const Batch* bt) {
   __shared__ AggTable tab;
@@ -421,12 +493,15 @@ __global__ __launch_bounds__(kNTv) void k_time_variance_b(const Batch* bt) {
   }
 }
 
-__global__ __launch_bounds__(kNT2) void k_fuse_tile_b(const Batch* bt) {
+// Each wave takes its own tiles: units w = (workgroup * kTilesPerGroup +
+// wave) + k * (grid * kTilesPerGroup).
+__global__ __launch_bounds__(kNT2b) void k_fuse_tile_b(const Batch* bt) {
   const int64_t total = bt->off[kBTile][bt->n];
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+  const int64_t step = (int64_t)gridDim.x * kTilesPerGroup;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for (int64_t w = (int64_t)blockIdx.x * kTilesPerGroup + wave; w < total; w += step) {
     const int i = batch_item(bt, kBTile, w);
-    tile_body(bt->items[i], (int)(w - bt->off[kBTile][i]));
-    __syncthreads();
+    tile_body_wave(bt->items[i], w - bt->off[kBTile][i]);
   }
 }
 
@@ -540,7 +615,9 @@ hipError_t launch_fuse_batch(const Batch* d_batch, const int grid[5], hipStream_
   if (err != hipSuccess) return err;
   {
     TimedLaunch tl("k_fuse_tile_b", stream);
-    hipLaunchKernelGGL(k_fuse_tile_b, dim3(grid_tile), dim3(kNT2), 0, stream, d_batch);
+    // grid_tile counts tiles in flight; a workgroup holds kTilesPerGroup
+    hipLaunchKernelGGL(k_fuse_tile_b, dim3((unsigned)((grid_tile + kTilesPerGroup - 1) / kTilesPerGroup)),
+                       dim3(kNT2b), 0, stream, d_batch);
   }
   if (grid[4] > 0) {
     TimedLaunch tl("k_time_variance_b", stream);
