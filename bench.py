@@ -146,15 +146,42 @@ KERNEL_SOURCE = {"fuse": "emx_fuse.hip", "clear": "emx_clear.hip", "cells": "emx
                  "move": "emx_cells.hip"}
 
 
+def code_only(text: str) -> str:
+    """C/C++ source without its comments, trailing blanks and empty lines:
+    what the compiler sees, so that a comment edit keeps a kernel's hash."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    lines = (ln.rstrip() for ln in "".join(out).split("\n"))
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_source_hash(kernel: str) -> str:
-    """Hash of the source file holding ``kernel`` and the headers it includes."""
+    """Hash of the code (comments left out) of the source file holding
+    ``kernel`` and the headers it includes."""
     role = kernel[2:].split("_")[0]
     src = KERNEL_SOURCE.get(role, "emx_cells.hip")
     d = os.path.join(ROOT, "paper_2204_12876_amd", "csrc")
     h = hashlib.sha256()
     for f in (src, "emx_device.h", "emx_kernels.h"):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        with open(os.path.join(d, f), encoding="utf-8") as fh:
+            h.update(f.encode() + code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -21,7 +21,7 @@ namespace emx {
 // the drift partials).
 constexpr int kChunk = 1024;
 // Map tiles of 32 x 16 cells: pass 2 of the fusion visits only the tiles the
-// frame touched, one thread per cell (a 400 x 400 map has 338 tiles).
+// frame touched (a 400 x 400 map has 13 x 25 = 325 tiles).
 constexpr int kTileLogX = 5;
 constexpr int kTileLogY = 4;
 constexpr int kTileW = 1 << kTileLogX;

@@ -123,3 +123,34 @@ def test_roofline_takes_the_kernel_with_the_most_time():
     fb = bench.frame_bytes(100, 50, 7, 5, 10)
     assert fb["fuse_chunk"] == 1200 + 56 and fb["fuse_tile"] == 105
     assert fb["move"] == 29 * 10 and bench.frame_bytes(100, 50, 7, 5, 0)["move"] == 0
+
+
+def test_source_hash_ignores_comments_but_not_code():
+    src = ('#include "a.h"  // header\n'
+           '/* a block\n   comment */\n'
+           'const char* s = "// not a comment";\n'
+           "int f(int x) { return x + '/'; }  // tail\n")
+    code = bench.code_only(src)
+    assert code == ('#include "a.h"\n'
+                    'const char* s = "// not a comment";\n'
+                    "int f(int x) { return x + '/'; }")
+    # a comment edit keeps the code; a code edit does not
+    assert bench.code_only(src.replace("// tail", "// other words")) == code
+    assert bench.code_only(src.replace("x + ", "x - ")) != code
+
+
+def test_traffic_is_read_only_for_the_kernels_it_was_taken_on(tmp_path, monkeypatch):
+    """A summary whose hash is the kernel's current code gives bytes per
+    launch (counters scaled by the calibration factors); another hash, or no
+    summary, gives None."""
+    k = "k_fuse_chunk_b"
+    f = tmp_path / "traffic.txt"
+    f.write_text("# comment: ignored\nfetch_factor: 2.0\nwrite_factor: 1.0\n"
+                 f"{k}.source_sha256_16: {bench.kernel_source_hash(k)}\n"
+                 f"{k}.fetch_kib: 10\n{k}.write_kib: 3\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic(k) == 1024.0 * (10 * 2.0 + 3 * 1.0)
+    f.write_text(f.read_text().replace(bench.kernel_source_hash(k), "0" * 16))
+    assert bench.measured_traffic(k) is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "absent.txt"))
+    assert bench.measured_traffic(k) is None
