@@ -12,15 +12,17 @@
 //     variances if a map uses time or outlier variance, clearing setup and
 //     march, then normals + traversability.
 // Every launch finds its work in the table, so a graph depends only on the
-// scratch address, the sort key width and the grid sizes.  Each stage's grid
+// scratch address and the grid sizes.  Each stage's grid
 // is the tuned size capped at the stage's work rounded up to a power of two,
 // so a small batch does not launch thousands of idle workgroups, and few
 // distinct graphs arise.  Captured graphs are kept in a small LRU cache.
 // Two pinned tables alternate: the host fills one while the other may still
 // be read by the previous batch's copy.
 //
-// The work of each item runs through the same kernel bodies as the plain
-// calls, so every map's results equal those of the plain calls bit for bit.
+// The work of each item runs through the same per-point and per-cell
+// arithmetic as the plain calls (fusion pass 2 differs only in how cells are
+// spread over threads), so every map's results equal those of the plain calls
+// bit for bit.
 #include <stdlib.h>
 #include <string.h>
 

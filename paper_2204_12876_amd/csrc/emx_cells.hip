@@ -1,10 +1,10 @@
 // Per-cell passes: prior fill, robot-centric move, 3x3 normals, conv traversability.
 //
-// The stencils (normals, traversability) stage an 18x18 halo tile of heights
-// and validity in LDS.  Each 256-thread workgroup then produces a 16x16 output
-// tile, one cell per thread: small tiles give a 400x400 map 625 workgroups,
-// enough to occupy every compute unit, at the cost of reading each height about
-// 1.27 times (mostly from cache).
+// The stencils (normals, traversability) stage a 66 x 18 halo tile of heights
+// and validity in LDS.  Each 256-thread workgroup then produces a 64 x 16
+// output tile, four cells per thread (a 400 x 400 map: 7 x 25 = 175 tiles).
+// The halo makes each height read about 1.16 times, the repeats mostly from
+// the L2 that the neighbouring tile shares (see the unit order below).
 // The batched launch computes normals and traversability from one staged tile.
 #include "emx_kernels.h"
 

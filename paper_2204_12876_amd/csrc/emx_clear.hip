@@ -3,7 +3,7 @@
 // The samples of a ray are q_k = o + (k/K) d for k = 1..K-1, in float32.
 // Their number varies from 0 to a few hundred per ray, so one thread per ray
 // leaves the long rays on the critical path.  The work is therefore split in
-// three launches:
+// two launches:
 //
 // setup, two roles in one grid:
 //   - Block role: per block of 2^b x 2^b cells, the largest height of a cell
@@ -12,6 +12,9 @@
 //     same pass writes each cell's 8-byte clearing record {h, or -inf if no
 //     ray may remove it, v}, so that the march's height test takes one load.
 //     Other blocks prune every sample, so their records are never read.
+//     The cells' loads come in two rounds, each issued at once: validity,
+//     then the update time, normal z and height of valid cells (or the upper
+//     bound of invalid ones).
 //   - Ray role, one thread per point:
 //       - the ray's exact in-map range of k.  A sample's cell is in the map over
 //         a contiguous range of k, because q_k.x and q_k.y are monotone in k:
@@ -29,6 +32,8 @@
 //   - Block 0 zeroes the counter set of the next plain call, and the block
 //     role zeroes the caller's removed-cell mask.
 // march: a persistent grid drains the queue, one segment per thread.
+//   - A segment's consecutive samples mostly stay in one block: the block
+//     maximum is loaded again only when the block changes.
 //   - A sample at height q.z >= the block maximum passes above every cell that
 //     could be removed, since removal needs h > q.z.  It is skipped without
 //     reading the cell: exact pruning.
