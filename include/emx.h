@@ -401,12 +401,14 @@ emx_status emx_import_state(emx_map* map, const void* d_src, void* stream);
  *   - Stages run in pipeline order for every item: move, fuse, clear, normals,
  *     traversability.  `stages` selects them per item.
  *   - Each item's results are bitwise identical to those of the plain calls
- *     run in the same order on that map: the same kernel bodies do the
- *     arithmetic, and every float32 sum has a fixed order.
+ *     run in the same order on that map: the per-point and per-cell
+ *     arithmetic is the same, the fusion's sums are integer sums (any order
+ *     gives the same bits), and every float32 sum has a fixed order.
  *   - The tuning selects only launch geometry (persistent grid sizes) and the
  *     clearing segment length.  It never changes results.
- *   - Maps with time_variance, wall_min_count or upper_bound set are refused
- *     (EMX_EINVAL): run those through the plain calls. */
+ *   - Every map option of the plain calls is served: time and outlier
+ *     variance, the wall rule (its counts take scratch, see
+ *     emx_batch_scratch_bytes), the upper bound layer and the exclusion area. */
 #define EMX_STAGE_MOVE 1u
 #define EMX_STAGE_FUSE 2u
 #define EMX_STAGE_CLEAR 4u
