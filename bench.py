@@ -136,6 +136,33 @@ def frame_bytes(n: float, C: float, touched: float, updated: float, entering: fl
             "move": 29 * entering}
 
 
+def ray_samples(x, y, z, pose, min_range: float, ray_step: float) -> int:
+    """Samples of one frame's clearing rays, S = sum of K - 1 over the valid
+    points, with K = ceil(max(|dx|, |dy|) / ray_step) for the ray d from the
+    sensor to the point (Sec. II-E): the march's unit of work, whether a
+    sample lies in the map or not.  Counted in float64 from the rotated point
+    (the ray does not depend on the translation), so a ray at a rounding
+    boundary may count one sample more or less than the kernels' float32
+    evaluation: a throughput unit, not a parity check."""
+    p = np.stack([np.asarray(v, np.float64) for v in (x, y, z)])
+    d2 = (p * p).sum(axis=0)
+    ok = np.isfinite(d2) & (d2 >= float(min_range) ** 2)
+    r = np.asarray(pose, np.float64)[:3, :3] @ p[:, ok]
+    m = np.maximum(np.abs(r[0]), np.abs(r[1])) * (1.0 / float(ray_step))
+    k = np.ceil(m[m < 2.0 ** 24])
+    return int(np.maximum(k - 1.0, 0.0).sum())
+
+
+def add_sample_rate(kernels: dict, samples: dict) -> None:
+    """Ray samples per launch and per second of each clearing march in
+    ``kernels``, from the total samples of its timed launches."""
+    for name, tot in samples.items():
+        e = kernels.get(name)
+        if e and e["launches"] > 0 and e["total_ms"] > 0:
+            e["samples_per_launch"] = tot / e["launches"]
+            e["G_samples_per_s"] = tot / (e["total_ms"] * 1e-3) / 1e9
+
+
 PLAIN_KERNEL = {"fuse_chunk": "k_fuse_chunk", "fuse_tile": "k_fuse_tile",
                 "clear_setup": "k_clear_setup", "clear_march": "k_clear_march",
                 "cells": "k_normals_trav", "move": "k_move"}
@@ -272,8 +299,11 @@ def serving_context(args, dev):
         a = acc.cpu().numpy().astype(bool)
         m.close()
         C = it["params"]["nx"] * it["params"]["ny"]
+        pr = it["params"]
+        S = ray_samples(xyz[0].numpy(), xyz[1].numpy(), xyz[2].numpy(), f.pose,
+                        pr.get("min_range", 0.05), pr.get("ray_step", pr["resolution"]))
         stats.append(dict(n=f.n, C=C, ny=it["params"]["ny"], touched=np.unique(c[c >= 0]).size,
-                          updated=np.unique(c[a]).size))
+                          updated=np.unique(c[a]).size, samples=S))
     largest = max((it["params"] for it in items), key=lambda p: p["nx"] * p["ny"])
     return dict(items=items, host=host, device=device, stats=stats, weights=w,
                 largest=largest, data=d)
@@ -400,14 +430,17 @@ def _serving_kernels(ctx, srv, mk, robots, K, W):
     _emx.timing_begin()
     treqs = run_closed_loop(srv, lambda k, j: mk(k, W + K + j), robots, K)
     kt = _emx.timing_end()
-    alg = {}
+    alg, samples = {}, {}
     for r in treqs:
         s = ctx["stats"][r.robot]
         names = BATCH_KERNEL if r.batch_items > 1 else PLAIN_KERNEL
         # the centre alternates by one cell in x: one column enters
         for role, b in frame_bytes(s["n"], s["C"], s["touched"], s["updated"], s["ny"]).items():
             alg[names[role]] = alg.get(names[role], 0.0) + b
+        march = names["clear_march"]
+        samples[march] = samples.get(march, 0) + s["samples"]
     kernels = kernel_table(kt, alg)
+    add_sample_rate(kernels, samples)
     return kernels, roofline(kernels)
 
 
@@ -580,10 +613,14 @@ def single_robot(args, dev):
     acc = torch.empty(args.points, dtype=torch.uint8, device=dev)
     r = params["resolution"]
     cell_of = [(math.floor(cx / r), math.floor(cy / r)) for cx, cy in centers]
-    alg = {}
+    alg, samples = {}, 0
     for j in range(K):
         run(m, W + j, cell=cell, acc=acc)
         n = frames[W + j][0].numel()
+        fx, fy, fz, fpose = frames[W + j][:4]
+        samples += ray_samples(fx.cpu().numpy(), fy.cpu().numpy(), fz.cpu().numpy(), fpose,
+                               params.get("min_range", 0.05),
+                               params.get("ray_step", params["resolution"]))
         c = cell[:n].cpu().numpy()
         a = acc[:n].cpu().numpy().astype(bool)
         sx = min(abs(cell_of[W + j][0] - cell_of[W + j - 1][0]), params["nx"])
@@ -601,6 +638,7 @@ def single_robot(args, dev):
     kt = _emx.timing_end()
     m.close()
     kernels = kernel_table(kt, alg)
+    add_sample_rate(kernels, {PLAIN_KERNEL["clear_march"]: samples})
     return {
         "workload": "one robot: 400x400 map at 0.04 m, 300k-point frames (dome LiDAR + 4 depth "
                     "frustums) along a trajectory, full path per frame through the plain calls",

@@ -154,3 +154,32 @@ def test_traffic_is_read_only_for_the_kernels_it_was_taken_on(tmp_path, monkeypa
     assert bench.measured_traffic(k) is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "absent.txt"))
     assert bench.measured_traffic(k) is None
+
+
+def test_ray_samples_hand_cases():
+    eye = np.eye(4)[:3]
+    step = 0.125                                  # exact in binary: K is exact
+    # (1, 0.25, 0): the ray's major axis spans 1 m = 8 steps, samples k = 1..7
+    assert bench.ray_samples([1.0], [0.25], [0.0], eye, 0.05, step) == 7
+    # a 90-degree yaw swaps the axes, the count stays
+    yaw = np.array([[0.0, -1.0, 0.0, 5.0], [1.0, 0.0, 0.0, -3.0], [0.0, 0.0, 1.0, 0.2]])
+    assert bench.ray_samples([1.0], [0.25], [0.0], yaw, 0.05, step) == 7
+    # the vertical part never counts; a ray shorter than one step has none
+    assert bench.ray_samples([0.5], [0.0], [3.0], eye, 0.05, step) == 3
+    assert bench.ray_samples([0.1], [0.0], [0.0], eye, 0.05, step) == 0
+    # points inside the minimum range and non-finite points cast no ray
+    assert bench.ray_samples([0.01, np.nan], [0.0, 0.0], [0.0, 0.0], eye, 0.05, step) == 0
+    # rays of 2^24 steps or more are skipped
+    assert bench.ray_samples([2.0 ** 21], [0.0], [0.0], eye, 0.05, step) == 0
+    # a frame is the sum of its rays
+    xs, ys, zs = [1.0, 0.5, 0.1], [0.25, 0.0, 0.0], [0.0, 3.0, 0.0]
+    assert bench.ray_samples(xs, ys, zs, eye, 0.05, step) == 7 + 3 + 0
+
+
+def test_sample_rate_per_march_launch():
+    k = bench.kernel_table({"k_clear_march_b": [4, 2.0], "k_cells_b": [4, 1.0]}, {})
+    bench.add_sample_rate(k, {"k_clear_march_b": 8e9, "k_clear_march": 5})
+    assert k["k_clear_march_b"]["samples_per_launch"] == 2e9
+    assert math.isclose(k["k_clear_march_b"]["G_samples_per_s"], 8e9 / 2e-3 / 1e9)
+    assert "samples_per_launch" not in k["k_cells_b"]
+    assert "k_clear_march" not in k                # a kernel that did not run stays absent
