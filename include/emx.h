@@ -20,8 +20,9 @@
  *   - Pointers named d_* are device (HBM) pointers.  All other pointers are host
  *     pointers, read synchronously during the call.
  *   - The caller owns every device buffer: points, map state, scratch and outputs.
- *     The library never allocates device memory.  Host-side map handles are the
- *     only thing it allocates.
+ *     The library never allocates device memory.  It allocates host-side
+ *     objects only: map handles, and batch executors with their pinned tables
+ *     and capture stream.
  *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
  *     Device work is enqueued on it and the call returns without synchronising.
  *     Results are visible after the stream passes the call.  Buffers handed to a
@@ -36,8 +37,9 @@
  *     compensation sums its errors in float64).  Decisions use a fixed
  *     operation order, round-to-nearest and no fused multiply-add.  Those
  *     decisions are the range check, cell index, gate, ray samples and clearing
- *     predicate; the order is stated below.  Every sum has a fixed order, so
- *     results are the same from run to run.
+ *     predicate; the order is stated below.  The fusion's sums are exact
+ *     integer sums and every float sum has a fixed order, so results are the
+ *     same from run to run.
  *
  * Map geometry (the paper is silent on it; these are this library's conventions):
  *   - Cells are half-open squares of side r.  Global cell (gx, gy) covers
